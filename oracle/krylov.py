@@ -1,0 +1,155 @@
+"""CG, deflated CG and flexible (deflated) CG (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+* ``cg``   plain conjugate gradients on A* x = f with the stopping rule
+           ||r_i|| <= tol ||f|| (Section 4.1).
+* ``dcg``  Algorithm 2 (FDCG): deflated operator M_D(z) = A*(z - pi(A* z)),
+           right-hand side f_D, an outer CG or FCG(m) iteration on the
+           deflated system (eq. (defl_sys)) and the reconstruction
+           x = (x_hat - pi(A* x_hat)) + pi(f) (eq. (x_defl)).
+           pi(z) = V z_hat(V^T z), where z_hat approximates (V^T A* V)^{-1}
+           by an exact factorisation or by the Multigrid iteration.
+
+Readings:
+* f_D: Algorithm 2 prints f_D = f - pi^T(f), which drops the A* of
+  eq. (defl_sys); this oracle uses eq. (defl_sys): f_D = (I - pi_A)^T f =
+  f - A* pi(f) (pi is symmetric).
+* Outer variants: 'cg' is standard CG on the deflated system (the DCG of
+  Tables 2-3, beta = rho_new / rho); 'fcg' is Algorithm 1 with the
+  truncation m_i = max{1, mod(i, m_max + 1)}, m_0 = 0 (Remark 5), and
+  m_max = None meaning FCG(inf), m_i = i.
+* Inner tolerance (a relative tolerance, as the inner stopping rule is
+  written): fixed rule tau^c = c_F * tol (eq. (fixed_tol)); adaptive rule
+  tau^c = c_A * tol * ||f|| / ||r_i|| (eq. (tol)), used inside the outer loop
+  while the prologue and epilogue solves use c_A * tol.
+* The outer stopping test is on the recurrence residual of the deflated
+  system relative to ||f|| (Section 4.1); the true residual of the
+  reconstructed x is reported, never substituted.
+
+Parity status: pinned.  CG against the iterates of a library CG; deflated CG
+with an exact inner solve against a dense Cholesky solution; the Kahl
+identity and the consistency of the deflated system; recurrence residual =
+true residual with exact inner solves; FCG(inf) = DCG counts with exact inner
+solves; the Delta-t trends of Tables 1-2 (tests/test_oracle_krylov.py).
+"""
+import numpy as np
+import scipy.linalg as sla
+
+from .multigrid import multigrid
+
+
+def cg(A, f, tol=1e-8, max_iter=100000, x0=None):
+    """Plain CG.  Returns (x, iterations, residual-norm history)."""
+    x = np.zeros_like(f) if x0 is None else x0.copy()
+    r = f - A @ x
+    fnorm = np.linalg.norm(f)
+    p = r.copy()
+    rho = r @ r
+    hist = [np.sqrt(rho)]
+    it = 0
+    while it < max_iter and np.sqrt(rho) > tol * fnorm:
+        q = A @ p
+        alpha = rho / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        rho_new = r @ r
+        p = r + (rho_new / rho) * p
+        rho = rho_new
+        it += 1
+        hist.append(np.sqrt(rho))
+    return x, it, hist
+
+
+def exact_inner(E):
+    """z_hat(v) = E^{-1} v by a dense Cholesky factorisation of E = V^T A* V."""
+    fac = sla.cho_factor(E.toarray() if hasattr(E, 'toarray') else E, lower=True)
+
+    def solve(v, tol_c):
+        return sla.cho_solve(fac, v), 0
+    return solve
+
+
+def mg_inner(H, m1=2, m2=2, n_max=100):
+    """z_hat(v) = Multigrid({Z_k}, v, 0, m1, m2, tol_c, n_max) (Algorithm 2)."""
+    def solve(v, tol_c):
+        return multigrid(H, v, None, m1, m2, tol_c, n_max)
+    return solve
+
+
+class DCGResult:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def dcg(Astar, V, f, inner, tol=1e-8, max_iter=100000, x0=None, outer='cg',
+        m_max=None, c_F=0.01, c_A=None):
+    """Deflated (flexible) CG, Algorithm 2.  Returns a DCGResult with x,
+    outer iterations, total inner cycles (Tot), the per-solve inner cycle
+    counts, and recurrence / true relative residuals."""
+    fnorm = np.linalg.norm(f)
+    cycles = []
+
+    def tol_c(rnorm=None):
+        if c_A is None:
+            return c_F * tol
+        if rnorm is None:
+            return c_A * tol
+        return c_A * tol * fnorm / rnorm
+
+    def pi(z, tc):
+        y, c = inner(V.T @ z, tc)
+        cycles.append(c)
+        return V @ y
+
+    def M_D(z, tc):
+        return Astar @ (z - pi(Astar @ z, tc))
+
+    pf = pi(f, tol_c())                       # pi(f), reused in the epilogue
+    f_D = f - Astar @ pf
+    x = np.zeros_like(f) if x0 is None else x0.copy()
+    r = f_D.copy() if x0 is None else f_D - M_D(x, tol_c())
+    it = 0
+    if outer == 'cg':
+        p = r.copy()
+        rho = r @ r
+        while it < max_iter and np.sqrt(rho) > tol * fnorm:
+            q = M_D(p, tol_c(np.sqrt(rho)))
+            alpha = rho / (p @ q)
+            x += alpha * p
+            r -= alpha * q
+            rho_new = r @ r
+            p = r + (rho_new / rho) * p
+            rho = rho_new
+            it += 1
+    elif outer == 'fcg':
+        ds, qs, dqs = [], [], []
+        while it < max_iter and np.linalg.norm(r) > tol * fnorm:
+            if m_max is None:
+                m_i = it
+            else:
+                m_i = 0 if it == 0 else max(1, it % (m_max + 1))
+            d = r.copy()
+            for k in range(it - m_i, it):
+                d -= (r @ qs[k]) / dqs[k] * ds[k]
+            q = M_D(d, tol_c(np.linalg.norm(r)))
+            dq = d @ q
+            alpha = (d @ r) / dq
+            x += alpha * d
+            r -= alpha * q
+            ds.append(d)
+            qs.append(q)
+            dqs.append(dq)
+            if m_max is not None and len(ds) > m_max + 1:
+                ds[-m_max - 2] = qs[-m_max - 2] = None      # no longer referenced
+            it += 1
+    else:
+        raise ValueError(outer)
+    rec = np.linalg.norm(r) / fnorm
+    x_out = (x - pi(Astar @ x, tol_c())) + pf
+    true = np.linalg.norm(f - Astar @ x_out) / fnorm
+    outer_cycles = cycles[1:-1] if x0 is None else cycles[2:-1]
+    return DCGResult(x=x_out, x_hat=x, iterations=it, cycles=cycles,
+                     total_cycles=int(sum(cycles)),
+                     outer_cycles=outer_cycles,
+                     rel_res_recurrence=rec, rel_res_true=true)
