@@ -1,0 +1,203 @@
+/*
+ * dcg.h -- C ABI of the MI355X deflated-CG solver for the implicit time step
+ * of the pseudo-stress Stokes problem.
+ *
+ * The operator (paper, Section 3, eq. (pb_study)) is A* = M + alpha A with
+ *   M  the dev-dev mass form (mu^{-1} dev sigma, dev tau)  (Section 2.3),
+ *   A  the div-div SIPG form sum_{k,i,j} a^h_ij(sigma_ki, tau_kj)
+ *      (eq. (component_form), Section 3.3.2),
+ *   alpha = dt (implicit Euler, Section 2.3), mu = nu.
+ * discretised with discontinuous Q1 per stress component on the uniform grid
+ * of n x n squares of the unit square, penalty gamma = penalty * n, SIPG face
+ * terms on interior faces and on the traction boundary {x = 0} u {y = 0}.
+ *
+ * The solve is deflated CG (Section 4.1, Algorithm 2) with the deflation
+ * basis V of eq. (Vmatrix) (called Z below), whose inner system
+ * Z^T A* Z = (dt / 2) L is a scaled SIPG Laplacian (Corollary 1).  The inner
+ * system is solved by the Multigrid iteration (Algorithm 3) of W-cycles
+ * (Algorithm 4) with a Restricted Additive Schwarz smoother (Section 4.2) to
+ * the fixed relative tolerance c_F * tol (eq. (fixed_tol)).
+ *
+ * Vector layout (every FP64 tensor vector passed through this ABI):
+ *   length 16 n^2, element-major, idx = 16 e + 4 c + j with
+ *   e = ey * n + ex (square (ex, ey) = [ex/n, (ex+1)/n] x [ey/n, (ey+1)/n]),
+ *   c in {0: sigma_11, 1: sigma_12, 2: sigma_21, 3: sigma_22} (Section 3.1),
+ *   j = ix + 2 iy the corner (ex + ix, ey + iy) / n of the square.
+ * Scalar (Laplace / multigrid) vectors: length 4 n_k^2, idx = 4 e + j.
+ *
+ * Pointers: every vector argument is a DEVICE pointer on the current HIP
+ * device unless stated otherwise; host buffers are marked "host".  The caller
+ * owns all vectors; the library owns every matrix, hierarchy, workspace and
+ * scratch buffer and frees them in dcg_destroy / dcg_server_destroy.  The
+ * library never frees caller memory.  A stream argument is a hipStream_t
+ * (NULL = the legacy default stream); the library enqueues its work there.
+ *
+ * Errors: negative status = error (nothing written to the output vector or
+ * its contents are unspecified); dcg_last_error(h) / dcg_last_error(NULL)
+ * give the message of the last failing call on that handle / thread.
+ * Positive status DCG_NOT_CONVERGED: the output holds the reconstructed last
+ * iterate and the stats are valid.
+ */
+#ifndef DCG_H
+#define DCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DCG_OK = 0,
+  DCG_NOT_CONVERGED = 1,  /* max_outer reached; x holds the last iterate      */
+  DCG_PENDING = 2,        /* dcg_poll: request not finished yet               */
+  DCG_EINVAL = -1,        /* bad argument, unsupported size, NaN/Inf input    */
+  DCG_ENOMEM = -2,        /* device or host allocation failed / over budget   */
+  DCG_EDEVICE = -3,       /* a HIP call or kernel launch failed               */
+  DCG_EAGAIN = -4,        /* server queue full                                */
+  DCG_ENOTFOUND = -5,     /* unknown ticket                                   */
+  DCG_EBREAKDOWN = -6     /* (p, q) <= 0 or non-finite in the outer iteration */
+} dcg_status;
+
+typedef enum { DCG_FP64 = 0, DCG_MIXED = 1 } dcg_precision;
+/* DCG_MIXED: multigrid levels (smoother, transfers, level SpMVs) in FP32 with
+ * FP32 accumulation; outer CG, deflation, the inner refinement residual and
+ * the coarsest Cholesky solve in FP64. */
+
+typedef enum {
+  DCG_OUTER_CG = 0,   /* Fletcher-Reeves beta = rho_new / rho (Tables 2-3)    */
+  DCG_OUTER_FCG1 = 1  /* flexible CG with one stored direction, Algorithm 1
+                         truncated to m_i = 1 (Remark 5, m_max = 1)           */
+} dcg_outer;
+
+typedef struct {
+  int32_t n;        /* squares per side; 16 * 2^k for k >= 0, at most 2048   */
+  double penalty;   /* alpha* of the SIPG penalty gamma = alpha* / h [10]     */
+  int32_t pre;      /* m1 pre-smoothing RAS sweeps  [2]                       */
+  int32_t post;     /* m2 post-smoothing RAS sweeps [2]                       */
+} dcg_mesh;
+
+typedef struct {
+  dcg_precision prec;  /* [DCG_MIXED]                                         */
+  dcg_outer outer;     /* [DCG_OUTER_CG]                                      */
+  double c_F;          /* inner tolerance factor, tau^c = c_F * tol [0.01]    */
+  int32_t max_outer;   /* [50000]                                             */
+  int32_t max_inner;   /* W-cycles per inner solve, n_max of Alg. 3 [100]     */
+  int32_t x0_given;    /* 0: x0 = 0; 1: x holds the initial guess on entry    */
+  int32_t use_graph;   /* 1: replay each W-cycle as a captured HIP graph [1]  */
+  int64_t hbm_budget_bytes; /* server admission budget, 0 = device total      */
+} dcg_options;
+
+typedef struct {
+  int32_t status;          /* dcg_status of the solve                         */
+  int32_t outer_iters;     /* "Out" of Table 3                                */
+  int32_t total_wcycles;   /* "Tot": every W-cycle of the solve               */
+  int32_t inner_solves;    /* number of inner solves (prologue + epilogue too) */
+  double inner_per_outer;  /* "Inn": W-cycles per outer iteration (mean)      */
+  double rel_res_recurrence; /* ||r_i|| / ||b|| at exit                       */
+  double rel_res_true;     /* ||b - A* x|| / ||b|| after reconstruction       */
+  double t_setup_ms;       /* handle setup time (mesh context build/upload)   */
+  double t_solve_ms;       /* wall time of dcg_solve                          */
+} dcg_stats;
+
+typedef struct dcg_ctx* dcg_handle;
+typedef struct dcg_srv* dcg_server;
+
+/* Fills *mesh and *opt with the defaults shown in brackets above. */
+void dcg_defaults(dcg_mesh* mesh, dcg_options* opt);
+
+/* Builds (or reuses from the process-wide cache) the dt-independent mesh
+ * context -- A_div, the element mass blocks, A_div Z, the Galerkin multigrid
+ * hierarchy of L (Algorithm 2: Z_{k-1} = I Z_k I), the RAS tile inverses and
+ * the coarsest inverse -- on the current device, and a solver handle for the
+ * scalars dt > 0, nu > 0.  opt may be NULL (defaults).  Returns DCG_EINVAL
+ * for unsupported n / parameters, DCG_ENOMEM when device memory runs out. */
+dcg_status dcg_setup(const dcg_mesh* mesh, double dt, double nu,
+                     const dcg_options* opt, dcg_handle* out);
+
+/* Solves A* x = b to ||r_i|| <= tol ||b|| (Section 4.1) by Algorithm 2 with
+ * the outer variant of the handle's options: prologue f_D = b - A* pi(b),
+ * outer iterations on the deflated system, epilogue
+ * x = (x_hat - pi(A* x_hat)) + pi(b) (eq. (x_defl)).  b, x: device, length
+ * 16 n^2, FP64, element-major; b is not modified.  Blocks until done.
+ * st (host, may be NULL) receives the counts of Table 3 and the residuals. */
+dcg_status dcg_solve(dcg_handle h, const double* b, double* x, double tol,
+                     dcg_stats* st, void* hip_stream);
+
+/* Operator-level entry points (for verification and composition).  All on
+ * the handle's mesh context; vectors are device pointers.  "level" counts
+ * multigrid levels 1 (coarsest, 16 x 16) .. J (finest); level vectors are
+ * FP32 in the DCG_MIXED form and FP64 in the DCG_FP64 form ("real" below).
+ *
+ *  op                 in           in2         out          computes
+ *  DCG_OP_ASTAR       p  (f64,N)   -           w  (f64,N)   A* p  (eq. (pb_study))
+ *  DCG_OP_ZT          w  (f64,N)   -           s  (f64,m)   Z^T w  (eq. (Vmatrix))
+ *  DCG_OP_Z           y  (f64,m)   -           v  (f64,N)   Z y
+ *  DCG_OP_ADIVZ       y  (f64,m)   -           v  (f64,N)   A_div Z y
+ *  DCG_OP_DEFLATED    p  (f64,N)   -           q  (f64,N)   M_D p = A*(p - pi(A* p))
+ *  DCG_OP_INNER       s  (f64,m)   -           y  (f64,m)   (Z^T A* Z)^{-1} s by Alg. 3
+ *  DCG_OP_LAPLACE     z  (real,m_k) -          v  (real,m_k) L_k z (L_J = 2 Z^T A_div Z)
+ *  DCG_OP_RAS         f  (real,m_k) z (real)   z' (real,m_k) z + S_k (f - L_k z)
+ *  DCG_OP_RESTRICT    r  (real,m_k) -          rc (real,m_{k-1}) P_k^T r
+ *  DCG_OP_PROLONG     e  (real,m_{k-1}) -      v  (real,m_k) P_k e
+ *  DCG_OP_COARSE      f  (real,m_1) -          z  (real,m_1) L_1^{-1} f (FP64 inverse)
+ *  DCG_OP_WCYCLE      f  (real,m_k) z0 (real or NULL = 0)  z (real,m_k)  Wcycle_k(f, z0)
+ *
+ * Level operators act on L_k = (2/dt) Z_k (the dt-free Laplacian hierarchy);
+ * the hierarchy of Algorithm 2 is Z_k = (dt/2) L_k.  m = 4 n^2, m_k = 4 n_k^2.
+ * Returns DCG_EINVAL for a bad op/level or NULL pointer. */
+typedef enum {
+  DCG_OP_ASTAR = 0, DCG_OP_ZT = 1, DCG_OP_Z = 2, DCG_OP_ADIVZ = 3,
+  DCG_OP_DEFLATED = 4, DCG_OP_INNER = 5, DCG_OP_LAPLACE = 6, DCG_OP_RAS = 7,
+  DCG_OP_RESTRICT = 8, DCG_OP_PROLONG = 9, DCG_OP_COARSE = 10, DCG_OP_WCYCLE = 11
+} dcg_op;
+
+dcg_status dcg_apply(dcg_handle h, dcg_op op, int32_t level, const void* in,
+                     const void* in2, void* out, void* hip_stream);
+
+/* Number of multigrid levels J of a mesh (log2(n/16) + 1), or -1. */
+int32_t dcg_num_levels(int32_t n);
+
+/* Host-only assembly, no device needed: writes one assembled matrix of the
+ * mesh context into the host buffer ``dst`` as a dense row-major FP64 block
+ * array in the block-ELL layout used on the device, and the int32 column
+ * (neighbour element) indices into ``cols`` (host, may be NULL):
+ *   which = 0: A_div,    blocks 16 x 16, dst [n^2][5][16][16]
+ *   which = 1: A_div Z,  blocks 16 x 4,  dst [n^2][5][16][4]
+ *   which = 2: M_1,      element mass 4 x 4, dst [n^2][4][4] (cols unused)
+ *   which = 3: L_level,  blocks 4 x 4,   dst [n_k^2][5][4][4]
+ *   which = 4: RAS tile inverses of level, D_i-weighted, dst [T_k][128][128]
+ *              (F[j][i] = (L_k)_i^{-1}[j][i] d_i), cols [T_k][32] = squares
+ *   which = 5: coarsest inverse L_1^{-1}, dst [1024][1024]
+ * Slots are (self, x-1, x+1, y-1, y+1); a missing neighbour has a zero
+ * block and column index -1.  ``dst_len`` is the buffer length in doubles;
+ * *needed (may be NULL) receives the required length.  Returns DCG_EINVAL
+ * when the buffer is too small or the arguments are invalid. */
+dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
+                             double* dst, int64_t dst_len, int32_t* cols,
+                             int64_t cols_len, int64_t* needed);
+
+/* Live timing of the dominant kernel of the solve, the RAS tile solves of
+ * the finest level (Section 4.2, (A_J)_i^{-1} applied to every block).
+ * While enabled, every launch of that kernel made by dcg_solve on this
+ * handle is bracketed by a pair of HIP events recorded on the solve's
+ * stream (inside the captured W-cycle graph as event-record nodes); the
+ * elapsed times are accumulated at the solver's convergence syncs.
+ * Enabling or disabling discards the captured graph.  _read returns the
+ * accumulated milliseconds and launch count since the last enable. */
+dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable);
+dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launches);
+
+dcg_status dcg_destroy(dcg_handle h);
+const char* dcg_strerror(dcg_status s);
+const char* dcg_last_error(dcg_handle h);
+
+/* Releases every cached mesh context (all devices).  Handles keep their own
+ * reference; call after destroying them to return the memory. */
+void dcg_clear_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCG_H */

@@ -1,0 +1,200 @@
+"""ctypes binding of libdcg.so (include/dcg.h): argument marshalling only.
+
+Every function keeps the name of its C entry point.  Vector arguments are
+torch tensors on the GPU (or raw device addresses as ints); the binding
+checks dtype, device, contiguity and length, passes ``data_ptr()`` and the
+current torch stream, and raises DCGError for negative status codes.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libdcg.so is not built (%s); run `python paper_2606_13429_amd/build.py` "
+        "or __graft_entry__.build() first" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------------ types
+DCG_OK, DCG_NOT_CONVERGED, DCG_PENDING = 0, 1, 2
+DCG_EINVAL, DCG_ENOMEM, DCG_EDEVICE, DCG_EAGAIN, DCG_ENOTFOUND, DCG_EBREAKDOWN = -1, -2, -3, -4, -5, -6
+DCG_FP64, DCG_MIXED = 0, 1
+DCG_OUTER_CG, DCG_OUTER_FCG1 = 0, 1
+(DCG_OP_ASTAR, DCG_OP_ZT, DCG_OP_Z, DCG_OP_ADIVZ, DCG_OP_DEFLATED, DCG_OP_INNER, DCG_OP_LAPLACE,
+ DCG_OP_RAS, DCG_OP_RESTRICT, DCG_OP_PROLONG, DCG_OP_COARSE, DCG_OP_WCYCLE) = range(12)
+
+
+class dcg_mesh(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("penalty", ctypes.c_double),
+                ("pre", ctypes.c_int32), ("post", ctypes.c_int32)]
+
+
+class dcg_options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("outer", ctypes.c_int), ("c_F", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+                ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class dcg_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("total_wcycles", ctypes.c_int32), ("inner_solves", ctypes.c_int32),
+                ("inner_per_outer", ctypes.c_double), ("rel_res_recurrence", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_h = ctypes.c_void_p
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER
+
+_SIGS = {
+    "dcg_defaults": (None, [_P(dcg_mesh), _P(dcg_options)]),
+    "dcg_setup": (ctypes.c_int, [_P(dcg_mesh), ctypes.c_double, ctypes.c_double, _P(dcg_options), _P(_h)]),
+    "dcg_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.c_double, _P(dcg_stats), _vp]),
+    "dcg_apply": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    "dcg_num_levels": (ctypes.c_int32, [ctypes.c_int32]),
+    "dcg_host_assemble": (ctypes.c_int, [_P(dcg_mesh), ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double),
+                                         ctypes.c_int64, _P(ctypes.c_int32), ctypes.c_int64, _P(ctypes.c_int64)]),
+    "dcg_kernel_timing": (ctypes.c_int, [_h, ctypes.c_int32]),
+    "dcg_kernel_timing_read": (ctypes.c_int, [_h, _P(ctypes.c_double), _P(ctypes.c_int64)]),
+    "dcg_destroy": (ctypes.c_int, [_h]),
+    "dcg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "dcg_last_error": (ctypes.c_char_p, [_h]),
+    "dcg_clear_cache": (None, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class DCGError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (dcg_strerror(status), status, message))
+        self.status = status
+
+
+def _check(status, handle=None):
+    if status < 0:
+        raise DCGError(status, dcg_last_error(handle))
+    return status
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    import torch
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ API
+def dcg_defaults():
+    m, o = dcg_mesh(), dcg_options()
+    _lib.dcg_defaults(ctypes.byref(m), ctypes.byref(o))
+    return m, o
+
+
+def dcg_num_levels(n):
+    return _lib.dcg_num_levels(n)
+
+
+def dcg_strerror(status):
+    return _lib.dcg_strerror(status).decode()
+
+
+def dcg_last_error(handle=None):
+    return _lib.dcg_last_error(handle).decode()
+
+
+def dcg_setup(mesh, dt, nu=1.0, opt=None):
+    h = _h()
+    _check(_lib.dcg_setup(ctypes.byref(mesh), dt, nu, ctypes.byref(opt) if opt is not None else None,
+                          ctypes.byref(h)))
+    return h
+
+
+def dcg_solve(handle, b, x, tol, stream=None):
+    """Returns (status, dcg_stats); raises DCGError on negative status."""
+    n = None
+    st = dcg_stats()
+    status = _lib.dcg_solve(handle, _ptr(b, _f64(), n, "b"), _ptr(x, _f64(), n, "x"), tol,
+                            ctypes.byref(st), _stream(stream))
+    _check(status, handle)
+    return status, st
+
+
+def dcg_apply(handle, op, level, inp, in2, out, stream=None):
+    return _check(_lib.dcg_apply(handle, op, level, _ptr(inp, name="in"), _ptr(in2, name="in2"),
+                                 _ptr(out, name="out"), _stream(stream)), handle)
+
+
+def dcg_host_assemble(mesh, which, level=0):
+    """Returns (values as a flat numpy float64 array, int32 columns or None)."""
+    import numpy as np
+    need = ctypes.c_int64()
+    _check(_lib.dcg_host_assemble(ctypes.byref(mesh), which, level, None, 0, None, 0, ctypes.byref(need)))
+    vals = np.empty(need.value, dtype=np.float64)
+    ne = mesh.n * mesh.n
+    ncols = {0: ne * 5, 1: ne * 5, 3: None, 4: None}.get(which)
+    if which == 3:
+        nk = mesh.n >> (dcg_num_levels(mesh.n) - level)
+        ncols = nk * nk * 5
+    elif which == 4:
+        ncols = vals.size // (128 * 128) * 32
+    cols = np.empty(ncols, dtype=np.int32) if ncols else None
+    _check(_lib.dcg_host_assemble(
+        ctypes.byref(mesh), which, level, vals.ctypes.data_as(_P(ctypes.c_double)), vals.size,
+        cols.ctypes.data_as(_P(ctypes.c_int32)) if cols is not None else None,
+        cols.size if cols is not None else 0, None))
+    return vals, cols
+
+
+def dcg_kernel_timing(handle, enable):
+    return _check(_lib.dcg_kernel_timing(handle, int(enable)), handle)
+
+
+def dcg_kernel_timing_read(handle):
+    """Returns (total milliseconds, launches) of the timed kernel."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.dcg_kernel_timing_read(handle, ctypes.byref(ms), ctypes.byref(n)), handle)
+    return ms.value, n.value
+
+
+def dcg_destroy(handle):
+    return _lib.dcg_destroy(handle)
+
+
+def dcg_clear_cache():
+    _lib.dcg_clear_cache()
+
+
+def _f64():
+    import torch
+    return torch.float64

@@ -1,0 +1,218 @@
+// extern "C" entry points of include/dcg.h: argument checks, handle
+// management and conversion of library errors into dcg_status codes.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "runtime.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dcg_status fail(dcg_ctx* h, dcg_status s, const std::string& msg) {
+  g_last_error = msg;
+  if (h) h->last_error = msg;
+  return s;
+}
+
+template <typename Fn>
+dcg_status guarded(dcg_ctx* h, Fn fn) {
+  try {
+    return fn();
+  } catch (const dcg::Error& e) {
+    return fail(h, e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(h, DCG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(h, DCG_EINVAL, e.what());
+  }
+}
+
+bool valid_mesh(const dcg_mesh& m, std::string& why) {
+  if (dcg::num_levels(m.n) < 0) {
+    why = "n must be 16 * 2^k with 16 <= n <= 2048";
+    return false;
+  }
+  if (!(m.penalty > 0.0) || !std::isfinite(m.penalty)) {
+    why = "penalty must be positive";
+    return false;
+  }
+  if (m.pre < 0 || m.post < 0 || m.pre > 16 || m.post > 16) {
+    why = "pre/post smoothing steps must be in [0, 16]";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dcg_defaults(dcg_mesh* mesh, dcg_options* opt) {
+  if (mesh) {
+    mesh->n = 512;
+    mesh->penalty = 10.0;
+    mesh->pre = 2;
+    mesh->post = 2;
+  }
+  if (opt) {
+    std::memset(opt, 0, sizeof *opt);
+    opt->prec = DCG_MIXED;
+    opt->outer = DCG_OUTER_CG;
+    opt->c_F = 0.01;
+    opt->max_outer = 50000;
+    opt->max_inner = 100;
+    opt->x0_given = 0;
+    opt->use_graph = 1;
+    opt->hbm_budget_bytes = 0;
+  }
+}
+
+int32_t dcg_num_levels(int32_t n) { return dcg::num_levels(n); }
+
+dcg_status dcg_setup(const dcg_mesh* mesh, double dt, double nu, const dcg_options* opt,
+                     dcg_handle* out) {
+  if (!mesh || !out) return fail(nullptr, DCG_EINVAL, "mesh and out must not be NULL");
+  *out = nullptr;
+  std::string why;
+  if (!valid_mesh(*mesh, why)) return fail(nullptr, DCG_EINVAL, why);
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(nullptr, DCG_EINVAL, "dt must be positive");
+  if (!(nu > 0.0) || !std::isfinite(nu)) return fail(nullptr, DCG_EINVAL, "nu must be positive");
+  dcg_options o;
+  dcg_defaults(nullptr, &o);
+  if (opt) o = *opt;
+  if (o.prec != DCG_FP64 && o.prec != DCG_MIXED) return fail(nullptr, DCG_EINVAL, "bad precision");
+  if (o.outer != DCG_OUTER_CG && o.outer != DCG_OUTER_FCG1) return fail(nullptr, DCG_EINVAL, "bad outer variant");
+  if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
+    return fail(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
+  dcg_ctx* h = nullptr;
+  const dcg_status st = guarded(nullptr, [&]() {
+    const auto t0 = std::chrono::steady_clock::now();
+    h = new dcg_ctx();
+    DCG_HIP(hipGetDevice(&h->device));
+    h->mp = *mesh;
+    h->opt = o;
+    h->dt = dt;
+    h->nu = nu;
+    h->fp32 = o.prec == DCG_MIXED;
+    h->mesh = dcg::get_context(mesh->n, mesh->penalty, h->fp32);
+    dcg::handle_init(h);
+    h->t_setup_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return DCG_OK;
+  });
+  if (st != DCG_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return DCG_OK;
+}
+
+dcg_status dcg_solve(dcg_handle h, const double* b, double* x, double tol, dcg_stats* st,
+                     void* hip_stream) {
+  if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  return guarded(h, [&]() {
+    return dcg::solve(h, b, x, tol, st, static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+dcg_status dcg_apply(dcg_handle h, dcg_op op, int32_t level, const void* in, const void* in2,
+                     void* out, void* hip_stream) {
+  if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  return guarded(h, [&]() {
+    return dcg::apply(h, op, level, in, in2, out, static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level, double* dst,
+                             int64_t dst_len, int32_t* cols, int64_t cols_len, int64_t* needed) {
+  if (!mesh) return fail(nullptr, DCG_EINVAL, "mesh must not be NULL");
+  std::string why;
+  if (!valid_mesh(*mesh, why)) return fail(nullptr, DCG_EINVAL, why);
+  if (which < 0 || which > 5) return fail(nullptr, DCG_EINVAL, "which must be in [0, 5]");
+  return guarded(nullptr, [&]() -> dcg_status {
+    const int J = dcg::num_levels(mesh->n);
+    if ((which == 3 || which == 4) && (level < 1 || level > J))
+      return fail(nullptr, DCG_EINVAL, "level out of range");
+    if (which == 4 && level < 2) return fail(nullptr, DCG_EINVAL, "RAS tiles exist on levels >= 2");
+    dcg::HostContext hc;
+    dcg::build_host_context(mesh->n, mesh->penalty, which == 4, which == 5, hc);
+    const int64_t ne = int64_t(mesh->n) * mesh->n;
+    std::vector<double> tmp;
+    const std::vector<double>* src = nullptr;
+    const std::vector<int32_t>* csrc = nullptr;
+    switch (which) {
+      case 0: src = &hc.Adiv; csrc = &hc.cols; break;
+      case 1: src = &hc.AdivZ; csrc = &hc.cols; break;
+      case 2: src = &hc.M1; break;
+      case 3: src = &hc.levels[level - 1].L; csrc = &hc.levels[level - 1].cols; break;
+      case 4: {
+        const dcg::HostLevel& hl = hc.levels[level - 1];
+        const size_t per = size_t(dcg::kTileDofs) * dcg::kTileDofs;
+        tmp.resize(per * hl.tiles);
+        for (int t = 0; t < hl.tiles; ++t)
+          std::memcpy(&tmp[per * t], hl.unique_inv[hl.tile_class[t]].data(), per * sizeof(double));
+        src = &tmp;
+        csrc = &hl.tile_elems;
+        break;
+      }
+      case 5: src = &hc.coarse_inv; break;
+    }
+    (void)ne;
+    if (needed) *needed = int64_t(src->size());
+    if (!dst) return DCG_OK;
+    if (dst_len < int64_t(src->size())) return fail(nullptr, DCG_EINVAL, "dst buffer too small");
+    std::memcpy(dst, src->data(), src->size() * sizeof(double));
+    if (cols && csrc) {
+      if (cols_len < int64_t(csrc->size())) return fail(nullptr, DCG_EINVAL, "cols buffer too small");
+      std::memcpy(cols, csrc->data(), csrc->size() * sizeof(int32_t));
+    }
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable) {
+  if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  return guarded(h, [&]() {
+    dcg::kernel_timing(h, enable != 0);
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launches) {
+  if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  if (total_ms) *total_ms = h->ktime_ms;
+  if (launches) *launches = h->klaunches;
+  return DCG_OK;
+}
+
+dcg_status dcg_destroy(dcg_handle h) {
+  delete h;
+  return DCG_OK;
+}
+
+const char* dcg_strerror(dcg_status s) {
+  switch (s) {
+    case DCG_OK: return "ok";
+    case DCG_NOT_CONVERGED: return "not converged (max_outer reached)";
+    case DCG_PENDING: return "pending";
+    case DCG_EINVAL: return "invalid argument";
+    case DCG_ENOMEM: return "out of memory";
+    case DCG_EDEVICE: return "device error";
+    case DCG_EAGAIN: return "queue full, try again";
+    case DCG_ENOTFOUND: return "unknown ticket";
+    case DCG_EBREAKDOWN: return "breakdown of the outer iteration";
+  }
+  return "unknown status";
+}
+
+const char* dcg_last_error(dcg_handle h) {
+  return h ? h->last_error.c_str() : g_last_error.c_str();
+}
+
+void dcg_clear_cache(void) { dcg::clear_context_cache(); }
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// Mesh contexts: host assembly (host_setup.cpp) converted to the device
+// layouts of kernels.hpp and uploaded once per (device, n, penalty).
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <thread>
+#include <tuple>
+
+#include "runtime.hpp"
+
+namespace dcg {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  const dcg_status s = (e == hipErrorOutOfMemory) ? DCG_ENOMEM : DCG_EDEVICE;
+  throw Error(s, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* MeshContext::alloc(size_t b) {
+  void* p = nullptr;
+  DCG_HIP(hipMalloc(&p, b));
+  allocations.push_back(p);
+  bytes += b;
+  return p;
+}
+
+MeshContext::~MeshContext() {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  for (void* p : allocations) (void)hipFree(p);
+  (void)hipSetDevice(cur);
+}
+
+namespace {
+
+template <typename Fn>
+void threaded(int64_t count, Fn fn) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (count < 1024) nt = 1;
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([=, &fn]() {
+      for (int64_t i = count * t / nt; i < count * (t + 1) / nt; ++i) fn(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+// Uploads a [ne][slot][rows][cols] block array into the device layout
+// double2 [slot][cols/2][ne][rows] in chunks of squares.
+void upload_blocks_pairs(const std::vector<double>& host, int64_t ne, int rows, int ncol,
+                         double2* dev) {
+  const int kcs = ncol / 2;
+  const int64_t chunk = 1 << 15;
+  std::vector<double2> stage(size_t(chunk) * kSlots * kcs * rows);
+  for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
+    const int64_t cnt = std::min(chunk, ne - e0);
+    threaded(cnt, [&](int64_t de) {
+      const int64_t e = e0 + de;
+      for (int s = 0; s < kSlots; ++s)
+        for (int kc = 0; kc < kcs; ++kc)
+          for (int r = 0; r < rows; ++r) {
+            const double* src = &host[((e * kSlots + s) * rows + r) * ncol + 2 * kc];
+            stage[((size_t(s) * kcs + kc) * cnt + de) * rows + r] = make_double2(src[0], src[1]);
+          }
+    });
+    for (int s = 0; s < kSlots; ++s)
+      for (int kc = 0; kc < kcs; ++kc)
+        DCG_HIP(hipMemcpy(dev + ((int64_t(s) * kcs + kc) * ne + e0) * rows,
+                          &stage[(size_t(s) * kcs + kc) * cnt * rows], sizeof(double2) * cnt * rows,
+                          hipMemcpyHostToDevice));
+  }
+}
+
+void upload_cols(const std::vector<int32_t>& host, int64_t ne, int32_t* dev) {
+  std::vector<int32_t> t(size_t(ne) * kSlots);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int s = 0; s < kSlots; ++s) t[size_t(s) * ne + e] = host[e * kSlots + s];
+  DCG_HIP(hipMemcpy(dev, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+}
+
+template <typename T>
+void upload_level_L(const HostLevel& hl, T* dev) {
+  const int64_t ne = int64_t(hl.n) * hl.n;
+  std::vector<T> t(size_t(ne) * kSlots * 16);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int s = 0; s < kSlots; ++s)
+      for (int k = 0; k < 16; ++k) t[(size_t(s) * ne + e) * 16 + k] = T(hl.L[(e * kSlots + s) * 16 + k]);
+  DCG_HIP(hipMemcpy(dev, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <typename T>
+void upload_factors(const HostLevel& hl, T* dev) {
+  const int64_t per = kTileDofs * kTileDofs;
+  const int chunk = 512;
+  std::vector<T> stage(size_t(chunk) * per);
+  for (int t0 = 0; t0 < hl.tiles; t0 += chunk) {
+    const int cnt = std::min(chunk, hl.tiles - t0);
+    threaded(cnt, [&](int64_t dt) {
+      const std::vector<double>& src = hl.unique_inv[hl.tile_class[t0 + dt]];
+      T* d = &stage[size_t(dt) * per];
+      for (int64_t k = 0; k < per; ++k) d[k] = T(src[k]);
+    });
+    DCG_HIP(hipMemcpy(dev + int64_t(t0) * per, stage.data(), sizeof(T) * cnt * per,
+                      hipMemcpyHostToDevice));
+  }
+}
+
+struct Key {
+  int device, n;
+  double penalty;
+  bool operator<(const Key& o) const {
+    return std::tie(device, n, penalty) < std::tie(o.device, o.n, o.penalty);
+  }
+};
+std::mutex g_cache_mu;
+std::map<Key, std::shared_ptr<MeshContext>> g_cache;
+
+std::shared_ptr<MeshContext> build_context(int device, int n, double penalty) {
+  auto t0 = std::chrono::steady_clock::now();
+  auto ctx = std::make_shared<MeshContext>();
+  ctx->device = device;
+  ctx->host = std::make_unique<HostContext>();
+  HostContext& hc = *ctx->host;
+  try {
+    build_host_context(n, penalty, true, true, hc);
+  } catch (const std::exception& ex) {
+    throw Error(DCG_EINVAL, ex.what());
+  }
+  ctx->n = n;
+  ctx->J = hc.J;
+  ctx->ne = n * n;
+  ctx->penalty = penalty;
+  const int64_t ne = ctx->ne;
+  ctx->Adiv = static_cast<double2*>(ctx->alloc(sizeof(double) * ne * kSlots * 256));
+  ctx->AdivZ = static_cast<double2*>(ctx->alloc(sizeof(double) * ne * kSlots * 64));
+  ctx->M1 = static_cast<double*>(ctx->alloc(sizeof(double) * ne * 16));
+  ctx->cols = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * ne * kSlots));
+  upload_blocks_pairs(hc.Adiv, ne, 16, 16, ctx->Adiv);
+  upload_blocks_pairs(hc.AdivZ, ne, 16, 4, ctx->AdivZ);
+  DCG_HIP(hipMemcpy(ctx->M1, hc.M1.data(), sizeof(double) * ne * 16, hipMemcpyHostToDevice));
+  upload_cols(hc.cols, ne, ctx->cols);
+  // the tensor blocks are not needed on the host any more
+  std::vector<double>().swap(hc.Adiv);
+  std::vector<double>().swap(hc.AdivZ);
+  std::vector<double>().swap(hc.M1);
+  ctx->lv.resize(hc.J);
+  for (int k = 1; k <= hc.J; ++k) {
+    const HostLevel& hl = hc.levels[k - 1];
+    DeviceLevel& dl = ctx->lv[k - 1];
+    dl.n = hl.n;
+    dl.ne = hl.n * hl.n;
+    dl.cols = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * dl.ne * kSlots));
+    upload_cols(hl.cols, dl.ne, dl.cols);
+    // FP64 level operator: the refinement residual needs it at the finest
+    // level and the FP64 form at every level
+    dl.L64 = static_cast<double*>(ctx->alloc(sizeof(double) * dl.ne * kSlots * 16));
+    upload_level_L<double>(hl, dl.L64);
+    if (k >= 2) {
+      dl.tiles = hl.tiles;
+      dl.tile_elems = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_elems.size()));
+      DCG_HIP(hipMemcpy(dl.tile_elems, hl.tile_elems.data(), sizeof(int32_t) * hl.tile_elems.size(),
+                        hipMemcpyHostToDevice));
+      dl.cover = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.cover.size()));
+      DCG_HIP(hipMemcpy(dl.cover, hl.cover.data(), sizeof(int32_t) * hl.cover.size(),
+                        hipMemcpyHostToDevice));
+    }
+  }
+  ctx->coarse_inv = static_cast<double*>(ctx->alloc(sizeof(double) * kCoarseDofs * kCoarseDofs));
+  DCG_HIP(hipMemcpy(ctx->coarse_inv, hc.coarse_inv.data(),
+                    sizeof(double) * kCoarseDofs * kCoarseDofs, hipMemcpyHostToDevice));
+  ctx->t_build_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return ctx;
+}
+
+}  // namespace
+
+void MeshContext::ensure_factors(bool fp32) {
+  std::lock_guard<std::mutex> lk(mu);
+  if (fp32 ? have_f32 : have_f64) return;
+  if (!host) throw Error(DCG_EDEVICE, "mesh context lost its host data");
+  int cur = 0;
+  DCG_HIP(hipGetDevice(&cur));
+  DCG_HIP(hipSetDevice(device));
+  for (int k = 1; k <= J; ++k) {
+    const HostLevel& hl = host->levels[k - 1];
+    DeviceLevel& dl = lv[k - 1];
+    if (fp32) {
+      dl.L32 = static_cast<float*>(alloc(sizeof(float) * dl.ne * kSlots * 16));
+      upload_level_L<float>(hl, dl.L32);
+    }
+    if (k >= 2) {
+      const size_t cnt = size_t(hl.tiles) * kTileDofs * kTileDofs;
+      if (fp32) {
+        dl.F32 = static_cast<float*>(alloc(sizeof(float) * cnt));
+        upload_factors<float>(hl, dl.F32);
+      } else {
+        dl.F64 = static_cast<double*>(alloc(sizeof(double) * cnt));
+        upload_factors<double>(hl, dl.F64);
+      }
+    }
+  }
+  (fp32 ? have_f32 : have_f64) = true;
+  if (have_f32 && have_f64) host.reset();
+  DCG_HIP(hipSetDevice(cur));
+}
+
+std::shared_ptr<MeshContext> get_context(int n, double penalty, bool fp32) {
+  int device = 0;
+  DCG_HIP(hipGetDevice(&device));
+  std::shared_ptr<MeshContext> ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(Key{device, n, penalty});
+    if (it != g_cache.end()) ctx = it->second;
+  }
+  if (!ctx) {
+    auto built = build_context(device, n, penalty);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(Key{device, n, penalty});
+    if (it != g_cache.end()) {
+      ctx = it->second;          // another thread won the race
+    } else {
+      g_cache[Key{device, n, penalty}] = built;
+      ctx = built;
+    }
+  }
+  ctx->ensure_factors(fp32);
+  return ctx;
+}
+
+void clear_context_cache() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.clear();
+}
+
+}  // namespace dcg

@@ -1,0 +1,51 @@
+// Host-side construction of the dt-independent mesh context: DG-Q1 element
+// and face integrals, block-ELL assembly of A_div, A_div Z, the element mass
+// blocks, the Galerkin hierarchy of L = 2 Z^T A_div Z and the RAS tile
+// inverses (paper Sections 3.1, 3.3.2, 4.2; Algorithm 2).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dcg {
+
+constexpr int kSlots = 5;        // self, x-1, x+1, y-1, y+1
+constexpr int kTileCore = 4;     // 4 x 4 squares per RAS core
+constexpr int kTileSlots = 32;   // core + face-neighbour layer
+constexpr int kTileDofs = 128;   // 4 dofs per square
+constexpr int kCoarsestN = 16;   // level 1 is 16 x 16 squares
+constexpr int kCoarseDofs = 4 * kCoarsestN * kCoarsestN;
+
+struct HostLevel {
+  int n = 0;                       // squares per side on this level
+  std::vector<double> L;           // [Ne][5][4][4]
+  std::vector<int32_t> cols;       // [Ne][5], -1 = no neighbour
+  // RAS data, levels k >= 2
+  int tiles = 0;
+  std::vector<int32_t> tile_elems; // [T][32], -1 = padded slot
+  std::vector<int32_t> tile_class; // [T] index into unique_inv
+  std::vector<std::vector<double>> unique_inv;  // each [128][128], F = A_i^{-1} D_i
+  std::vector<int32_t> cover;      // [Ne][3] = tile * 32 + slot, -1 = none
+};
+
+struct HostContext {
+  int n = 0, J = 0;
+  double penalty = 10.0;
+  std::vector<double> Adiv;        // [Ne][5][16][16]
+  std::vector<double> AdivZ;       // [Ne][5][16][4]
+  std::vector<double> M1;          // [Ne][4][4]
+  std::vector<int32_t> cols;       // [Ne][5]
+  std::vector<HostLevel> levels;   // levels[k - 1], k = 1..J
+  std::vector<double> coarse_inv;  // [1024][1024]
+};
+
+// J = log2(n / 16) + 1, or -1 if n is not 16 * 2^k (n <= 2048).
+int num_levels(int n);
+
+// Builds the full context; throws std::runtime_error on failure.  When
+// ``with_tiles`` is false the RAS inverses and the coarsest inverse are
+// skipped (used by the host-only assembly queries that do not need them).
+void build_host_context(int n, double penalty, bool with_tiles, bool with_coarse,
+                        HostContext& out);
+
+}  // namespace dcg

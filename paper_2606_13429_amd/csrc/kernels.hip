@@ -1,0 +1,804 @@
+// gfx950 kernels of the deflated-CG hot path (paper Section 4, Algorithms 2-4).
+//
+// Everything here is bandwidth bound (well under 1 flop per byte), so the
+// kernels are organised around coalesced 16-byte loads of the stored
+// operators: a wavefront of 64 lanes reads 1 KiB per load instruction, the
+// operator layouts (kernels.hpp) put consecutive lanes on consecutive
+// 16-byte words, and vector operands come from L2 / LDS.  Dot products are
+// two-stage and deterministic: a fixed-order wave64 shuffle tree and an LDS
+// tree per workgroup, per-workgroup partials, and one fixed-order final
+// pass (no floating-point atomics anywhere).
+#include "kernels.hpp"
+
+#include <cmath>
+
+namespace dcg {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Workgroup sum of v (all 256 threads participate); result valid in thread 0.
+__device__ inline double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  return s;
+}
+
+// ---------------------------------------------------------------- 4-vectors
+__device__ inline void ld4(const float* p, float v[4]) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ inline void ld4(const double* p, double v[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ inline void st4(float* p, const float v[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline void st4(double* p, const double v[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+
+inline int grid_for(int64_t items, int per_block, int cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  return int(g < cap ? g : cap);
+}
+
+// ============================================================ outer kernels
+// w = (1/nu) M u + dt A_div u, s = Z^T w.  Thread (square e, row r); one
+// workgroup = 16 squares.  M = C (x) M_1 with C the dev-dev coefficient
+// matrix (Section 3.1): rows 11/22 see (u11 - u22)/2, rows 12/21 see u.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_astar(
+    const double2* __restrict__ A, const int32_t* __restrict__ cols, const double* __restrict__ M1,
+    int ne, double dt, double inv_nu, const double* __restrict__ x, const double* __restrict__ p_old,
+    const double* __restrict__ b, const Scalars* __restrict__ sc, double* __restrict__ p_new,
+    double* __restrict__ w, double* __restrict__ s, double* __restrict__ part) {
+  __shared__ double lds[4];
+  const int r = threadIdx.x & 15;
+  const double beta = MODE == kAstarDir ? sc->beta : 0.0;
+  const int groups = (ne + 15) >> 4;
+  double dot = 0.0;
+  for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+    const int e = (g << 4) + (threadIdx.x >> 4);
+    const bool valid = e < ne;
+    double acc = 0.0, wv = 0.0;
+    double self[16];
+    if (valid) {
+#pragma unroll
+      for (int slot = 0; slot < 5; ++slot) {
+        const int c = cols[slot * ne + e];
+        if (c < 0) continue;
+        double u[16];
+        const double2* xs = reinterpret_cast<const double2*>(x + 16 * (int64_t)c);
+#pragma unroll
+        for (int kc = 0; kc < 8; ++kc) {
+          double2 v = xs[kc];
+          if (MODE == kAstarDir) {
+            const double2 po = reinterpret_cast<const double2*>(p_old + 16 * (int64_t)c)[kc];
+            v.x = v.x + beta * po.x;
+            v.y = v.y + beta * po.y;
+          }
+          u[2 * kc] = v.x;
+          u[2 * kc + 1] = v.y;
+        }
+        const double2* Ab = A + ((int64_t)slot * 8 * ne + e) * 16 + r;
+#pragma unroll
+        for (int kc = 0; kc < 8; ++kc) {
+          const double2 a = Ab[(int64_t)kc * ne * 16];
+          acc += a.x * u[2 * kc] + a.y * u[2 * kc + 1];
+        }
+        if (slot == 0) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) self[k] = u[k];
+        }
+      }
+      const int cc = r >> 2, j = r & 3;
+      double m[4];
+      ld4(M1 + 16 * (int64_t)e + 4 * j, m);
+      double mu;
+      if (cc == 0 || cc == 3) {
+        const double d0 = self[0] - self[12], d1 = self[1] - self[13];
+        const double d2 = self[2] - self[14], d3 = self[3] - self[15];
+        mu = 0.5 * (m[0] * d0 + m[1] * d1 + m[2] * d2 + m[3] * d3);
+        if (cc == 3) mu = -mu;
+      } else {
+        const int o = 4 * cc;
+        mu = m[0] * self[o] + m[1] * self[o + 1] + m[2] * self[o + 2] + m[3] * self[o + 3];
+      }
+      wv = inv_nu * mu + dt * acc;
+      if (MODE == kAstarResidual) {
+        wv = b[16 * (int64_t)e + r] - wv;
+        dot += wv * wv;
+      }
+      if (w) w[16 * (int64_t)e + r] = wv;
+      if (MODE == kAstarDir || MODE == kAstarFirst) p_new[16 * (int64_t)e + r] = self[r];
+    }
+    // s = Z^T w: lanes r = j and r = 12 + j of the same square
+    const double w22 = __shfl_down(wv, 12, 16);
+    if (s && valid && r < 4) s[4 * (int64_t)e + r] = (wv + w22) * kInvSqrt2;
+  }
+  if (MODE == kAstarResidual) {
+    const double t = block_sum(dot, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
+}
+
+// q = w - c (A_div Z) z, partial (p, q); prologue: r = w - c AZ z -> q, p_out,
+// partials (w, w), (r, r).
+template <bool PROLOGUE>
+__global__ __launch_bounds__(kThreads) void k_deflate(
+    const double2* __restrict__ AZ, const int32_t* __restrict__ cols, int ne, double c,
+    const double* __restrict__ z, const double* __restrict__ w, const double* __restrict__ p,
+    double* __restrict__ q, double* __restrict__ p_out, double* __restrict__ part) {
+  __shared__ double lds[4];
+  const int r = threadIdx.x & 15;
+  const int groups = (ne + 15) >> 4;
+  double d0 = 0.0, d1 = 0.0;
+  for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+    const int e = (g << 4) + (threadIdx.x >> 4);
+    if (e >= ne) continue;
+    double acc = 0.0;
+#pragma unroll
+    for (int slot = 0; slot < 5; ++slot) {
+      const int col = cols[slot * ne + e];
+      if (col < 0) continue;
+      const double2* zc = reinterpret_cast<const double2*>(z + 4 * (int64_t)col);
+      const double2* Ab = AZ + ((int64_t)slot * 2 * ne + e) * 16 + r;
+      const double2 a0 = Ab[0], a1 = Ab[(int64_t)ne * 16];
+      const double2 z0 = zc[0], z1 = zc[1];
+      acc += a0.x * z0.x + a0.y * z0.y + a1.x * z1.x + a1.y * z1.y;
+    }
+    const int64_t i = 16 * (int64_t)e + r;
+    const double wv = w[i];
+    const double qv = wv - c * acc;
+    q[i] = qv;
+    if (PROLOGUE) {
+      p_out[i] = qv;
+      d0 += wv * wv;
+      d1 += qv * qv;
+    } else {
+      d0 += p[i] * qv;
+    }
+  }
+  const double t0 = block_sum(d0, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t0;
+  if (PROLOGUE) {
+    const double t1 = block_sum(d1, lds);
+    if (threadIdx.x == 0) part[kPartStride + blockIdx.x] = t1;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_adivz(const double2* __restrict__ AZ,
+                                                    const int32_t* __restrict__ cols, int ne,
+                                                    const double* __restrict__ y,
+                                                    double* __restrict__ out) {
+  const int e = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int r = threadIdx.x & 15;
+  if (e >= ne) return;
+  double acc = 0.0;
+  for (int slot = 0; slot < 5; ++slot) {
+    const int col = cols[slot * ne + e];
+    if (col < 0) continue;
+    const double2* zc = reinterpret_cast<const double2*>(y + 4 * (int64_t)col);
+    const double2* Ab = AZ + ((int64_t)slot * 2 * ne + e) * 16 + r;
+    const double2 a0 = Ab[0], a1 = Ab[(int64_t)ne * 16];
+    acc += a0.x * zc[0].x + a0.y * zc[0].y + a1.x * zc[1].x + a1.y * zc[1].y;
+  }
+  out[16 * (int64_t)e + r] = acc;
+}
+
+// x += alpha p; r -= alpha q; partial (r, r) [flexible: (r,q), (p,r)]
+template <bool FLEX>
+__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t n, const Scalars* __restrict__ sc,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ q,
+                                                        double* __restrict__ x,
+                                                        double* __restrict__ r,
+                                                        double* __restrict__ part) {
+  __shared__ double lds[4];
+  const double alpha = sc->alpha;
+  double rr = 0.0, rq = 0.0, pr = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double pi = p[i], qi = q[i];
+    x[i] = x[i] + alpha * pi;
+    const double ri = r[i] - alpha * qi;
+    r[i] = ri;
+    rr += ri * ri;
+    if (FLEX) {
+      rq += ri * qi;
+      pr += pi * ri;
+    }
+  }
+  const double t0 = block_sum(rr, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t0;
+  if (FLEX) {
+    const double t1 = block_sum(rq, lds);
+    if (threadIdx.x == 0) part[kPartStride + blockIdx.x] = t1;
+    const double t2 = block_sum(pr, lds);
+    if (threadIdx.x == 0) part[2 * kPartStride + blockIdx.x] = t2;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpy_dot(int64_t n, double a,
+                                                       const double* __restrict__ q,
+                                                       double* __restrict__ r,
+                                                       double* __restrict__ part) {
+  __shared__ double lds[4];
+  double rr = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double ri = r[i] + a * q[i];
+    r[i] = ri;
+    rr += ri * ri;
+  }
+  const double t = block_sum(rr, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ part, int nb,
+                                                     int op, Scalars* __restrict__ sc) {
+  __shared__ double sm[kThreads];
+  const int nslot = op == kRedB2Rho ? 2 : (op == kRedFcgBeta ? 3 : 1);
+  double sums[3] = {0.0, 0.0, 0.0};
+  for (int slot = 0; slot < nslot; ++slot) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) v += part[slot * kPartStride + i];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+      __syncthreads();
+    }
+    sums[slot] = sm[0];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case kRedB2Rho:
+      sc->b2 = sums[0];
+      sc->rho = sums[1];
+      sc->dr = sums[1];
+      break;
+    case kRedAlpha:
+    case kRedFcgAlpha: {
+      const double pq = sums[0];
+      sc->pq = pq;
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        sc->breakdown = 1;
+        sc->alpha = 0.0;
+      } else {
+        sc->alpha = (op == kRedAlpha ? sc->rho : sc->dr) / pq;
+      }
+      break;
+    }
+    case kRedBeta:
+      sc->beta = sc->rho > 0.0 ? sums[0] / sc->rho : 0.0;
+      sc->rho = sums[0];
+      sc->dr = sums[0];
+      break;
+    case kRedFcgBeta: {
+      const double beta = sc->pq > 0.0 ? -sums[1] / sc->pq : 0.0;
+      sc->rho = sums[0];
+      sc->beta = beta;
+      sc->dr = sums[0] + beta * sums[2];
+      break;
+    }
+    case kRedS2:
+      sc->s2 = sums[0];
+      sc->r2 = sums[0];
+      break;
+    case kRedR2:
+      sc->r2 = sums[0];
+      break;
+    case kRedRes:
+      sc->res2 = sums[0];
+      break;
+    case kRedRho:
+      sc->rho = sums[0];
+      sc->dr = sums[0];
+      break;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_zt(int ne, const double* __restrict__ w,
+                                                 double* __restrict__ s) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= 4 * (int64_t)ne) return;
+  const int64_t e = i >> 2, j = i & 3;
+  s[i] = (w[16 * e + j] + w[16 * e + 12 + j]) * kInvSqrt2;
+}
+
+__global__ __launch_bounds__(kThreads) void k_z(int ne, const double* __restrict__ y, double c,
+                                                double* __restrict__ v) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= 16 * (int64_t)ne) return;
+  const int64_t e = i >> 4, cc = (i >> 2) & 3, j = i & 3;
+  v[i] = (cc == 0 || cc == 3) ? (c * y[4 * e + j]) * kInvSqrt2 : 0.0;
+}
+
+// x = (xh - Z (c zt)) + Z (c zb)  (eq. (x_defl) with pi(b) reused)
+__global__ __launch_bounds__(kThreads) void k_reconstruct(int ne, const double* __restrict__ xh,
+                                                          const double* __restrict__ zt,
+                                                          const double* __restrict__ zb, double c,
+                                                          double* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= 16 * (int64_t)ne) return;
+  const int64_t e = i >> 4, cc = (i >> 2) & 3, j = i & 3;
+  double v = xh[i];
+  if (cc == 0 || cc == 3) {
+    v = v - (c * zt[4 * e + j]) * kInvSqrt2;
+    v = v + (c * zb[4 * e + j]) * kInvSqrt2;
+  }
+  x[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale(int64_t n, double c,
+                                                    const double* __restrict__ in,
+                                                    double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i < n) out[i] = c * in[i];
+}
+
+// ============================================================ inner refinement
+// r = s - L64 z (first: r = s) in FP64, fJ = (T) r, partial ||r||^2.
+// Thread (square e, row a): one workgroup = 64 squares.
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kThreads) void k_refine_residual(
+    const double* __restrict__ L, const int32_t* __restrict__ cols, int ne,
+    const double* __restrict__ s, const double* __restrict__ z, T* __restrict__ fJ,
+    double* __restrict__ part) {
+  __shared__ double lds[4];
+  const int a = threadIdx.x & 3;
+  const int groups = (ne + 63) >> 6;
+  double nrm = 0.0;
+  for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+    const int e = (g << 6) + (threadIdx.x >> 2);
+    if (e >= ne) continue;
+    double acc = 0.0;
+    if (!FIRST) {
+#pragma unroll
+      for (int slot = 0; slot < 5; ++slot) {
+        const int col = cols[slot * ne + e];
+        if (col < 0) continue;
+        double l[4], zc[4];
+        ld4(L + (((int64_t)slot * ne + e) * 4 + a) * 4, l);
+        ld4(z + 4 * (int64_t)col, zc);
+        acc += l[0] * zc[0] + l[1] * zc[1] + l[2] * zc[2] + l[3] * zc[3];
+      }
+    }
+    const int64_t i = 4 * (int64_t)e + a;
+    const double rv = s[i] - acc;
+    fJ[i] = static_cast<T>(rv);
+    nrm += rv * rv;
+  }
+  const double t = block_sum(nrm, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kThreads) void k_refine_update(int64_t m, const T* __restrict__ zJ,
+                                                            double* __restrict__ z) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= m) return;
+  const double d = static_cast<double>(zJ[i]);
+  z[i] = FIRST ? d : z[i] + d;
+}
+
+// ============================================================ multigrid levels
+// out = L z (RES = false) or out = f - L z (RES = true); thread (square, row).
+template <typename T, bool RES>
+__global__ __launch_bounds__(kThreads) void k_lap(const T* __restrict__ L,
+                                                  const int32_t* __restrict__ cols, int ne,
+                                                  const T* __restrict__ f, const T* __restrict__ z,
+                                                  T* __restrict__ out) {
+  const int e = blockIdx.x * 64 + (threadIdx.x >> 2);
+  const int a = threadIdx.x & 3;
+  if (e >= ne) return;
+  T acc = T(0);
+#pragma unroll
+  for (int slot = 0; slot < 5; ++slot) {
+    const int col = cols[slot * ne + e];
+    if (col < 0) continue;
+    T l[4], zc[4];
+    ld4(L + (((int64_t)slot * ne + e) * 4 + a) * 4, l);
+    ld4(z + 4 * (int64_t)col, zc);
+    acc += l[0] * zc[0] + l[1] * zc[1] + l[2] * zc[2] + l[3] * zc[3];
+  }
+  const int64_t i = 4 * (int64_t)e + a;
+  out[i] = RES ? f[i] - acc : acc;
+}
+
+// Y_t = F_t^T-weighted solve of tile t: Y[t][i] = sum_j F[t][j][i] r[g(t, j)],
+// i.e. D_t (L_k)_t^{-1} R_t r.  One wavefront per tile; the 128-value gather
+// of r is staged in LDS and broadcast, each lane owns 4 (FP32) or 2 (FP64)
+// output columns and streams the factor row by row with 16-byte loads.
+__global__ __launch_bounds__(kThreads) void k_ras_tiles_f32(const float* __restrict__ F,
+                                                            const int32_t* __restrict__ te,
+                                                            int tiles, const float* __restrict__ r,
+                                                            float* __restrict__ Y) {
+  __shared__ float rl[4][128];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + wave;
+  if (t < tiles && lane < 32) {
+    const int e = te[t * 32 + lane];
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (e >= 0) ld4(r + 4 * (int64_t)e, v);
+    st4(&rl[wave][4 * lane], v);
+  }
+  __syncthreads();
+  if (t >= tiles) return;
+  const int half = lane >> 5, c4 = lane & 31;
+  const float4* Ft = reinterpret_cast<const float4*>(F + (int64_t)t * 16384);
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll 16
+  for (int m = 0; m < 64; ++m) {
+    const int j = 2 * m + half;
+    const float4 fv = Ft[j * 32 + c4];
+    const float rj = rl[wave][j];
+    a0 += fv.x * rj;
+    a1 += fv.y * rj;
+    a2 += fv.z * rj;
+    a3 += fv.w * rj;
+  }
+  a0 += __shfl_xor(a0, 32, 64);
+  a1 += __shfl_xor(a1, 32, 64);
+  a2 += __shfl_xor(a2, 32, 64);
+  a3 += __shfl_xor(a3, 32, 64);
+  if (half == 0) {
+    const float v[4] = {a0, a1, a2, a3};
+    st4(Y + (int64_t)t * 128 + 4 * c4, v);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ras_tiles_f64(const double* __restrict__ F,
+                                                            const int32_t* __restrict__ te,
+                                                            int tiles, const double* __restrict__ r,
+                                                            double* __restrict__ Y) {
+  __shared__ double rl[4][128];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + wave;
+  if (t < tiles && lane < 32) {
+    const int e = te[t * 32 + lane];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (e >= 0) ld4(r + 4 * (int64_t)e, v);
+    st4(&rl[wave][4 * lane], v);
+  }
+  __syncthreads();
+  if (t >= tiles) return;
+  const double2* Ft = reinterpret_cast<const double2*>(F + (int64_t)t * 16384);
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll 16
+  for (int j = 0; j < 128; ++j) {
+    const double2 fv = Ft[j * 64 + lane];
+    const double rj = rl[wave][j];
+    a0 += fv.x * rj;
+    a1 += fv.y * rj;
+  }
+  reinterpret_cast<double2*>(Y + (int64_t)t * 128)[lane] = make_double2(a0, a1);
+}
+
+// z = (zero ? 0 : z) + sum over the (at most 3) blocks covering the square,
+// in increasing block order (R_i^T D_i summation of the RAS update).
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(kThreads) void k_ras_update(const int32_t* __restrict__ cover, int ne,
+                                                         const T* __restrict__ Y,
+                                                         T* __restrict__ z) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= 4 * (int64_t)ne) return;
+  const int64_t e = i >> 2;
+  const int j = int(i & 3);
+  T v = ZERO ? T(0) : z[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int c = cover[e * 3 + k];
+    if (c >= 0) v += Y[4 * (int64_t)c + j];
+  }
+  z[i] = v;
+}
+
+// Coefficient of coarse corner A at fine corner a of child ch: the coarse
+// bilinear function at ((ch_x + a_x)/2, (ch_y + a_y)/2); values in
+// {0, 1/4, 1/2, 1}, exact in any precision.
+template <typename T>
+__device__ inline T pcoef(int ch, int a, int A) {
+  const int px = (ch & 1) + (a & 1), py = (ch >> 1) + (a >> 1);   // position in halves
+  const int wx = (A & 1) ? px : 2 - px, wy = (A >> 1) ? py : 2 - py;
+  return T(wx * wy) * T(0.25);
+}
+
+// rc = P^T r; thread per coarse dof (E, A)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict(int nc, const T* __restrict__ r,
+                                                       T* __restrict__ rc) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t nec = (int64_t)nc * nc;
+  if (i >= 4 * nec) return;
+  const int64_t E = i >> 2;
+  const int A = int(i & 3);
+  const int EX = int(E % nc), EY = int(E / nc);
+  const int nf = 2 * nc;
+  T acc = T(0);
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+    const int64_t e = (int64_t)(2 * EY + (ch >> 1)) * nf + 2 * EX + (ch & 1);
+    T v[4];
+    ld4(r + 4 * e, v);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc += pcoef<T>(ch, a, A) * v[a];
+  }
+  rc[i] = acc;
+}
+
+// z += P ec; thread per fine dof (e, a)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_prolong(int nc, const T* __restrict__ ec,
+                                                      T* __restrict__ z) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int nf = 2 * nc;
+  if (i >= 4 * (int64_t)nf * nf) return;
+  const int64_t e = i >> 2;
+  const int a = int(i & 3);
+  const int ex = int(e % nf), ey = int(e / nf);
+  const int ch = (ex & 1) + 2 * (ey & 1);
+  const int64_t E = (int64_t)(ey >> 1) * nc + (ex >> 1);
+  T v[4];
+  ld4(ec + 4 * E, v);
+  T acc = T(0);
+#pragma unroll
+  for (int A = 0; A < 4; ++A) acc += pcoef<T>(ch, a, A) * v[A];
+  z[i] = z[i] + acc;
+}
+
+// z = L_1^{-1} f with the FP64 inverse; one wavefront per row.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_coarse(const double* __restrict__ inv,
+                                                     const T* __restrict__ f, T* __restrict__ z) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= 1024) return;
+  const double* ir = inv + (int64_t)row * 1024;
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int j = lane + 64 * m;
+    acc += ir[j] * static_cast<double>(f[j]);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) z[row] = static_cast<T>(acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill(int64_t n, T v, T* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const T* __restrict__ x,
+                                                   T* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+}  // namespace
+
+// ============================================================ launchers
+hipError_t launch_astar(int mode, const double2* A, const int32_t* cols, const double* M1, int ne,
+                        double dt, double inv_nu, const double* x, const double* p_old,
+                        const double* b, const Scalars* sc, double* p_new, double* w, double* s,
+                        double* part, hipStream_t st) {
+  const int grid = grid_for(ne, 16, kPartStride);
+  switch (mode) {
+    case kAstarPlain:
+      k_astar<kAstarPlain><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b, sc,
+                                                      p_new, w, s, part);
+      break;
+    case kAstarDir:
+      k_astar<kAstarDir><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b, sc,
+                                                    p_new, w, s, part);
+      break;
+    case kAstarFirst:
+      k_astar<kAstarFirst><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b, sc,
+                                                      p_new, w, s, part);
+      break;
+    case kAstarResidual:
+      k_astar<kAstarResidual><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b,
+                                                         sc, p_new, w, s, part);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int astar_blocks(int ne) { return grid_for(ne, 16, kPartStride); }
+
+hipError_t launch_deflate(bool prologue, const double2* AZ, const int32_t* cols, int ne, double c,
+                          const double* z, const double* w, const double* p, double* q,
+                          double* p_out, double* part, hipStream_t st) {
+  const int grid = grid_for(ne, 16, kPartStride);
+  if (prologue)
+    k_deflate<true><<<grid, kThreads, 0, st>>>(AZ, cols, ne, c, z, w, p, q, p_out, part);
+  else
+    k_deflate<false><<<grid, kThreads, 0, st>>>(AZ, cols, ne, c, z, w, p, q, p_out, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_adivz(const double2* AZ, const int32_t* cols, int ne, const double* y, double* out,
+                        hipStream_t st) {
+  k_adivz<<<grid_for(ne, 16, 1 << 30), kThreads, 0, st>>>(AZ, cols, ne, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(bool flexible, int64_t nvec, const Scalars* sc, const double* p,
+                            const double* q, double* x, double* r, double* part, int* nblocks,
+                            hipStream_t st) {
+  const int grid = grid_for(nvec, kThreads * 4, 8192);
+  *nblocks = grid;
+  if (flexible)
+    k_cg_update<true><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part);
+  else
+    k_cg_update<false><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dot(int64_t nvec, double a, const double* q, double* r, double* part,
+                           int* nblocks, hipStream_t st) {
+  const int grid = grid_for(nvec, kThreads * 4, 8192);
+  *nblocks = grid;
+  k_axpy_dot<<<grid, kThreads, 0, st>>>(nvec, a, q, r, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st) {
+  k_reduce<<<1, kThreads, 0, st>>>(part, nblocks, op, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_zt(int ne, const double* w, double* s, hipStream_t st) {
+  k_zt<<<grid_for(4 * (int64_t)ne, kThreads, 1 << 30), kThreads, 0, st>>>(ne, w, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_z(int ne, const double* y, double scale, double* v, hipStream_t st) {
+  k_z<<<grid_for(16 * (int64_t)ne, kThreads, 1 << 30), kThreads, 0, st>>>(ne, y, scale, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const double* zb, double c,
+                              double* x, hipStream_t st) {
+  k_reconstruct<<<grid_for(16 * (int64_t)ne, kThreads, 1 << 30), kThreads, 0, st>>>(ne, xh, zt, zb,
+                                                                                   c, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int64_t n, double c, const double* in, double* out, hipStream_t st) {
+  k_scale<<<grid_for(n, kThreads, 1 << 30), kThreads, 0, st>>>(n, c, in, out);
+  return hipGetLastError();
+}
+
+int refine_blocks(int ne) { return grid_for(ne, 64, kPartStride); }
+
+template <typename T>
+hipError_t launch_refine_residual(bool first, const double* L64, const int32_t* cols, int ne,
+                                  const double* s, const double* z, T* fJ, double* part,
+                                  hipStream_t st) {
+  const int grid = refine_blocks(ne);
+  if (first)
+    k_refine_residual<T, true><<<grid, kThreads, 0, st>>>(L64, cols, ne, s, z, fJ, part);
+  else
+    k_refine_residual<T, false><<<grid, kThreads, 0, st>>>(L64, cols, ne, s, z, fJ, part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_refine_update(bool first, int64_t m, const T* zJ, double* z, hipStream_t st) {
+  const int grid = grid_for(m, kThreads, 1 << 30);
+  if (first)
+    k_refine_update<T, true><<<grid, kThreads, 0, st>>>(m, zJ, z);
+  else
+    k_refine_update<T, false><<<grid, kThreads, 0, st>>>(m, zJ, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lap(bool residual, const T* L, const int32_t* cols, int ne, const T* f, const T* z,
+                      T* out, hipStream_t st) {
+  const int grid = grid_for(ne, 64, 1 << 30);
+  if (residual)
+    k_lap<T, true><<<grid, kThreads, 0, st>>>(L, cols, ne, f, z, out);
+  else
+    k_lap<T, false><<<grid, kThreads, 0, st>>>(L, cols, ne, f, z, out);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_ras_tiles<float>(const float* F, const int32_t* te, int tiles, const float* r,
+                                   float* Y, hipStream_t st) {
+  k_ras_tiles_f32<<<grid_for(tiles, 4, 1 << 30), kThreads, 0, st>>>(F, te, tiles, r, Y);
+  return hipGetLastError();
+}
+template <>
+hipError_t launch_ras_tiles<double>(const double* F, const int32_t* te, int tiles, const double* r,
+                                    double* Y, hipStream_t st) {
+  k_ras_tiles_f64<<<grid_for(tiles, 4, 1 << 30), kThreads, 0, st>>>(F, te, tiles, r, Y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ras_update(bool zero, const int32_t* cover, int ne, const T* Y, T* z,
+                             hipStream_t st) {
+  const int grid = grid_for(4 * (int64_t)ne, kThreads, 1 << 30);
+  if (zero)
+    k_ras_update<T, true><<<grid, kThreads, 0, st>>>(cover, ne, Y, z);
+  else
+    k_ras_update<T, false><<<grid, kThreads, 0, st>>>(cover, ne, Y, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(int nc, const T* r, T* rc, hipStream_t st) {
+  k_restrict<T><<<grid_for(4 * (int64_t)nc * nc, kThreads, 1 << 30), kThreads, 0, st>>>(nc, r, rc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(int nc, const T* ec, T* z, hipStream_t st) {
+  k_prolong<T><<<grid_for(16 * (int64_t)nc * nc, kThreads, 1 << 30), kThreads, 0, st>>>(nc, ec, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse(const double* inv, const T* f, T* z, hipStream_t st) {
+  k_coarse<T><<<256, kThreads, 0, st>>>(inv, f, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(int64_t n, T v, T* x, hipStream_t st) {
+  k_fill<T><<<grid_for(n, kThreads, 1 << 30), kThreads, 0, st>>>(n, v, x);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st) {
+  k_copy<T><<<grid_for(n, kThreads, 1 << 30), kThreads, 0, st>>>(n, x, y);
+  return hipGetLastError();
+}
+
+#define DCG_INSTANTIATE(T)                                                                      \
+  template hipError_t launch_refine_residual<T>(bool, const double*, const int32_t*, int,      \
+                                                const double*, const double*, T*, double*,     \
+                                                hipStream_t);                                  \
+  template hipError_t launch_refine_update<T>(bool, int64_t, const T*, double*, hipStream_t);  \
+  template hipError_t launch_lap<T>(bool, const T*, const int32_t*, int, const T*, const T*, T*, \
+                                    hipStream_t);                                              \
+  template hipError_t launch_ras_update<T>(bool, const int32_t*, int, const T*, T*, hipStream_t); \
+  template hipError_t launch_restrict<T>(int, const T*, T*, hipStream_t);                      \
+  template hipError_t launch_prolong<T>(int, const T*, T*, hipStream_t);                       \
+  template hipError_t launch_coarse<T>(const double*, const T*, T*, hipStream_t);              \
+  template hipError_t launch_fill<T>(int64_t, T, T*, hipStream_t);                             \
+  template hipError_t launch_copy<T>(int64_t, const T*, T*, hipStream_t);
+
+DCG_INSTANTIATE(float)
+DCG_INSTANTIATE(double)
+
+}  // namespace dcg

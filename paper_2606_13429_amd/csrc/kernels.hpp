@@ -1,0 +1,120 @@
+// Launchers of the gfx950 kernels of the deflated-CG hot path.  Every
+// launcher enqueues on ``st`` and returns hipGetLastError() of the launch.
+//
+// Device layouts (Ne = squares of the level, all indices int32 except where
+// a product can exceed 2^31):
+//   tensor vectors   [16 e + 4 c + j]                 (FP64)
+//   scalar vectors   [4 e + j]                        (FP64 or level real T)
+//   A_div            double2 [slot][kc=8][Ne][row=16]  row r, columns 2kc, 2kc+1
+//   A_div Z          double2 [slot][kc=2][Ne][row=16]
+//   M_1              double  [Ne][16]
+//   L_k              T       [slot][Ne][row=4][4]
+//   cols             int32   [slot][Ne]               -1 = none
+//   RAS factors      T       [tile][j=128][i=128]     F[j][i] = (L_k)_i^{-1}[j][i] d_i
+//   tile squares     int32   [tile][32]
+//   cover            int32   [Ne][3]                  tile * 32 + slot, -1 = none
+//   coarsest inverse double  [1024][1024]
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dcg {
+
+// Device-resident scalars of one solve (read by the update kernels).
+struct Scalars {
+  double b2;        // ||b||^2
+  double rho;       // (r, r)
+  double pq;        // (p, q)
+  double alpha, beta;
+  double dr;        // (d, r) of the flexible variant
+  double res2;      // ||b - A* x||^2 or the last plain dot
+  double s2, r2;    // inner iteration: ||s||^2 and ||s - L z||^2
+  double spare[7];
+  int32_t breakdown;
+  int32_t pad[3];
+};
+
+enum ReduceOp : int {
+  kRedB2Rho = 0,     // slots (b,b), (r,r)          -> b2, rho
+  kRedAlpha = 1,     // slot (p,q)                  -> pq, alpha = rho / pq
+  kRedBeta = 2,      // slot (r,r)                  -> beta = rho'/rho, rho = rho'
+  kRedS2 = 3,        // slot ||r||^2 of the inner   -> s2 = r2 = sum
+  kRedR2 = 4,        // slot ||r||^2 of the inner   -> r2
+  kRedRes = 5,       // slot (v,v)                  -> res2
+  kRedFcgAlpha = 6,  // slot (d,q)                  -> pq, alpha = dr / pq
+  kRedFcgBeta = 7,   // slots (r,r),(r,q),(d,r)     -> rho, beta = -(r,q)/pq, dr
+  kRedRho = 8        // slot (r,r)                  -> rho (and dr = rho)
+};
+
+constexpr int kPartStride = 1 << 16;   // max blocks of a reducing launch
+
+enum AstarMode : int {
+  kAstarPlain = 0,   // w = A* x
+  kAstarDir = 1,     // u = x + beta p_old, p_new = u, w = A* u
+  kAstarFirst = 2,   // u = x, p_new = u, w = A* u
+  kAstarResidual = 3 // w = b - A* x, partial (w, w)
+};
+
+// workgroups (= partial sums) of the reducing launches for ``ne`` squares
+int astar_blocks(int ne);     // launch_astar and launch_deflate
+int refine_blocks(int ne);    // launch_refine_residual
+
+hipError_t launch_astar(int mode, const double2* A, const int32_t* cols, const double* M1, int ne,
+                        double dt, double inv_nu, const double* x, const double* p_old,
+                        const double* b, const Scalars* sc, double* p_new, double* w, double* s,
+                        double* part, hipStream_t st);
+// q = w - c * (A_div Z) z ; partial (p, q).  With ``prologue``: r = w - c AZ z
+// written to q and to p_out, partials (w, w) and (q, q).
+hipError_t launch_deflate(bool prologue, const double2* AZ, const int32_t* cols, int ne, double c,
+                          const double* z, const double* w, const double* p, double* q,
+                          double* p_out, double* part, hipStream_t st);
+// q = AZ y (plain product, no partials)
+hipError_t launch_adivz(const double2* AZ, const int32_t* cols, int ne, const double* y, double* out,
+                        hipStream_t st);
+// x += alpha p ; r -= alpha q ; partial (r, r)  [flexible: + (r,q), (p,r)]
+hipError_t launch_cg_update(bool flexible, int64_t nvec, const Scalars* sc, const double* p,
+                            const double* q, double* x, double* r, double* part, int* nblocks,
+                            hipStream_t st);
+// r += a q ; partial (r, r)
+hipError_t launch_axpy_dot(int64_t nvec, double a, const double* q, double* r, double* part,
+                           int* nblocks, hipStream_t st);
+hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st);
+
+hipError_t launch_zt(int ne, const double* w, double* s, hipStream_t st);
+hipError_t launch_z(int ne, const double* y, double scale, double* v, hipStream_t st);
+// x = (xh - Z (c zt)) + Z (c zb)
+hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const double* zb, double c,
+                              double* x, hipStream_t st);
+hipError_t launch_scale(int64_t n, double c, const double* in, double* out, hipStream_t st);
+
+// inner refinement (FP64 residual of the level-J Laplacian)
+template <typename T>
+hipError_t launch_refine_residual(bool first, const double* L64, const int32_t* cols, int ne,
+                                  const double* s, const double* z, T* fJ, double* part,
+                                  hipStream_t st);
+template <typename T>
+hipError_t launch_refine_update(bool first, int64_t m, const T* zJ, double* z, hipStream_t st);
+
+// multigrid level kernels
+template <typename T>
+hipError_t launch_lap(bool residual, const T* L, const int32_t* cols, int ne, const T* f, const T* z,
+                      T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_ras_tiles(const T* F, const int32_t* tile_elems, int tiles, const T* r, T* Y,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_ras_update(bool zero, const int32_t* cover, int ne, const T* Y, T* z,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(int nc, const T* r, T* rc, hipStream_t st);
+template <typename T>
+hipError_t launch_prolong(int nc, const T* ec, T* z, hipStream_t st);
+template <typename T>
+hipError_t launch_coarse(const double* inv, const T* f, T* z, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(int64_t n, T v, T* x, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st);
+
+}  // namespace dcg

@@ -1,0 +1,118 @@
+// Device-side mesh contexts, solver workspaces and handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dcg.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+namespace dcg {
+
+// Error carrying a dcg_status; thrown inside the library, converted to a
+// status at the C ABI.
+struct Error : std::runtime_error {
+  dcg_status status;
+  Error(dcg_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+void hip_check(hipError_t e, const char* what);
+#define DCG_HIP(expr) ::dcg::hip_check((expr), #expr)
+
+// One multigrid level on the device.
+struct DeviceLevel {
+  int n = 0, ne = 0;
+  int32_t* cols = nullptr;        // [5][ne]
+  double* L64 = nullptr;          // [5][ne][4][4]
+  float* L32 = nullptr;
+  int tiles = 0;                  // levels >= 2
+  int32_t* tile_elems = nullptr;  // [tiles][32]
+  int32_t* cover = nullptr;       // [ne][3]
+  float* F32 = nullptr;           // [tiles][128][128]
+  double* F64 = nullptr;
+};
+
+// Dt-independent operators of one mesh on one device; shared by handles and
+// by the serving engine (reference counted through shared_ptr).
+struct MeshContext {
+  int device = 0;
+  int n = 0, J = 0, ne = 0;
+  double penalty = 10.0;
+  double2* Adiv = nullptr;        // [5][8][ne][16]
+  double2* AdivZ = nullptr;       // [5][2][ne][16]
+  double* M1 = nullptr;           // [ne][16]
+  int32_t* cols = nullptr;        // [5][ne]
+  std::vector<DeviceLevel> lv;    // lv[k - 1]
+  double* coarse_inv = nullptr;   // [1024][1024]
+  size_t bytes = 0;
+  double t_build_ms = 0.0;
+  std::mutex mu;                  // guards lazy factor uploads
+  std::unique_ptr<HostContext> host;   // kept until both factor precisions exist
+  bool have_f32 = false, have_f64 = false;
+
+  ~MeshContext();
+  void ensure_factors(bool fp32);   // uploads L_k and tile inverses of that precision
+  void* alloc(size_t bytes);
+  std::vector<void*> allocations;
+};
+
+// Returns the cached context of (current device, n, penalty), building and
+// uploading it on first use.
+std::shared_ptr<MeshContext> get_context(int n, double penalty, bool fp32);
+void clear_context_cache();
+
+// Per-handle device workspace, sized for one mesh and one precision.
+struct Workspace {
+  int ne = 0;
+  size_t bytes = 0;
+  std::vector<void*> allocations;
+  double *xh = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *w = nullptr, *q = nullptr;
+  double *s = nullptr, *zref = nullptr, *zb = nullptr, *zt = nullptr;
+  double* part = nullptr;                 // [3][kPartStride]
+  Scalars* sc = nullptr;                  // device
+  Scalars* sc_host = nullptr;             // pinned host mirror
+  // level buffers (level real type), index k - 1
+  std::vector<void*> f, z, rr, Y;
+  void* alloc(size_t bytes);
+  void release();
+  ~Workspace();
+};
+
+}  // namespace dcg
+
+// Solver handle (the opaque dcg_handle of the C ABI).
+struct dcg_ctx {
+  std::shared_ptr<dcg::MeshContext> mesh;
+  dcg_mesh mp{};
+  dcg_options opt{};
+  double dt = 0.0, nu = 1.0;
+  bool fp32 = true;
+  dcg::Workspace ws;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t wgraph = nullptr;        // W-cycle on the finest level
+  std::string last_error;
+  double t_setup_ms = 0.0;
+  int device = 0;
+  // live timing of the finest-level RAS tile kernel
+  static constexpr int kMaxTimed = 32;
+  bool ktime = false;
+  hipEvent_t kev[2 * kMaxTimed] = {};
+  int krec = 0;                 // event pairs recorded by the current cycle
+  double ktime_ms = 0.0;
+  int64_t klaunches = 0;
+  ~dcg_ctx();
+};
+
+namespace dcg {
+void handle_init(dcg_ctx* h);             // allocates the workspace
+dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* st,
+                 hipStream_t stream);
+void kernel_timing(dcg_ctx* h, bool enable);
+dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* in2, void* out,
+                 hipStream_t stream);
+}  // namespace dcg

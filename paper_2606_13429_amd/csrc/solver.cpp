@@ -1,0 +1,470 @@
+// Solver driver: the deflated-CG outer iteration (Algorithm 2), the inner
+// Multigrid iteration (Algorithm 3) as FP64 iterative refinement around
+// W-cycles (Algorithm 4) of the level real type, and the operator-level
+// entry points.  All arithmetic runs in the kernels of kernels.hip; the host
+// only enqueues launches and reads the device scalar block at the
+// convergence tests.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "runtime.hpp"
+
+namespace dcg {
+
+void* Workspace::alloc(size_t b) {
+  void* p = nullptr;
+  DCG_HIP(hipMalloc(&p, b));
+  allocations.push_back(p);
+  bytes += b;
+  return p;
+}
+
+void Workspace::release() {
+  for (void* p : allocations) (void)hipFree(p);
+  allocations.clear();
+  if (sc_host) (void)hipHostFree(sc_host);
+  sc_host = nullptr;
+}
+
+Workspace::~Workspace() { release(); }
+
+}  // namespace dcg
+
+dcg_ctx::~dcg_ctx() {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  if (wgraph) (void)hipGraphExecDestroy(wgraph);
+  for (hipEvent_t& e : kev)
+    if (e) (void)hipEventDestroy(e);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  ws.release();
+  (void)hipSetDevice(cur);
+}
+
+namespace dcg {
+namespace {
+
+constexpr double kTwo = 2.0;   // Z^T A* Z = (dt/2) L  =>  A* Z (2/dt) = 2 A_div Z
+constexpr double kApplyTol = 1e-8;   // outer tolerance assumed by DCG_OP_INNER / DEFLATED
+
+size_t real_size(bool fp32) { return fp32 ? sizeof(float) : sizeof(double); }
+
+template <typename T>
+T* lvbuf(std::vector<void*>& v, int k) {
+  return static_cast<T*>(v[k - 1]);
+}
+
+template <typename T>
+const T* level_L(const DeviceLevel& d);
+template <>
+const float* level_L<float>(const DeviceLevel& d) { return d.L32; }
+template <>
+const double* level_L<double>(const DeviceLevel& d) { return d.L64; }
+template <typename T>
+const T* level_F(const DeviceLevel& d);
+template <>
+const float* level_F<float>(const DeviceLevel& d) { return d.F32; }
+template <>
+const double* level_F<double>(const DeviceLevel& d) { return d.F64; }
+
+// ------------------------------------------------------------ W-cycle
+// One RAS smoothing step z <- z + S_k (f - L_k z); ``zero`` means z = 0 on
+// entry, in which case the residual is f itself.
+template <typename T>
+void ras_sweep(dcg_ctx* h, int k, bool zero, hipStream_t st) {
+  const DeviceLevel& d = h->mesh->lv[k - 1];
+  T* f = lvbuf<T>(h->ws.f, k);
+  T* z = lvbuf<T>(h->ws.z, k);
+  T* r = lvbuf<T>(h->ws.rr, k);
+  T* Y = lvbuf<T>(h->ws.Y, k);
+  if (!zero) DCG_HIP(launch_lap<T>(true, level_L<T>(d), d.cols, d.ne, f, z, r, st));
+  const bool timed = h->ktime && k == h->mesh->J && h->krec < dcg_ctx::kMaxTimed;
+  if (timed) DCG_HIP(hipEventRecord(h->kev[2 * h->krec], st));
+  DCG_HIP(launch_ras_tiles<T>(level_F<T>(d), d.tile_elems, d.tiles, zero ? f : r, Y, st));
+  if (timed) DCG_HIP(hipEventRecord(h->kev[2 * h->krec++ + 1], st));
+  DCG_HIP(launch_ras_update<T>(zero, d.cover, d.ne, Y, z, st));
+}
+
+// z_k = Wcycle_k(f_k, z_k) (Algorithm 4); ``zero``: the initial guess is 0.
+template <typename T>
+void wcycle(dcg_ctx* h, int k, bool zero, hipStream_t st) {
+  MeshContext& m = *h->mesh;
+  if (k == 1) {   // exact coarsest solve; the initial guess is irrelevant
+    DCG_HIP(launch_coarse<T>(m.coarse_inv, lvbuf<T>(h->ws.f, 1), lvbuf<T>(h->ws.z, 1), st));
+    return;
+  }
+  const DeviceLevel& d = m.lv[k - 1];
+  T* f = lvbuf<T>(h->ws.f, k);
+  T* z = lvbuf<T>(h->ws.z, k);
+  T* r = lvbuf<T>(h->ws.rr, k);
+  const int pre = h->mp.pre, post = h->mp.post;
+  if (zero && pre == 0) DCG_HIP(launch_fill<T>(4 * int64_t(d.ne), T(0), z, st));
+  for (int i = 0; i < pre; ++i) ras_sweep<T>(h, k, zero && i == 0, st);
+  // coarse-grid correction: r_{k-1} = P^T (f - L z)
+  DCG_HIP(launch_lap<T>(true, level_L<T>(d), d.cols, d.ne, f, z, r, st));
+  DCG_HIP(launch_restrict<T>(d.n / 2, r, lvbuf<T>(h->ws.f, k - 1), st));
+  wcycle<T>(h, k - 1, true, st);
+  // second coarse call from e_bar; on level 1 it returns the same exact
+  // solve, so it is skipped there
+  if (k - 1 >= 2) wcycle<T>(h, k - 1, false, st);
+  DCG_HIP(launch_prolong<T>(d.n / 2, lvbuf<T>(h->ws.z, k - 1), z, st));
+  for (int i = 0; i < post; ++i) ras_sweep<T>(h, k, false, st);
+}
+
+// Adds the elapsed times of the event pairs recorded by the last W-cycle
+// (called after the stream has been synchronised).
+void collect_kernel_times(dcg_ctx* h) {
+  if (!h->ktime) return;
+  for (int i = 0; i < h->krec; ++i) {
+    float ms = 0.f;
+    DCG_HIP(hipEventElapsedTime(&ms, h->kev[2 * i], h->kev[2 * i + 1]));
+    h->ktime_ms += ms;
+    ++h->klaunches;
+  }
+}
+
+template <typename T>
+void run_wcycle_finest(dcg_ctx* h, hipStream_t st) {
+  if (h->opt.use_graph && h->mesh->J >= 2) {
+    if (!h->wgraph) {
+      h->krec = 0;
+      hipGraph_t g = nullptr;
+      DCG_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        wcycle<T>(h, h->mesh->J, true, h->capture_stream);
+      } catch (...) {
+        (void)hipStreamEndCapture(h->capture_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      DCG_HIP(hipStreamEndCapture(h->capture_stream, &g));
+      const hipError_t e = hipGraphInstantiate(&h->wgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      DCG_HIP(e);
+    }
+    DCG_HIP(hipGraphLaunch(h->wgraph, st));   // replays the captured event pairs too
+  } else {
+    h->krec = 0;
+    wcycle<T>(h, h->mesh->J, true, st);
+  }
+}
+
+void read_scalars(dcg_ctx* h, hipStream_t st) {
+  DCG_HIP(hipMemcpyAsync(h->ws.sc_host, h->ws.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+  DCG_HIP(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------ inner solve
+// z ~= L^{-1} s (FP64) by the Multigrid iteration (Algorithm 3): W-cycles
+// while ||s - L z|| / ||s|| > tol_c and fewer than max_inner cycles.  Each
+// cycle is applied to the current FP64 residual and added in FP64, which for
+// a linear cycle equals Wcycle(s, z) (iterative refinement form).  Returns
+// the number of W-cycles.
+template <typename T>
+int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
+  MeshContext& m = *h->mesh;
+  const DeviceLevel& fine = m.lv[m.J - 1];
+  const int64_t mlen = 4 * int64_t(fine.ne);
+  T* fJ = lvbuf<T>(h->ws.f, m.J);
+  T* zJ = lvbuf<T>(h->ws.z, m.J);
+  const int nb = refine_blocks(fine.ne);
+  DCG_HIP(launch_refine_residual<T>(true, fine.L64, fine.cols, fine.ne, s, nullptr, fJ, h->ws.part, st));
+  DCG_HIP(launch_reduce(h->ws.part, nb, kRedS2, h->ws.sc, st));
+  read_scalars(h, st);
+  const double s2 = h->ws.sc_host->s2;
+  if (!std::isfinite(s2)) throw Error(DCG_EINVAL, "non-finite inner right-hand side");
+  int cycles = 0;
+  if (s2 > 0.0) {
+    double r2 = s2;
+    const double lim = tol_c * tol_c * s2;
+    while (cycles < h->opt.max_inner && r2 > lim) {
+      run_wcycle_finest<T>(h, st);
+      DCG_HIP(launch_refine_update<T>(cycles == 0, mlen, zJ, z, st));
+      DCG_HIP(launch_refine_residual<T>(false, fine.L64, fine.cols, fine.ne, s, z, fJ, h->ws.part, st));
+      DCG_HIP(launch_reduce(h->ws.part, nb, kRedR2, h->ws.sc, st));
+      read_scalars(h, st);
+      collect_kernel_times(h);
+      r2 = h->ws.sc_host->r2;
+      ++cycles;
+      if (!std::isfinite(r2)) throw Error(DCG_EBREAKDOWN, "non-finite inner residual");
+    }
+  }
+  if (cycles == 0) DCG_HIP(launch_fill<double>(mlen, 0.0, z, st));
+  return cycles;
+}
+
+int inner(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
+  return h->fp32 ? inner_solve<float>(h, s, z, tol_c, st) : inner_solve<double>(h, s, z, tol_c, st);
+}
+
+void check_ptr(const void* p, const char* what) {
+  if (!p) throw Error(DCG_EINVAL, std::string(what) + " is NULL");
+}
+
+}  // namespace
+
+void handle_init(dcg_ctx* h) {
+  MeshContext& m = *h->mesh;
+  Workspace& ws = h->ws;
+  ws.ne = m.ne;
+  const int64_t N = 16 * int64_t(m.ne), M = 4 * int64_t(m.ne);
+  double** vecs[] = {&ws.xh, &ws.r, &ws.p[0], &ws.p[1], &ws.w, &ws.q};
+  for (double** v : vecs) *v = static_cast<double*>(ws.alloc(sizeof(double) * N));
+  double** svecs[] = {&ws.s, &ws.zref, &ws.zb, &ws.zt};
+  for (double** v : svecs) *v = static_cast<double*>(ws.alloc(sizeof(double) * M));
+  ws.part = static_cast<double*>(ws.alloc(sizeof(double) * 3 * kPartStride));
+  ws.sc = static_cast<Scalars*>(ws.alloc(sizeof(Scalars)));
+  DCG_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.sc_host), sizeof(Scalars), hipHostMallocDefault));
+  std::memset(ws.sc_host, 0, sizeof(Scalars));
+  DCG_HIP(hipMemcpy(ws.sc, ws.sc_host, sizeof(Scalars), hipMemcpyHostToDevice));
+  const size_t rs = real_size(h->fp32);
+  ws.f.assign(m.J, nullptr);
+  ws.z.assign(m.J, nullptr);
+  ws.rr.assign(m.J, nullptr);
+  ws.Y.assign(m.J, nullptr);
+  for (int k = 1; k <= m.J; ++k) {
+    const DeviceLevel& d = m.lv[k - 1];
+    ws.f[k - 1] = ws.alloc(rs * 4 * d.ne);
+    ws.z[k - 1] = ws.alloc(rs * 4 * d.ne);
+    ws.rr[k - 1] = ws.alloc(rs * 4 * d.ne);
+    if (k >= 2) ws.Y[k - 1] = ws.alloc(rs * 128 * size_t(d.tiles));
+  }
+  DCG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+}
+
+// ------------------------------------------------------------ solve
+dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* st,
+                 hipStream_t stream) {
+  check_ptr(b, "b");
+  check_ptr(x, "x");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) throw Error(DCG_EINVAL, "tol must be finite and >= 0");
+  const auto t0 = std::chrono::steady_clock::now();
+  MeshContext& m = *h->mesh;
+  Workspace& ws = h->ws;
+  const int ne = m.ne;
+  const int64_t N = 16 * int64_t(ne);
+  const bool flex = h->opt.outer == DCG_OUTER_FCG1;
+  const double tol_c = h->opt.c_F * tol;
+  const double c_recon = 2.0 / h->dt;
+  const double inv_nu = 1.0 / h->nu;
+  const int nbA = astar_blocks(ne);
+  dcg_stats stats{};
+  int cycles_total = 0, inner_solves = 0, cycles_outer = 0;
+  DCG_HIP(hipMemsetAsync(ws.sc, 0, sizeof(Scalars), stream));
+
+  // prologue: pi(b) = Z E^{-1} Z^T b; f_D = b - A* pi(b) (eq. (defl_sys))
+  DCG_HIP(launch_zt(ne, b, ws.s, stream));
+  cycles_total += inner(h, ws.s, ws.zb, tol_c, stream);
+  ++inner_solves;
+  DCG_HIP(launch_deflate(true, m.AdivZ, m.cols, ne, kTwo, ws.zb, b, nullptr, ws.r, ws.p[0], ws.part,
+                         stream));
+  DCG_HIP(launch_reduce(ws.part, nbA, kRedB2Rho, ws.sc, stream));
+  read_scalars(h, stream);
+  const double b2 = ws.sc_host->b2;
+  if (!std::isfinite(b2) || !std::isfinite(ws.sc_host->rho))
+    throw Error(DCG_EINVAL, "b contains NaN or Inf");
+  if (b2 == 0.0) {
+    DCG_HIP(launch_fill<double>(N, 0.0, x, stream));
+    DCG_HIP(hipStreamSynchronize(stream));
+    stats.status = DCG_OK;
+    stats.inner_solves = inner_solves;
+    stats.t_setup_ms = h->t_setup_ms;
+    stats.t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = stats;
+    return DCG_OK;
+  }
+  if (h->opt.x0_given) {
+    // x_hat_0 = x_0, r_0 = f_D - M_D x_0 with M_D x_0 = A* x_0 - A* Z y_0,
+    // y_0 = E^{-1} Z^T A* x_0 (Algorithm 1 applied to the deflated system)
+    DCG_HIP(launch_copy<double>(N, x, ws.xh, stream));
+    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu, ws.xh, nullptr, nullptr,
+                         ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
+    cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
+    ++inner_solves;
+    DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zt, ws.w, ws.w, ws.q, nullptr,
+                           ws.part, stream));
+    int nbu = 0;
+    DCG_HIP(launch_axpy_dot(N, -1.0, ws.q, ws.r, ws.part, &nbu, stream));
+    DCG_HIP(launch_reduce(ws.part, nbu, kRedRho, ws.sc, stream));
+    read_scalars(h, stream);
+  } else {
+    DCG_HIP(launch_fill<double>(N, 0.0, ws.xh, stream));
+  }
+
+  const double lim = tol * tol * b2;
+  double rho = ws.sc_host->rho;
+  int it = 0, pidx = 0;
+  dcg_status status = DCG_OK;
+  while (true) {
+    if (rho <= lim) break;
+    if (it >= h->opt.max_outer) {
+      status = DCG_NOT_CONVERGED;
+      break;
+    }
+    // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
+    DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu,
+                         ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
+                         stream));
+    pidx = 1 - pidx;
+    const int c = inner(h, ws.s, ws.zref, tol_c, stream);
+    cycles_total += c;
+    cycles_outer += c;
+    ++inner_solves;
+    // q = w - A* Z y = M_D p  (y = (2/dt) z)
+    DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zref, ws.w, ws.p[pidx], ws.q, nullptr,
+                           ws.part, stream));
+    DCG_HIP(launch_reduce(ws.part, nbA, flex ? kRedFcgAlpha : kRedAlpha, ws.sc, stream));
+    int nbu = 0;
+    DCG_HIP(launch_cg_update(flex, N, ws.sc, ws.p[pidx], ws.q, ws.xh, ws.r, ws.part, &nbu, stream));
+    DCG_HIP(launch_reduce(ws.part, nbu, flex ? kRedFcgBeta : kRedBeta, ws.sc, stream));
+    ++it;
+    read_scalars(h, stream);
+    if (ws.sc_host->breakdown) {
+      status = DCG_EBREAKDOWN;
+      break;
+    }
+    rho = ws.sc_host->rho;
+    if (!std::isfinite(rho)) {
+      status = DCG_EBREAKDOWN;
+      break;
+    }
+  }
+  stats.rel_res_recurrence = std::sqrt(std::max(rho, 0.0) / b2);
+
+  // epilogue: x = (x_hat - pi(A* x_hat)) + pi(b)  (eq. (x_defl))
+  DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu, ws.xh, nullptr, nullptr,
+                       ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
+  cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
+  ++inner_solves;
+  DCG_HIP(launch_reconstruct(ne, ws.xh, ws.zt, ws.zb, c_recon, x, stream));
+  DCG_HIP(launch_astar(kAstarResidual, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu, x, nullptr, b, ws.sc,
+                       nullptr, ws.w, nullptr, ws.part, stream));
+  DCG_HIP(launch_reduce(ws.part, nbA, kRedRes, ws.sc, stream));
+  read_scalars(h, stream);
+  stats.rel_res_true = std::sqrt(ws.sc_host->res2 / b2);
+  stats.status = status;
+  stats.outer_iters = it;
+  stats.total_wcycles = cycles_total;
+  stats.inner_solves = inner_solves;
+  stats.inner_per_outer = it > 0 ? double(cycles_outer) / it : 0.0;
+  stats.t_setup_ms = h->t_setup_ms;
+  stats.t_solve_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = stats;
+  if (status == DCG_EBREAKDOWN) throw Error(DCG_EBREAKDOWN, "outer iteration broke down ((p, q) <= 0 or non-finite)");
+  return status;
+}
+
+void kernel_timing(dcg_ctx* h, bool enable) {
+  if (enable && !h->kev[0])
+    for (hipEvent_t& e : h->kev) DCG_HIP(hipEventCreate(&e));
+  if (h->wgraph) {
+    DCG_HIP(hipGraphExecDestroy(h->wgraph));
+    h->wgraph = nullptr;
+  }
+  h->ktime = enable;
+  h->krec = 0;
+  h->ktime_ms = 0.0;
+  h->klaunches = 0;
+}
+
+// ------------------------------------------------------------ apply
+namespace {
+
+template <typename T>
+void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, void* out,
+                 hipStream_t st) {
+  MeshContext& m = *h->mesh;
+  if (k < 1 || k > m.J) throw Error(DCG_EINVAL, "level out of range");
+  const DeviceLevel& d = m.lv[k - 1];
+  const int64_t mk = 4 * int64_t(d.ne);
+  const T* x = static_cast<const T*>(in);
+  T* y = static_cast<T*>(out);
+  switch (op) {
+    case DCG_OP_LAPLACE:
+      DCG_HIP(launch_lap<T>(false, level_L<T>(d), d.cols, d.ne, nullptr, x, y, st));
+      break;
+    case DCG_OP_RAS: {
+      if (k < 2) throw Error(DCG_EINVAL, "RAS smoother exists on levels >= 2");
+      check_ptr(in2, "in2 (z)");
+      DCG_HIP(launch_copy<T>(mk, x, lvbuf<T>(h->ws.f, k), st));
+      DCG_HIP(launch_copy<T>(mk, static_cast<const T*>(in2), lvbuf<T>(h->ws.z, k), st));
+      ras_sweep<T>(h, k, false, st);
+      DCG_HIP(launch_copy<T>(mk, lvbuf<T>(h->ws.z, k), y, st));
+      break;
+    }
+    case DCG_OP_RESTRICT:
+      if (k < 2) throw Error(DCG_EINVAL, "restriction needs level >= 2");
+      DCG_HIP(launch_restrict<T>(d.n / 2, x, y, st));
+      break;
+    case DCG_OP_PROLONG:
+      if (k < 2) throw Error(DCG_EINVAL, "prolongation needs level >= 2");
+      DCG_HIP(launch_fill<T>(mk, T(0), y, st));
+      DCG_HIP(launch_prolong<T>(d.n / 2, x, y, st));
+      break;
+    case DCG_OP_COARSE:
+      if (k != 1) throw Error(DCG_EINVAL, "coarse solve is on level 1");
+      DCG_HIP(launch_coarse<T>(m.coarse_inv, x, y, st));
+      break;
+    case DCG_OP_WCYCLE:
+      DCG_HIP(launch_copy<T>(mk, x, lvbuf<T>(h->ws.f, k), st));
+      if (in2) DCG_HIP(launch_copy<T>(mk, static_cast<const T*>(in2), lvbuf<T>(h->ws.z, k), st));
+      wcycle<T>(h, k, in2 == nullptr, st);
+      DCG_HIP(launch_copy<T>(mk, lvbuf<T>(h->ws.z, k), y, st));
+      break;
+    default:
+      throw Error(DCG_EINVAL, "unknown level operator");
+  }
+}
+
+}  // namespace
+
+dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* in2, void* out,
+                 hipStream_t st) {
+  check_ptr(in, "in");
+  check_ptr(out, "out");
+  MeshContext& m = *h->mesh;
+  const int ne = m.ne;
+  const double* x = static_cast<const double*>(in);
+  double* y = static_cast<double*>(out);
+  switch (op) {
+    case DCG_OP_ASTAR:
+      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, 1.0 / h->nu, x, nullptr,
+                           nullptr, h->ws.sc, nullptr, y, nullptr, nullptr, st));
+      break;
+    case DCG_OP_ZT:
+      DCG_HIP(launch_zt(ne, x, y, st));
+      break;
+    case DCG_OP_Z:
+      DCG_HIP(launch_z(ne, x, 1.0, y, st));
+      break;
+    case DCG_OP_ADIVZ:
+      DCG_HIP(launch_adivz(m.AdivZ, m.cols, ne, x, y, st));
+      break;
+    case DCG_OP_INNER: {
+      inner(h, x, h->ws.zref, h->opt.c_F * kApplyTol, st);
+      DCG_HIP(launch_scale(4 * int64_t(ne), 2.0 / h->dt, h->ws.zref, y, st));
+      break;
+    }
+    case DCG_OP_DEFLATED: {
+      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, 1.0 / h->nu, x, nullptr,
+                           nullptr, h->ws.sc, nullptr, h->ws.w, h->ws.s, nullptr, st));
+      inner(h, h->ws.s, h->ws.zref, h->opt.c_F * kApplyTol, st);
+      DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, h->ws.zref, h->ws.w, x, y, nullptr,
+                             h->ws.part, st));
+      break;
+    }
+    default:
+      if (h->fp32)
+        apply_level<float>(h, op, level, in, in2, out, st);
+      else
+        apply_level<double>(h, op, level, in, in2, out, st);
+  }
+  DCG_HIP(hipStreamSynchronize(st));
+  return DCG_OK;
+}
+
+}  // namespace dcg

@@ -1,0 +1,145 @@
+"""Solver parity through dcg_solve: the GPU deflated CG against the oracle's
+Algorithm 2 on the same seeded right-hand side.
+
+Gate (spec bar): ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-8 and
+outer iteration counts within +-2, for the FP64 and the mixed form.  Both
+run the same algorithm; the inner solves are accurate to c_F * tol = 1e-10,
+so the two iterate sequences differ only by rounding and by the FP32
+W-cycles of the mixed form, which the FP64 refinement absorbs."""
+import numpy as np
+import pytest
+
+from dcg_workloads import rhs
+from layout import comp_to_elem, elem_to_comp
+from oracle import discretisation as d
+from oracle import krylov as kr
+from oracle import multigrid as mg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lib = pytest.importorskip("paper_2606_13429_amd._binding")
+import paper_2606_13429_amd as dcg  # noqa: E402
+
+_ORACLE = {}
+
+
+def _oracle(n, dt, seed, tol, outer="cg", inner="mg"):
+    key = (n, dt, seed, tol, outer, inner)
+    if key not in _ORACLE:
+        As = d.operator(n, dt)
+        V = d.deflation_basis(n)
+        E = (V.T @ As @ V).tocsr()
+        f = elem_to_comp(rhs(n, seed), n)
+        inn = kr.exact_inner(E) if inner == "exact" or n == 16 else kr.mg_inner(mg.Hierarchy(E, n))
+        kw = dict(outer="fcg", m_max=1) if outer == "fcg1" else {}
+        _ORACLE[key] = kr.dcg(As, V, f, inn, tol=tol, **kw)
+    return _ORACLE[key]
+
+
+def _gpu(n, dt, seed, tol, prec, outer="cg", **kw):
+    s = dcg.Solver(n, dt, prec=prec, outer=outer, **kw)
+    b = torch.from_numpy(rhs(n, seed)).cuda()
+    x = torch.empty_like(b)
+    status, st = s.solve(b, x, tol)
+    torch.cuda.synchronize()
+    return status, st, x.cpu().numpy(), s
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,dt", [(16, 1e-2), (32, 1e-3), (64, 1e-5)])
+def test_solve_matches_oracle(n, dt, prec):
+    ref = _oracle(n, dt, 0, 1e-8)
+    status, st, x, _ = _gpu(n, dt, 0, 1e-8, prec)
+    assert status == lib.DCG_OK
+    assert abs(st.outer_iters - ref.iterations) <= 2, (st.outer_iters, ref.iterations)
+    xr = comp_to_elem(ref.x, n)
+    err = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+    assert err <= 1e-8, err
+    assert st.rel_res_recurrence <= 1e-8
+    assert st.rel_res_true <= 2e-8
+    if n > 16:
+        assert abs(st.inner_per_outer - np.mean(ref.outer_cycles)) <= 1.0
+
+
+def test_solve_matches_dense_solution_at_tight_tolerance():
+    n, dt = 16, 1e-2
+    As = d.operator(n, dt).toarray()
+    xs = comp_to_elem(np.linalg.solve(As, elem_to_comp(rhs(n, 3), n)), n)
+    for prec in ("fp64", "mixed"):
+        status, st, x, _ = _gpu(n, dt, 3, 1e-12, prec)
+        assert status == lib.DCG_OK
+        assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_flexible_outer_matches_oracle_fcg1():
+    n, dt = 32, 1e-4
+    ref = _oracle(n, dt, 1, 1e-8, outer="fcg1")
+    status, st, x, _ = _gpu(n, dt, 1, 1e-8, "mixed", outer="fcg1")
+    assert status == lib.DCG_OK and abs(st.outer_iters - ref.iterations) <= 2
+    xr = comp_to_elem(ref.x, n)
+    assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+def test_iteration_counts_do_not_grow_as_dt_falls():
+    n = 32
+    counts = [_gpu(n, dt, 0, 1e-8, "mixed")[1].outer_iters for dt in (1e-4, 1e-6, 1e-8)]
+    assert counts[0] >= counts[1] >= counts[2] - 1
+
+
+def test_zero_rhs_returns_zero():
+    n = 32
+    s = dcg.Solver(n, 1e-3)
+    b = torch.zeros(16 * n * n, dtype=torch.float64, device="cuda")
+    x = torch.full_like(b, 7.0)
+    status, st = s.solve(b, x, 1e-8)
+    assert status == lib.DCG_OK and st.outer_iters == 0 and not x.any()
+
+
+def test_nan_rhs_is_rejected():
+    n = 32
+    s = dcg.Solver(n, 1e-3)
+    b = torch.from_numpy(rhs(n, 0)).cuda()
+    b[123] = float("nan")
+    x = torch.empty_like(b)
+    with pytest.raises(lib.DCGError) as ei:
+        s.solve(b, x, 1e-8)
+    assert ei.value.status == lib.DCG_EINVAL
+
+
+def test_max_outer_reports_not_converged():
+    n, dt = 32, 1e-3
+    status, st, x, _ = _gpu(n, dt, 0, 1e-8, "mixed", max_outer=3)
+    assert status == lib.DCG_NOT_CONVERGED and st.outer_iters == 3
+    assert st.rel_res_recurrence > 1e-8 and np.isfinite(x).all()
+
+
+def test_warm_start_from_solution_converges_immediately():
+    n, dt = 32, 1e-3
+    _, _, x_conv, _ = _gpu(n, dt, 4, 1e-11, "fp64")
+    s = dcg.Solver(n, dt, prec="fp64", x0_given=True)
+    b = torch.from_numpy(rhs(n, 4)).cuda()
+    x = torch.from_numpy(x_conv).cuda()
+    status, st = s.solve(b, x, 1e-8)
+    assert status == lib.DCG_OK and st.outer_iters <= 1
+    assert np.linalg.norm(x.cpu().numpy() - x_conv) <= 1e-8 * np.linalg.norm(x_conv)
+
+
+def test_graph_and_direct_launch_give_identical_results():
+    n, dt = 32, 1e-4
+    r1 = _gpu(n, dt, 5, 1e-8, "mixed", use_graph=True)
+    r2 = _gpu(n, dt, 5, 1e-8, "mixed", use_graph=False)
+    assert r1[1].outer_iters == r2[1].outer_iters
+    assert np.array_equal(r1[2], r2[2])
+
+
+def test_repeated_solves_are_bitwise_identical():
+    n, dt = 32, 1e-3
+    s = dcg.Solver(n, dt, prec="mixed")
+    b = torch.from_numpy(rhs(n, 6)).cuda()
+    xs = []
+    for _ in range(3):
+        x = torch.empty_like(b)
+        s.solve(b, x, 1e-8)
+        xs.append(x.cpu().numpy())
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[1], xs[2])

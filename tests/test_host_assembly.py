@@ -1,0 +1,110 @@
+"""Host-side setup of the library (C++ assembly, Galerkin hierarchy, RAS
+tile inverses, coarsest inverse) against the oracle.  CPU only: the
+library's dcg_host_assemble runs the same host code dcg_setup uploads."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from layout import block_ell_to_csr, tensor_perm
+from oracle import discretisation as d
+from oracle import multigrid as mg
+
+lib = pytest.importorskip("paper_2606_13429_amd._binding")
+
+
+def _mesh(n):
+    m, _ = lib.dcg_defaults()
+    m.n = n
+    return m
+
+
+def _rel(a, b):
+    if sp.issparse(a) or sp.issparse(b):
+        diff = sp.csr_matrix(a) - sp.csr_matrix(b)
+        return abs(diff).max() / abs(sp.csr_matrix(b)).max()
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max()
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_divdiv_blocks_match_oracle(n):
+    vals, cols = lib.dcg_host_assemble(_mesh(n), 0)
+    A_elem = block_ell_to_csr(vals, cols, n * n, 16, 16)
+    perm = tensor_perm(n)
+    A_lib = A_elem[perm][:, perm]
+    assert _rel(A_lib, d.divdiv(n)) < 1e-13
+
+
+def test_divdiv_on_identity_matches_oracle():
+    n = 32
+    vals, cols = lib.dcg_host_assemble(_mesh(n), 1)
+    AZ = block_ell_to_csr(vals, cols, n * n, 16, 4)
+    AZ_lib = AZ[tensor_perm(n)]
+    assert _rel(AZ_lib, d.divdiv_on_identity(n)) < 1e-13
+
+
+def test_element_mass_matches_oracle():
+    n = 16
+    vals, _ = lib.dcg_host_assemble(_mesh(n), 2)
+    M1 = sp.block_diag([vals.reshape(n * n, 4, 4)[e] for e in range(n * n)])
+    assert _rel(M1, d.scalar_mass(n)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_galerkin_hierarchy_matches_oracle(n):
+    # the library keeps L_k = (2/dt) Z_k; with dt = 2 the oracle's Z_J = V^T A* V is L_J
+    As = d.operator(n, 2.0)
+    V = d.deflation_basis(n)
+    H = mg.Hierarchy((V.T @ As @ V).tocsr(), n)
+    for k in range(1, H.J + 1):
+        nk = H.n[k]
+        vals, cols = lib.dcg_host_assemble(_mesh(n), 3, k)
+        Lk = block_ell_to_csr(vals, cols, nk * nk, 4, 4)
+        assert _rel(Lk, H.A[k]) < 1e-12, k
+
+
+def test_ras_tile_inverses_match_oracle():
+    n = 64
+    As = d.operator(n, 2.0)
+    V = d.deflation_basis(n)
+    H = mg.Hierarchy((V.T @ As @ V).tocsr(), n)
+    for k in range(2, H.J + 1):
+        vals, squares = lib.dcg_host_assemble(_mesh(n), 4, k)
+        T = vals.size // (128 * 128)
+        F = vals.reshape(T, 128, 128)
+        squares = squares.reshape(T, 32)
+        blocks, weights = mg.ras_blocks(H.n[k])
+        assert len(blocks) == T
+        Ak = H.A[k].tocsr()
+        for t in range(T):
+            dofs = blocks[t]
+            W = weights[t][:, None] * np.linalg.inv(Ak[dofs][:, dofs].toarray())   # D_i A_i^{-1}
+            # library local order: 4 * slot + j over its 32 square slots
+            pos = {dof: i for i, dof in enumerate(dofs)}
+            lib_dofs = [4 * e + j for e in squares[t] if e >= 0 for j in range(4)]
+            lib_idx = [4 * s + j for s, e in enumerate(squares[t]) if e >= 0 for j in range(4)]
+            o_idx = [pos[x] for x in lib_dofs]
+            Ft = F[t][np.ix_(lib_idx, lib_idx)]                 # F[j][i] = (D A^{-1})[i][j]
+            ref = W[np.ix_(o_idx, o_idx)].T
+            assert np.abs(Ft - ref).max() <= 1e-12 * np.abs(ref).max(), (k, t)
+            # padded slots carry no weight
+            pad = [4 * s + j for s, e in enumerate(squares[t]) if e < 0 for j in range(4)]
+            if pad:
+                assert not F[t][:, pad].any()
+
+
+def test_coarsest_inverse_matches_oracle():
+    n = 32
+    vals, _ = lib.dcg_host_assemble(_mesh(n), 5)
+    As = d.operator(n, 2.0)
+    V = d.deflation_basis(n)
+    H = mg.Hierarchy((V.T @ As @ V).tocsr(), n)
+    ref = np.linalg.inv(H.A[1].toarray())
+    assert _rel(vals.reshape(1024, 1024), ref) < 1e-10
+
+
+def test_invalid_mesh_rejected():
+    for bad in (0, 8, 48, 4096):
+        with pytest.raises(lib.DCGError) as ei:
+            lib.dcg_host_assemble(_mesh(bad), 0)
+        assert ei.value.status == lib.DCG_EINVAL
+    assert [lib.dcg_num_levels(n) for n in (16, 32, 512, 1024, 12)] == [1, 2, 6, 7, -1]
