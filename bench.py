@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the deflated-CG solve on one MI355X.
+
+Workload (the headline configuration): unit square, 512 x 512 squares,
+DG-Q1 pseudo-stress (4,194,304 unknowns), dt = 1e-4, nu = 1, penalty 10/h,
+RHS b ~ N(0, 1) from a seed, tol 1e-8, c_F = 0.01, W-cycle with 2 + 2 RAS
+sweeps, mixed form (FP32 multigrid inside the FP64 deflated CG).  A step is
+one complete dcg_solve (prologue, all outer iterations, epilogue) with all
+operators and vectors resident in HBM; ``value`` is solves per second.
+
+Also reported on the same JSON line:
+  fp64          one solve of the all-FP64 form (same RHS), for the comparison
+  roofline      the dominant kernel (finest-level RAS tile solves): algorithmic
+                bytes per launch / average launch time measured with HIP events
+                around every launch inside the timed solves
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of one finest-level RAS step (k_sweep), per finest square,
+# s = bytes per real: packed symmetric tile inverse 36 * 256 / 16 = 576 s,
+# operator L_J 5 x 4 x 4 = 80 s, f 4 s, pending-output writes 8 s, weight s;
+# plus, by step type: z_old 4 s, pending reads 12 s, z_new 4 s, coarse
+# iterate + pending (4 + 12) s / 4.  The four finest steps of a W-cycle are
+# one zero-start step (no L, no z), two steps with a pending update and one
+# with the prolongation; the model averages them.
+def sweep_bytes_per_square(s):
+    base = 576 * s + 4 * s + 8 * s + s
+    zero = base
+    pending = base + 80 * s + 4 * s + 12 * s + 4 * s
+    prolong = base + 80 * s + 4 * s + 4 * s + (4 * s + 12 * s) / 4
+    return (zero + 2 * pending + prolong) / 4
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n, dt, tol, gpu_outer, gpu_wcycles, c_F=0.01):
+    """The CPU oracle (FP64, NumPy/SciPy) on a bounded sample of the same
+    solve: one inner Multigrid solve (the prologue's, Algorithm 3 to c_F tol)
+    and one A* product, timed; solves/s extrapolated with the GPU solve's
+    W-cycle and outer-iteration counts (each outer iteration applies A*
+    twice in the oracle's M_D).  Oracle setup is not counted."""
+    from dcg_workloads import rhs
+    from oracle import discretisation, multigrid
+    t0 = time.time()
+    As = discretisation.operator(n, dt)
+    V = discretisation.deflation_basis(n)
+    E = (V.T @ As @ V).tocsr()
+    H = multigrid.Hierarchy(E, n)
+    t_setup = time.time() - t0
+    b = rhs(n, 0).reshape(n * n, 4, 4).transpose(1, 0, 2).reshape(-1)
+    s = V.T @ b
+    t0 = time.time()
+    _, cycles = multigrid.multigrid(H, s, tol=c_F * tol)
+    t_inner = time.time() - t0
+    t0 = time.time()
+    w = As @ b
+    t_spmv = time.time() - t0
+    t_wcycle = t_inner / max(cycles, 1)
+    t_solve = gpu_wcycles * t_wcycle + 2 * (gpu_outer + 2) * t_spmv
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": ("n=%d dt=%g: one inner multigrid solve (%d W-cycles, %.1f s) and one A* product "
+                       "(%.2f s), extrapolated to the GPU solve's %d W-cycles and %d outer iterations "
+                       "(estimate %.0f s per solve); oracle setup %.0f s not counted"
+                       % (n, dt, cycles, t_inner, t_spmv, gpu_wcycles, gpu_outer, t_solve, t_setup)),
+            "seconds_per_solve": t_solve}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--dt", type=float, default=1e-4)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--max-outer", type=int, default=50000,
+                    help="cap on outer iterations (profiling runs only; the headline uses the default)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only; the solve is not sharded across "
+              "GPUs (multi-GPU sharding is a design note).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2606_13429_amd as dcg
+    from paper_2606_13429_amd import _binding as lib
+    from dcg_workloads import rhs
+
+    n, dt, tol = args.n, args.dt, args.tol
+    torch.cuda.set_device(0)
+    log("setup n=%d dt=%g (mixed form)" % (n, dt))
+    t0 = time.time()
+    solver = dcg.Solver(n, dt, prec="mixed", max_outer=args.max_outer)
+    log("setup done in %.1f s" % (time.time() - t0))
+    bs = [torch.from_numpy(rhs(n, s)).cuda() for s in range(max(args.steps, 1))]
+    x = torch.empty_like(bs[0])
+    for i in range(args.warmup):
+        st = solver.solve(bs[0], x, tol)[1]
+        log("warmup %d: outer=%d Tot=%d %.1f ms" % (i, st.outer_iters, st.total_wcycles, st.t_solve_ms))
+
+    lib.dcg_kernel_timing(solver.handle, True)
+    stats = []
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.time()
+    ev0.record()
+    for i in range(args.steps):
+        status, st = solver.solve(bs[i], x, tol)
+        stats.append(st.as_dict())
+        log("step %d: status=%d outer=%d Tot=%d Inn=%.2f res=%.2e %.1f ms"
+            % (i, status, st.outer_iters, st.total_wcycles, st.inner_per_outer, st.rel_res_true,
+               st.t_solve_ms))
+    ev1.record()
+    torch.cuda.synchronize()
+    t_wall = time.time() - t_wall
+    ms_total = ev0.elapsed_time(ev1)
+    k_ms, k_launches = lib.dcg_kernel_timing_read(solver.handle)
+    lib.dcg_kernel_timing(solver.handle, False)
+    ms_per_step = ms_total / args.steps
+    value = 1000.0 / ms_per_step
+
+    tiles_bytes = int(sweep_bytes_per_square(4) * n * n)
+    k_avg_ms = k_ms / max(k_launches, 1)
+    achieved = tiles_bytes / (k_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_sweep<float,1> (finest-level RAS step)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(k_avg_ms * 1e3, 2), "launches": k_launches,
+                "bytes_per_launch": tiles_bytes}
+
+    outer = int(np.mean([s["outer_iters"] for s in stats]))
+    result = {
+        "metric": "dCG solves/s & HBM GB/s, n=512 dt=1e-4, FP32-MG vs FP64; serve p50/p99",
+        "value": round(value, 5), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 outer / f32 multigrid",
+        "data": "synthetic: b ~ N(0,1) seeds 0..%d, element-major" % (args.steps - 1),
+        "config": {"workload": "deflated CG, unit square %dx%d DG-Q1 (%d dofs), dt=%g, tol=%g, "
+                               "W-cycle J=%d with RAS 4x4+1, c_F=0.01, mixed form"
+                               % (n, n, 16 * n * n, dt, tol, lib.dcg_num_levels(n)),
+                   "n": n, "dt": dt, "tol": tol, "form": "mixed"},
+        "solve_stats": {"outer_iters": outer,
+                        "total_wcycles": int(np.mean([s["total_wcycles"] for s in stats])),
+                        "inner_per_outer": round(float(np.mean([s["inner_per_outer"] for s in stats])), 2),
+                        "rel_res_true": max(s["rel_res_true"] for s in stats),
+                        "setup_ms": round(stats[0]["t_setup_ms"], 1)},
+        "roofline": roofline,
+    }
+
+    if not args.skip_fp64:
+        log("FP64 form: setup + one solve")
+        s64 = dcg.Solver(n, dt, prec="fp64", max_outer=args.max_outer)
+        x64 = torch.empty_like(x)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, st64 = s64.solve(bs[0], x64, tol)
+        torch.cuda.synchronize()
+        t64 = time.time() - t0
+        rel = (torch.linalg.norm(x64 - x) / torch.linalg.norm(x64)).item() if args.steps == 1 else None
+        result["fp64"] = {"solves_per_s": round(1.0 / t64, 5), "outer_iters": st64.outer_iters,
+                          "total_wcycles": st64.total_wcycles, "rel_res_true": st64.rel_res_true,
+                          "mixed_speedup": round(value * t64, 3)}
+        if rel is not None:
+            result["fp64"]["mixed_vs_fp64_rel_diff"] = rel
+        s64.close()
+
+    if not args.skip_cpu:
+        log("CPU oracle baseline (setup is not counted)")
+        result["cpu_baseline"] = cpu_baseline(n, dt, tol, outer, result["solve_stats"]["total_wcycles"])
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

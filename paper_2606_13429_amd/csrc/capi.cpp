@@ -153,8 +153,15 @@ dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
         const dcg::HostLevel& hl = hc.levels[level - 1];
         const size_t per = size_t(dcg::kTileDofs) * dcg::kTileDofs;
         tmp.resize(per * hl.tiles);
-        for (int t = 0; t < hl.tiles; ++t)
-          std::memcpy(&tmp[per * t], hl.unique_inv[hl.tile_class[t]].data(), per * sizeof(double));
+        for (int t = 0; t < hl.tiles; ++t) {      // F[j][i] = (L_k)_t^{-1}[j][i] d_i
+          const double* inv = hl.unique_inv[hl.tile_class[t]].data();
+          for (int i = 0; i < dcg::kTileDofs; ++i) {
+            const int32_t e = hl.tile_elems[int64_t(t) * dcg::kTileSlots + i / 4];
+            const double di = e >= 0 ? hl.dw[e] : 0.0;
+            for (int j = 0; j < dcg::kTileDofs; ++j)
+              tmp[per * t + size_t(j) * dcg::kTileDofs + i] = inv[size_t(j) * dcg::kTileDofs + i] * di;
+          }
+        }
         src = &tmp;
         csrc = &hl.tile_elems;
         break;

@@ -89,9 +89,11 @@ void upload_level_L(const HostLevel& hl, T* dev) {
   DCG_HIP(hipMemcpy(dev, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
+// Tile inverses in the packed symmetric layout of the sweep kernel: per tile
+// the 36 upper 16 x 16 blocks (P <= Q, row by row), each row-major.
 template <typename T>
 void upload_factors(const HostLevel& hl, T* dev) {
-  const int64_t per = kTileDofs * kTileDofs;
+  const int64_t per = 36 * 256;
   const int chunk = 512;
   std::vector<T> stage(size_t(chunk) * per);
   for (int t0 = 0; t0 < hl.tiles; t0 += chunk) {
@@ -99,11 +101,23 @@ void upload_factors(const HostLevel& hl, T* dev) {
     threaded(cnt, [&](int64_t dt) {
       const std::vector<double>& src = hl.unique_inv[hl.tile_class[t0 + dt]];
       T* d = &stage[size_t(dt) * per];
-      for (int64_t k = 0; k < per; ++k) d[k] = T(src[k]);
+      int b = 0;
+      for (int P = 0; P < 8; ++P)
+        for (int Q = P; Q < 8; ++Q, ++b)
+          for (int ri = 0; ri < 16; ++ri)
+            for (int ci = 0; ci < 16; ++ci)
+              d[b * 256 + ri * 16 + ci] = T(src[size_t(16 * P + ri) * kTileDofs + 16 * Q + ci]);
     });
     DCG_HIP(hipMemcpy(dev + int64_t(t0) * per, stage.data(), sizeof(T) * cnt * per,
                       hipMemcpyHostToDevice));
   }
+}
+
+template <typename T>
+void upload_weights(const HostLevel& hl, T* dev) {
+  std::vector<T> t(hl.dw.size());
+  for (size_t i = 0; i < t.size(); ++i) t[i] = T(hl.dw[i]);
+  DCG_HIP(hipMemcpy(dev, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
 struct Key {
@@ -161,6 +175,12 @@ std::shared_ptr<MeshContext> build_context(int device, int n, double penalty) {
       dl.tile_elems = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_elems.size()));
       DCG_HIP(hipMemcpy(dl.tile_elems, hl.tile_elems.data(), sizeof(int32_t) * hl.tile_elems.size(),
                         hipMemcpyHostToDevice));
+      dl.tile_ext = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_ext.size()));
+      DCG_HIP(hipMemcpy(dl.tile_ext, hl.tile_ext.data(), sizeof(int32_t) * hl.tile_ext.size(),
+                        hipMemcpyHostToDevice));
+      dl.tile_dst = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_dst.size()));
+      DCG_HIP(hipMemcpy(dl.tile_dst, hl.tile_dst.data(), sizeof(int32_t) * hl.tile_dst.size(),
+                        hipMemcpyHostToDevice));
       dl.cover = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.cover.size()));
       DCG_HIP(hipMemcpy(dl.cover, hl.cover.data(), sizeof(int32_t) * hl.cover.size(),
                         hipMemcpyHostToDevice));
@@ -191,13 +211,17 @@ void MeshContext::ensure_factors(bool fp32) {
       upload_level_L<float>(hl, dl.L32);
     }
     if (k >= 2) {
-      const size_t cnt = size_t(hl.tiles) * kTileDofs * kTileDofs;
+      const size_t cnt = size_t(hl.tiles) * 36 * 256;
       if (fp32) {
         dl.F32 = static_cast<float*>(alloc(sizeof(float) * cnt));
         upload_factors<float>(hl, dl.F32);
+        dl.dw32 = static_cast<float*>(alloc(sizeof(float) * dl.ne));
+        upload_weights<float>(hl, dl.dw32);
       } else {
         dl.F64 = static_cast<double*>(alloc(sizeof(double) * cnt));
         upload_factors<double>(hl, dl.F64);
+        dl.dw64 = static_cast<double*>(alloc(sizeof(double) * dl.ne));
+        upload_weights<double>(hl, dl.dw64);
       }
     }
   }

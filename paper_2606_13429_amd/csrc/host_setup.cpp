@@ -266,6 +266,7 @@ void build_tiles(HostLevel& lv) {
   lv.tiles = tpr * tpr;
   const int64_t ne = int64_t(n) * n;
   lv.tile_elems.assign(int64_t(lv.tiles) * kTileSlots, -1);
+  lv.tile_ext.assign(int64_t(lv.tiles) * kTileExt, -1);
   std::vector<int32_t> count(ne, 0);
   auto elem = [&](int ex, int ey) -> int32_t {
     return (ex < 0 || ey < 0 || ex >= n || ey >= n) ? -1 : int32_t(int64_t(ey) * n + ex);
@@ -284,6 +285,19 @@ void build_tiles(HostLevel& lv) {
       }
       for (int s = 0; s < kTileSlots; ++s)
         if (te[s] >= 0) ++count[te[s]];
+      // extended pattern: block slots, then the ring at distance 1 outside it
+      int32_t* tx = &lv.tile_ext[(int64_t(b) * tpr + a) * kTileExt];
+      for (int s = 0; s < kTileSlots; ++s) tx[s] = te[s];
+      for (int l = 0; l < 4; ++l) {
+        tx[32 + l] = elem(x0 - 2, y0 + l);
+        tx[36 + l] = elem(x0 + 5, y0 + l);
+        tx[40 + l] = elem(x0 + l, y0 - 2);
+        tx[44 + l] = elem(x0 + l, y0 + 5);
+      }
+      tx[48] = elem(x0 - 1, y0 - 1);
+      tx[49] = elem(x0 + 4, y0 - 1);
+      tx[50] = elem(x0 - 1, y0 + 4);
+      tx[51] = elem(x0 + 4, y0 + 4);
     }
   // cover lists in increasing tile order (fixed summation order of the update)
   lv.cover.assign(ne * 3, -1);
@@ -294,6 +308,14 @@ void build_tiles(HostLevel& lv) {
       if (e < 0) continue;
       if (fill[e] >= 3) throw std::runtime_error("square in more than 3 RAS blocks");
       lv.cover[e * 3 + fill[e]++] = t * kTileSlots + s;
+    }
+  lv.dw.resize(ne);
+  for (int64_t e = 0; e < ne; ++e) lv.dw[e] = 1.0 / count[e];
+  lv.tile_dst.assign(int64_t(lv.tiles) * kTileSlots, -1);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int k = 0; k < 3; ++k) {
+      const int32_t c = lv.cover[e * 3 + k];
+      if (c >= 0) lv.tile_dst[c] = int32_t(e * 3 + k);
     }
   // local matrices (L_k)_i = R_i L_k R_i^T and weights D_i; identical local
   // problems (bit for bit) share one inverse computation
@@ -346,9 +368,6 @@ void build_tiles(HostLevel& lv) {
   parallel_for(int64_t(uniq_mat.size()), [&](int64_t u) {
     std::vector<double> inv(kTileDofs * kTileDofs);
     if (!spd_inverse(kTileDofs, uniq_mat[u].data(), inv.data(), 1)) return;
-    const double* dvec = &uniq_mat[u][kTileDofs * kTileDofs];
-    for (int j = 0; j < kTileDofs; ++j)
-      for (int c = 0; c < kTileDofs; ++c) inv[j * kTileDofs + c] *= dvec[c];
     lv.unique_inv[u] = std::move(inv);
     ok[u] = 1;
   }, 2);

@@ -13,6 +13,7 @@ constexpr int kSlots = 5;        // self, x-1, x+1, y-1, y+1
 constexpr int kTileCore = 4;     // 4 x 4 squares per RAS core
 constexpr int kTileSlots = 32;   // core + face-neighbour layer
 constexpr int kTileDofs = 128;   // 4 dofs per square
+constexpr int kTileExt = 52;     // block squares + their outside neighbours
 constexpr int kCoarsestN = 16;   // level 1 is 16 x 16 squares
 constexpr int kCoarseDofs = 4 * kCoarsestN * kCoarsestN;
 
@@ -23,9 +24,13 @@ struct HostLevel {
   // RAS data, levels k >= 2
   int tiles = 0;
   std::vector<int32_t> tile_elems; // [T][32], -1 = padded slot
+  std::vector<int32_t> tile_ext;   // [T][52]: the 32 block squares, then the 20
+                                   // squares at distance 1 outside the block
   std::vector<int32_t> tile_class; // [T] index into unique_inv
-  std::vector<std::vector<double>> unique_inv;  // each [128][128], F = A_i^{-1} D_i
+  std::vector<std::vector<double>> unique_inv;  // each [128][128] = (L_k)_i^{-1} (symmetric)
+  std::vector<double> dw;          // [Ne] partition-of-unity weight 1 / #blocks containing e
   std::vector<int32_t> cover;      // [Ne][3] = tile * 32 + slot, -1 = none
+  std::vector<int32_t> tile_dst;   // [T][32] = 3 e + k, k = rank of the tile in e's cover
 };
 
 struct HostContext {

@@ -117,4 +117,54 @@ hipError_t launch_fill(int64_t n, T v, T* x, hipStream_t st);
 template <typename T>
 hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st);
 
+// ------------------------------------------------------------ fused W-cycle
+// Arguments of one RAS step of level k (mg_kernels.hip).  z and Y of a level
+// are double buffers; a step reads z_old (+ the pending tile outputs Y_old,
+// + the prolongated coarse correction) and writes z_new (core squares of
+// every tile) and its own tile outputs Y_new.
+template <typename T>
+struct SweepArgs {
+  const T* F = nullptr;             // [tiles][36][16][16] packed symmetric inverses
+  const T* dw = nullptr;            // [ne] partition-of-unity weight 1 / #blocks
+  const int32_t* ext = nullptr;     // [tiles][52] block squares + outside neighbours
+  int tiles = 0, n = 0, ne = 0;
+  const T* L = nullptr;             // level operator [5][ne][4][4]
+  const int32_t* cols = nullptr;    // [5][ne]
+  const int32_t* dst = nullptr;     // [tiles][32] pending slot 3 e + k of each block square
+  const T* f = nullptr;
+  const T* z_old = nullptr;
+  const T* Y_old = nullptr;         // pending tile outputs [ne][3][4]
+  T* z_new = nullptr;
+  T* Y_new = nullptr;
+  int has_z = 0, has_y = 0, write_z = 0;
+  int prol = 0, nc = 0, c_has_y = 0;  // z += P (zc + pending Yc) of the coarser level
+  const T* zc = nullptr;
+  const T* Yc = nullptr;
+};
+
+template <typename T>
+struct RestrictArgs {
+  int n = 0, ne = 0;                // fine level
+  const T* L = nullptr;
+  const int32_t* cols = nullptr;
+  const T* f = nullptr;
+  const T* z_old = nullptr;
+  const T* Y_old = nullptr;         // pending tile outputs [ne][3][4]
+  T* z_new = nullptr;
+  T* rc = nullptr;                  // coarse right-hand side P^T (f - L z)
+  int has_z = 0, has_y = 0, write_z = 0;
+};
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, int waves_per_tile, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict_res(const RestrictArgs<T>& a, hipStream_t st);
+// out = (has_z ? z : 0) + pending Ye
+template <typename T>
+hipError_t launch_resolve(int ne, bool has_z, const T* z, const T* Ye, T* out, hipStream_t st);
+// z64 = (first ? 0 : z64) + (double)((has_z ? z : 0) + (has_y ? pending Ye : 0))
+template <typename T>
+hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T* z, const T* Ye,
+                             double* z64, hipStream_t st);
+
 }  // namespace dcg

@@ -32,9 +32,13 @@ struct DeviceLevel {
   float* L32 = nullptr;
   int tiles = 0;                  // levels >= 2
   int32_t* tile_elems = nullptr;  // [tiles][32]
+  int32_t* tile_ext = nullptr;    // [tiles][52]
   int32_t* cover = nullptr;       // [ne][3]
-  float* F32 = nullptr;           // [tiles][128][128]
+  int32_t* tile_dst = nullptr;    // [tiles][32]
+  float* F32 = nullptr;           // [tiles][36][16][16] packed symmetric inverses
   double* F64 = nullptr;
+  float* dw32 = nullptr;          // [ne] 1 / #blocks containing the square
+  double* dw64 = nullptr;
 };
 
 // Dt-independent operators of one mesh on one device; shared by handles and
@@ -76,8 +80,8 @@ struct Workspace {
   double* part = nullptr;                 // [3][kPartStride]
   Scalars* sc = nullptr;                  // device
   Scalars* sc_host = nullptr;             // pinned host mirror
-  // level buffers (level real type), index k - 1
-  std::vector<void*> f, z, rr, Y;
+  // level buffers (level real type), index k - 1; z and Y double-buffered
+  std::vector<void*> f, rr, z[2], Y[2];
   void* alloc(size_t bytes);
   void release();
   ~Workspace();
@@ -94,7 +98,8 @@ struct dcg_ctx {
   bool fp32 = true;
   dcg::Workspace ws;
   hipStream_t capture_stream = nullptr;
-  hipGraphExec_t wgraph = nullptr;        // W-cycle on the finest level
+  hipGraphExec_t wgraph = nullptr;        // coarse-grid correction of the finest level
+  int graph_state[4] = {0, 0, 0, 0};      // level J-1 state the graph leaves behind
   std::string last_error;
   double t_setup_ms = 0.0;
   int device = 0;
