@@ -178,6 +178,18 @@ dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
                              double* dst, int64_t dst_len, int32_t* cols,
                              int64_t cols_len, int64_t* needed);
 
+/* BDF2 time stepping (Section 2.3, implicit multistep family; BDF2 reading):
+ * for M d(sigma)/dt + A sigma = F the step n solves (M + alpha A) sigma^n = f
+ * with alpha = 2 dt_step / 3 and
+ *   f  = M (4/3 s1 - 1/3 s2) + c F,   c = 2 dt_step / 3,
+ * s1 = sigma^{n-1}, s2 = sigma^{n-2}; the warm start is x0 = 2 s1 - s2.
+ * This entry point computes f and x0 (device FP64 tensor vectors, element-
+ * major; f and x0 must not alias the inputs) with the handle's mass M =
+ * (1/nu) C (x) M_1; the solve itself is dcg_solve on a handle created with
+ * dt = alpha and x0_given = 1. */
+dcg_status dcg_bdf2_rhs(dcg_handle h, const double* s1, const double* s2, const double* F,
+                        double c, double* f, double* x0, void* hip_stream);
+
 /* Live timing of the dominant kernel of the solve, the RAS tile solves of
  * the finest level (Section 4.2, (A_J)_i^{-1} applied to every block).
  * While enabled, every launch of that kernel made by dcg_solve on this

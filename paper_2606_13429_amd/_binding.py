@@ -61,6 +61,7 @@ _SIGS = {
     "dcg_num_levels": (ctypes.c_int32, [ctypes.c_int32]),
     "dcg_host_assemble": (ctypes.c_int, [_P(dcg_mesh), ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double),
                                          ctypes.c_int64, _P(ctypes.c_int32), ctypes.c_int64, _P(ctypes.c_int64)]),
+    "dcg_bdf2_rhs": (ctypes.c_int, [_h, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "dcg_kernel_timing": (ctypes.c_int, [_h, ctypes.c_int32]),
     "dcg_kernel_timing_read": (ctypes.c_int, [_h, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "dcg_destroy": (ctypes.c_int, [_h]),
@@ -174,6 +175,12 @@ def dcg_host_assemble(mesh, which, level=0):
         cols.ctypes.data_as(_P(ctypes.c_int32)) if cols is not None else None,
         cols.size if cols is not None else 0, None))
     return vals, cols
+
+
+def dcg_bdf2_rhs(handle, s1, s2, F, c, f, x0, stream=None):
+    return _check(_lib.dcg_bdf2_rhs(handle, _ptr(s1, _f64(), name="s1"), _ptr(s2, _f64(), name="s2"),
+                                    _ptr(F, _f64(), name="F"), c, _ptr(f, _f64(), name="f"),
+                                    _ptr(x0, _f64(), name="x0"), _stream(stream)), handle)
 
 
 def dcg_kernel_timing(handle, enable):

@@ -181,6 +181,21 @@ dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
   });
 }
 
+dcg_status dcg_bdf2_rhs(dcg_handle h, const double* s1, const double* s2, const double* F,
+                        double c, double* f, double* x0, void* hip_stream) {
+  if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  if (!s1 || !s2 || !F || !f || !x0) return fail(h, DCG_EINVAL, "NULL vector");
+  if (f == s1 || f == s2 || x0 == s1 || x0 == s2 || f == x0)
+    return fail(h, DCG_EINVAL, "f and x0 must not alias the inputs or each other");
+  if (!std::isfinite(c)) return fail(h, DCG_EINVAL, "c must be finite");
+  return guarded(h, [&]() {
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    DCG_HIP(dcg::launch_bdf2_rhs(h->mesh->ne, h->mesh->M1, 1.0 / h->nu, s1, s2, F, c, f, x0, st));
+    DCG_HIP(hipStreamSynchronize(st));
+    return DCG_OK;
+  });
+}
+
 dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable) {
   if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
   return guarded(h, [&]() {

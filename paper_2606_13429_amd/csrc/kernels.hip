@@ -350,6 +350,37 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(int ne, const double* 
   x[i] = v;
 }
 
+// BDF2 right-hand side and warm start: f = (1/nu) (C (x) M_1)(4/3 s1 - 1/3 s2)
+// + c F, x0 = 2 s1 - s2; thread (square, row).
+__global__ __launch_bounds__(kThreads) void k_bdf2_rhs(int ne, const double* __restrict__ M1,
+                                                       double inv_nu, const double* __restrict__ s1,
+                                                       const double* __restrict__ s2,
+                                                       const double* __restrict__ F, double c,
+                                                       double* __restrict__ f,
+                                                       double* __restrict__ x0) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= 16 * (int64_t)ne) return;
+  const int64_t e = i >> 4;
+  const int r = int(i & 15), cc = r >> 2, j = r & 3;
+  double u[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    u[k] = 4.0 / 3.0 * s1[16 * e + k] - 1.0 / 3.0 * s2[16 * e + k];
+  double m[4];
+  ld4(M1 + 16 * e + 4 * j, m);
+  double mu;
+  if (cc == 0 || cc == 3) {
+    mu = 0.5 * (m[0] * (u[0] - u[12]) + m[1] * (u[1] - u[13]) + m[2] * (u[2] - u[14]) +
+                m[3] * (u[3] - u[15]));
+    if (cc == 3) mu = -mu;
+  } else {
+    const int o = 4 * cc;
+    mu = m[0] * u[o] + m[1] * u[o + 1] + m[2] * u[o + 2] + m[3] * u[o + 3];
+  }
+  f[i] = inv_nu * mu + c * F[i];
+  x0[i] = 2.0 * s1[i] - s2[i];
+}
+
 __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, double c,
                                                     const double* __restrict__ in,
                                                     double* __restrict__ out) {
@@ -687,6 +718,14 @@ hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const 
                               double* x, hipStream_t st) {
   k_reconstruct<<<grid_for(16 * (int64_t)ne, kThreads, 1 << 30), kThreads, 0, st>>>(ne, xh, zt, zb,
                                                                                    c, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_bdf2_rhs(int ne, const double* M1, double inv_nu, const double* s1,
+                           const double* s2, const double* F, double c, double* f, double* x0,
+                           hipStream_t st) {
+  k_bdf2_rhs<<<grid_for(16 * (int64_t)ne, kThreads, 1 << 30), kThreads, 0, st>>>(ne, M1, inv_nu, s1, s2,
+                                                                                F, c, f, x0);
   return hipGetLastError();
 }
 

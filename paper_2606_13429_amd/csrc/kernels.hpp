@@ -87,6 +87,10 @@ hipError_t launch_z(int ne, const double* y, double scale, double* v, hipStream_
 hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const double* zb, double c,
                               double* x, hipStream_t st);
 hipError_t launch_scale(int64_t n, double c, const double* in, double* out, hipStream_t st);
+// f = (1/nu) M (4/3 s1 - 1/3 s2) + c F ; x0 = 2 s1 - s2
+hipError_t launch_bdf2_rhs(int ne, const double* M1, double inv_nu, const double* s1,
+                           const double* s2, const double* F, double c, double* f, double* x0,
+                           hipStream_t st);
 
 // inner refinement (FP64 residual of the level-J Laplacian)
 template <typename T>
