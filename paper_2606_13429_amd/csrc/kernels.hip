@@ -64,13 +64,25 @@ inline int grid_for(int64_t items, int per_block, int cap) {
 // w = (1/nu) M u + dt A_div u, s = Z^T w.  Thread (square e, row r); one
 // workgroup = 16 squares.  M = C (x) M_1 with C the dev-dev coefficient
 // matrix (Section 3.1): rows 11/22 see (u11 - u22)/2, rows 12/21 see u.
+__device__ inline int slot_id(const Slots& sl) { return sl.list ? sl.list[blockIdx.y] : 0; }
+
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_astar(
     const double2* __restrict__ A, const int32_t* __restrict__ cols, const double* __restrict__ M1,
-    int ne, double dt, double inv_nu, const double* __restrict__ x, const double* __restrict__ p_old,
+    int ne, const double* __restrict__ x, const double* __restrict__ p_old,
     const double* __restrict__ b, const Scalars* __restrict__ sc, double* __restrict__ p_new,
-    double* __restrict__ w, double* __restrict__ s, double* __restrict__ part) {
+    double* __restrict__ w, double* __restrict__ s, double* __restrict__ part, Slots sl) {
   __shared__ double lds[4];
+  const int slot = slot_id(sl);
+  x += slot * sl.tstride;
+  if (p_old) p_old += slot * sl.tstride;
+  if (b) b += slot * sl.tstride;
+  if (p_new) p_new += slot * sl.tstride;
+  if (w) w += slot * sl.tstride;
+  if (s) s += slot * sl.sstride;
+  sc += slot;
+  if (part) part += slot * kSlotPart;
+  const double dt = sc->dt, inv_nu = sc->inv_nu;
   const int r = threadIdx.x & 15;
   const double beta = MODE == kAstarDir ? sc->beta : 0.0;
   const int groups = (ne + 15) >> 4;
@@ -146,8 +158,15 @@ template <bool PROLOGUE>
 __global__ __launch_bounds__(kThreads) void k_deflate(
     const double2* __restrict__ AZ, const int32_t* __restrict__ cols, int ne, double c,
     const double* __restrict__ z, const double* __restrict__ w, const double* __restrict__ p,
-    double* __restrict__ q, double* __restrict__ p_out, double* __restrict__ part) {
+    double* __restrict__ q, double* __restrict__ p_out, double* __restrict__ part, Slots sl) {
   __shared__ double lds[4];
+  const int slot = slot_id(sl);
+  z += slot * sl.sstride;
+  w += slot * sl.tstride;
+  if (p) p += slot * sl.tstride;
+  q += slot * sl.tstride;
+  if (p_out) p_out += slot * sl.tstride;
+  part += slot * kSlotPart;
   const int r = threadIdx.x & 15;
   const int groups = (ne + 15) >> 4;
   double d0 = 0.0, d1 = 0.0;
@@ -211,8 +230,15 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t n, const Scalars
                                                         const double* __restrict__ q,
                                                         double* __restrict__ x,
                                                         double* __restrict__ r,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, Slots sl) {
   __shared__ double lds[4];
+  const int slot = slot_id(sl);
+  p += slot * sl.tstride;
+  q += slot * sl.tstride;
+  x += slot * sl.tstride;
+  r += slot * sl.tstride;
+  sc += slot;
+  part += slot * kSlotPart;
   const double alpha = sc->alpha;
   double rr = 0.0, rq = 0.0, pr = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
@@ -254,8 +280,11 @@ __global__ __launch_bounds__(kThreads) void k_axpy_dot(int64_t n, double a,
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ part, int nb,
-                                                     int op, Scalars* __restrict__ sc) {
+                                                     int op, Scalars* __restrict__ sc, Slots sl) {
   __shared__ double sm[kThreads];
+  const int slot = slot_id(sl);
+  part += slot * kSlotPart;
+  sc += slot;
   const int nslot = op == kRedB2Rho ? 2 : (op == kRedFcgBeta ? 3 : 1);
   double sums[3] = {0.0, 0.0, 0.0};
   for (int slot = 0; slot < nslot; ++slot) {
@@ -319,7 +348,10 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ 
 }
 
 __global__ __launch_bounds__(kThreads) void k_zt(int ne, const double* __restrict__ w,
-                                                 double* __restrict__ s) {
+                                                 double* __restrict__ s, Slots sl) {
+  const int slot = slot_id(sl);
+  w += slot * sl.tstride;
+  s += slot * sl.sstride;
   const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (i >= 4 * (int64_t)ne) return;
   const int64_t e = i >> 2, j = i & 3;
@@ -337,8 +369,15 @@ __global__ __launch_bounds__(kThreads) void k_z(int ne, const double* __restrict
 // x = (xh - Z (c zt)) + Z (c zb)  (eq. (x_defl) with pi(b) reused)
 __global__ __launch_bounds__(kThreads) void k_reconstruct(int ne, const double* __restrict__ xh,
                                                           const double* __restrict__ zt,
-                                                          const double* __restrict__ zb, double c,
-                                                          double* __restrict__ x) {
+                                                          const double* __restrict__ zb,
+                                                          const Scalars* __restrict__ sc,
+                                                          double* __restrict__ x, Slots sl) {
+  const int slot = slot_id(sl);
+  xh += slot * sl.tstride;
+  zt += slot * sl.sstride;
+  zb += slot * sl.sstride;
+  x += slot * sl.tstride;
+  const double c = 2.0 / sc[slot].dt;
   const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (i >= 16 * (int64_t)ne) return;
   const int64_t e = i >> 4, cc = (i >> 2) & 3, j = i & 3;
@@ -395,8 +434,13 @@ template <typename T, bool FIRST>
 __global__ __launch_bounds__(kThreads) void k_refine_residual(
     const double* __restrict__ L, const int32_t* __restrict__ cols, int ne,
     const double* __restrict__ s, const double* __restrict__ z, T* __restrict__ fJ,
-    double* __restrict__ part) {
+    double* __restrict__ part, Slots sl) {
   __shared__ double lds[4];
+  const int slot = slot_id(sl);
+  s += slot * sl.sstride;
+  if (z) z += slot * sl.sstride;
+  fJ += slot * sl.lstride;
+  part += slot * kSlotPart;
   const int a = threadIdx.x & 3;
   const int groups = (ne + 63) >> 6;
   double nrm = 0.0;
@@ -633,26 +677,26 @@ __global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const T* __restric
 
 // ============================================================ launchers
 hipError_t launch_astar(int mode, const double2* A, const int32_t* cols, const double* M1, int ne,
-                        double dt, double inv_nu, const double* x, const double* p_old,
-                        const double* b, const Scalars* sc, double* p_new, double* w, double* s,
-                        double* part, hipStream_t st) {
-  const int grid = grid_for(ne, 16, kPartStride);
+                        const double* x, const double* p_old, const double* b, const Scalars* sc,
+                        double* p_new, double* w, double* s, double* part, hipStream_t st,
+                        const Slots& sl, int count) {
+  const dim3 grid(grid_for(ne, 16, kPartStride), count);
   switch (mode) {
     case kAstarPlain:
-      k_astar<kAstarPlain><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b, sc,
-                                                      p_new, w, s, part);
+      k_astar<kAstarPlain><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
+                                                      part, sl);
       break;
     case kAstarDir:
-      k_astar<kAstarDir><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b, sc,
-                                                    p_new, w, s, part);
+      k_astar<kAstarDir><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
+                                                    part, sl);
       break;
     case kAstarFirst:
-      k_astar<kAstarFirst><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b, sc,
-                                                      p_new, w, s, part);
+      k_astar<kAstarFirst><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
+                                                      part, sl);
       break;
     case kAstarResidual:
-      k_astar<kAstarResidual><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, dt, inv_nu, x, p_old, b,
-                                                         sc, p_new, w, s, part);
+      k_astar<kAstarResidual><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w,
+                                                         s, part, sl);
       break;
     default:
       return hipErrorInvalidValue;
@@ -664,12 +708,12 @@ int astar_blocks(int ne) { return grid_for(ne, 16, kPartStride); }
 
 hipError_t launch_deflate(bool prologue, const double2* AZ, const int32_t* cols, int ne, double c,
                           const double* z, const double* w, const double* p, double* q,
-                          double* p_out, double* part, hipStream_t st) {
-  const int grid = grid_for(ne, 16, kPartStride);
+                          double* p_out, double* part, hipStream_t st, const Slots& sl, int count) {
+  const dim3 grid(grid_for(ne, 16, kPartStride), count);
   if (prologue)
-    k_deflate<true><<<grid, kThreads, 0, st>>>(AZ, cols, ne, c, z, w, p, q, p_out, part);
+    k_deflate<true><<<grid, kThreads, 0, st>>>(AZ, cols, ne, c, z, w, p, q, p_out, part, sl);
   else
-    k_deflate<false><<<grid, kThreads, 0, st>>>(AZ, cols, ne, c, z, w, p, q, p_out, part);
+    k_deflate<false><<<grid, kThreads, 0, st>>>(AZ, cols, ne, c, z, w, p, q, p_out, part, sl);
   return hipGetLastError();
 }
 
@@ -681,13 +725,14 @@ hipError_t launch_adivz(const double2* AZ, const int32_t* cols, int ne, const do
 
 hipError_t launch_cg_update(bool flexible, int64_t nvec, const Scalars* sc, const double* p,
                             const double* q, double* x, double* r, double* part, int* nblocks,
-                            hipStream_t st) {
-  const int grid = grid_for(nvec, kThreads * 4, 8192);
-  *nblocks = grid;
+                            hipStream_t st, const Slots& sl, int count) {
+  const int gx = grid_for(nvec, kThreads * 4, 8192);
+  *nblocks = gx;
+  const dim3 grid(gx, count);
   if (flexible)
-    k_cg_update<true><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part);
+    k_cg_update<true><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part, sl);
   else
-    k_cg_update<false><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part);
+    k_cg_update<false><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part, sl);
   return hipGetLastError();
 }
 
@@ -699,13 +744,14 @@ hipError_t launch_axpy_dot(int64_t nvec, double a, const double* q, double* r, d
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st) {
-  k_reduce<<<1, kThreads, 0, st>>>(part, nblocks, op, sc);
+hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st,
+                         const Slots& sl, int count) {
+  k_reduce<<<dim3(1, count), kThreads, 0, st>>>(part, nblocks, op, sc, sl);
   return hipGetLastError();
 }
 
-hipError_t launch_zt(int ne, const double* w, double* s, hipStream_t st) {
-  k_zt<<<grid_for(4 * (int64_t)ne, kThreads, 1 << 30), kThreads, 0, st>>>(ne, w, s);
+hipError_t launch_zt(int ne, const double* w, double* s, hipStream_t st, const Slots& sl, int count) {
+  k_zt<<<dim3(grid_for(4 * (int64_t)ne, kThreads, 1 << 30), count), kThreads, 0, st>>>(ne, w, s, sl);
   return hipGetLastError();
 }
 
@@ -714,10 +760,11 @@ hipError_t launch_z(int ne, const double* y, double scale, double* v, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const double* zb, double c,
-                              double* x, hipStream_t st) {
-  k_reconstruct<<<grid_for(16 * (int64_t)ne, kThreads, 1 << 30), kThreads, 0, st>>>(ne, xh, zt, zb,
-                                                                                   c, x);
+hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const double* zb,
+                              const Scalars* sc, double* x, hipStream_t st, const Slots& sl,
+                              int count) {
+  k_reconstruct<<<dim3(grid_for(16 * (int64_t)ne, kThreads, 1 << 30), count), kThreads, 0, st>>>(
+      ne, xh, zt, zb, sc, x, sl);
   return hipGetLastError();
 }
 
@@ -739,12 +786,12 @@ int refine_blocks(int ne) { return grid_for(ne, 64, kPartStride); }
 template <typename T>
 hipError_t launch_refine_residual(bool first, const double* L64, const int32_t* cols, int ne,
                                   const double* s, const double* z, T* fJ, double* part,
-                                  hipStream_t st) {
-  const int grid = refine_blocks(ne);
+                                  hipStream_t st, const Slots& sl, int count) {
+  const dim3 grid(refine_blocks(ne), count);
   if (first)
-    k_refine_residual<T, true><<<grid, kThreads, 0, st>>>(L64, cols, ne, s, z, fJ, part);
+    k_refine_residual<T, true><<<grid, kThreads, 0, st>>>(L64, cols, ne, s, z, fJ, part, sl);
   else
-    k_refine_residual<T, false><<<grid, kThreads, 0, st>>>(L64, cols, ne, s, z, fJ, part);
+    k_refine_residual<T, false><<<grid, kThreads, 0, st>>>(L64, cols, ne, s, z, fJ, part, sl);
   return hipGetLastError();
 }
 
@@ -826,7 +873,7 @@ hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st) {
 #define DCG_INSTANTIATE(T)                                                                      \
   template hipError_t launch_refine_residual<T>(bool, const double*, const int32_t*, int,      \
                                                 const double*, const double*, T*, double*,     \
-                                                hipStream_t);                                  \
+                                                hipStream_t, const Slots&, int);               \
   template hipError_t launch_refine_update<T>(bool, int64_t, const T*, double*, hipStream_t);  \
   template hipError_t launch_lap<T>(bool, const T*, const int32_t*, int, const T*, const T*, T*, \
                                     hipStream_t);                                              \

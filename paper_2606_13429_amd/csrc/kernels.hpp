@@ -30,7 +30,8 @@ struct Scalars {
   double dr;        // (d, r) of the flexible variant
   double res2;      // ||b - A* x||^2 or the last plain dot
   double s2, r2;    // inner iteration: ||s||^2 and ||s - L z||^2
-  double spare[7];
+  double dt, inv_nu;  // operator parameters of this request (A* = (1/nu) M + dt A_div)
+  double spare[5];
   int32_t breakdown;
   int32_t pad[3];
 };
@@ -48,6 +49,19 @@ enum ReduceOp : int {
 };
 
 constexpr int kPartStride = 1 << 16;   // max blocks of a reducing launch
+constexpr int64_t kSlotPart = 3 * int64_t(kPartStride);   // partial sums per request
+
+// Request addressing of the batched launches: blockIdx.y selects request
+// list[y], whose vectors sit at base + request * stride and whose scalars and
+// partial sums at sc + request, part + request * kSlotPart.  list == nullptr
+// addresses one request (request 0) -- the single-solve path.
+struct Slots {
+  const int32_t* list = nullptr;
+  int64_t tstride = 0;   // tensor vectors, 16 ne FP64
+  int64_t sstride = 0;   // scalar FP64 vectors, 4 ne
+  int64_t lstride = 0;   // finest-level vectors of the level type, 4 ne
+  int64_t ystride = 0;   // finest-level pending outputs, 12 ne
+};
 
 enum AstarMode : int {
   kAstarPlain = 0,   // w = A* x
@@ -61,31 +75,35 @@ int astar_blocks(int ne);     // launch_astar and launch_deflate
 int refine_blocks(int ne);    // launch_refine_residual
 
 hipError_t launch_astar(int mode, const double2* A, const int32_t* cols, const double* M1, int ne,
-                        double dt, double inv_nu, const double* x, const double* p_old,
-                        const double* b, const Scalars* sc, double* p_new, double* w, double* s,
-                        double* part, hipStream_t st);
+                        const double* x, const double* p_old, const double* b, const Scalars* sc,
+                        double* p_new, double* w, double* s, double* part, hipStream_t st,
+                        const Slots& sl = Slots(), int count = 1);
 // q = w - c * (A_div Z) z ; partial (p, q).  With ``prologue``: r = w - c AZ z
 // written to q and to p_out, partials (w, w) and (q, q).
 hipError_t launch_deflate(bool prologue, const double2* AZ, const int32_t* cols, int ne, double c,
                           const double* z, const double* w, const double* p, double* q,
-                          double* p_out, double* part, hipStream_t st);
+                          double* p_out, double* part, hipStream_t st, const Slots& sl = Slots(),
+                          int count = 1);
 // q = AZ y (plain product, no partials)
 hipError_t launch_adivz(const double2* AZ, const int32_t* cols, int ne, const double* y, double* out,
                         hipStream_t st);
 // x += alpha p ; r -= alpha q ; partial (r, r)  [flexible: + (r,q), (p,r)]
 hipError_t launch_cg_update(bool flexible, int64_t nvec, const Scalars* sc, const double* p,
                             const double* q, double* x, double* r, double* part, int* nblocks,
-                            hipStream_t st);
+                            hipStream_t st, const Slots& sl = Slots(), int count = 1);
 // r += a q ; partial (r, r)
 hipError_t launch_axpy_dot(int64_t nvec, double a, const double* q, double* r, double* part,
                            int* nblocks, hipStream_t st);
-hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st);
+hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st,
+                         const Slots& sl = Slots(), int count = 1);
 
-hipError_t launch_zt(int ne, const double* w, double* s, hipStream_t st);
+hipError_t launch_zt(int ne, const double* w, double* s, hipStream_t st, const Slots& sl = Slots(),
+                     int count = 1);
 hipError_t launch_z(int ne, const double* y, double scale, double* v, hipStream_t st);
-// x = (xh - Z (c zt)) + Z (c zb)
-hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const double* zb, double c,
-                              double* x, hipStream_t st);
+// x = (xh - Z (c zt)) + Z (c zb), c = 2 / dt of the request
+hipError_t launch_reconstruct(int ne, const double* xh, const double* zt, const double* zb,
+                              const Scalars* sc, double* x, hipStream_t st,
+                              const Slots& sl = Slots(), int count = 1);
 hipError_t launch_scale(int64_t n, double c, const double* in, double* out, hipStream_t st);
 // f = (1/nu) M (4/3 s1 - 1/3 s2) + c F ; x0 = 2 s1 - s2
 hipError_t launch_bdf2_rhs(int ne, const double* M1, double inv_nu, const double* s1,
@@ -96,7 +114,7 @@ hipError_t launch_bdf2_rhs(int ne, const double* M1, double inv_nu, const double
 template <typename T>
 hipError_t launch_refine_residual(bool first, const double* L64, const int32_t* cols, int ne,
                                   const double* s, const double* z, T* fJ, double* part,
-                                  hipStream_t st);
+                                  hipStream_t st, const Slots& sl = Slots(), int count = 1);
 template <typename T>
 hipError_t launch_refine_update(bool first, int64_t m, const T* zJ, double* z, hipStream_t st);
 
@@ -169,6 +187,6 @@ hipError_t launch_resolve(int ne, bool has_z, const T* z, const T* Ye, T* out, h
 // z64 = (first ? 0 : z64) + (double)((has_z ? z : 0) + (has_y ? pending Ye : 0))
 template <typename T>
 hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T* z, const T* Ye,
-                             double* z64, hipStream_t st);
+                             double* z64, hipStream_t st, const Slots& sl = Slots(), int count = 1);
 
 }  // namespace dcg

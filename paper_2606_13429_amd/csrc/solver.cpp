@@ -278,6 +278,17 @@ LvState run_wcycle_finest(dcg_ctx* h, hipStream_t st) {
   return s;
 }
 
+// Resets the device scalar block and stores the operator parameters dt, 1/nu
+// the kernels read from it.
+void set_params(dcg_ctx* h, hipStream_t st) {
+  Scalars init{};
+  init.dt = h->dt;
+  init.inv_nu = 1.0 / h->nu;
+  *h->ws.sc_host = init;
+  DCG_HIP(hipMemcpyAsync(h->ws.sc, h->ws.sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st));
+  DCG_HIP(hipStreamSynchronize(st));
+}
+
 void read_scalars(dcg_ctx* h, hipStream_t st) {
   DCG_HIP(hipMemcpyAsync(h->ws.sc_host, h->ws.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
   DCG_HIP(hipStreamSynchronize(st));
@@ -382,12 +393,10 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
   const int64_t N = 16 * int64_t(ne);
   const bool flex = h->opt.outer == DCG_OUTER_FCG1;
   const double tol_c = h->opt.c_F * tol;
-  const double c_recon = 2.0 / h->dt;
-  const double inv_nu = 1.0 / h->nu;
   const int nbA = astar_blocks(ne);
   dcg_stats stats{};
   int cycles_total = 0, inner_solves = 0, cycles_outer = 0;
-  DCG_HIP(hipMemsetAsync(ws.sc, 0, sizeof(Scalars), stream));
+  set_params(h, stream);
 
   // prologue: pi(b) = Z E^{-1} Z^T b; f_D = b - A* pi(b) (eq. (defl_sys))
   DCG_HIP(launch_zt(ne, b, ws.s, stream));
@@ -415,7 +424,7 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
     // x_hat_0 = x_0, r_0 = f_D - M_D x_0 with M_D x_0 = A* x_0 - A* Z y_0,
     // y_0 = E^{-1} Z^T A* x_0 (Algorithm 1 applied to the deflated system)
     DCG_HIP(launch_copy<double>(N, x, ws.xh, stream));
-    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu, ws.xh, nullptr, nullptr,
+    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
                          ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
     cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
     ++inner_solves;
@@ -440,7 +449,7 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
       break;
     }
     // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
-    DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu,
+    DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Adiv, m.cols, m.M1, ne,
                          ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
                          stream));
     pidx = 1 - pidx;
@@ -470,12 +479,12 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
   stats.rel_res_recurrence = std::sqrt(std::max(rho, 0.0) / b2);
 
   // epilogue: x = (x_hat - pi(A* x_hat)) + pi(b)  (eq. (x_defl))
-  DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu, ws.xh, nullptr, nullptr,
+  DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
                        ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
   cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
   ++inner_solves;
-  DCG_HIP(launch_reconstruct(ne, ws.xh, ws.zt, ws.zb, c_recon, x, stream));
-  DCG_HIP(launch_astar(kAstarResidual, m.Adiv, m.cols, m.M1, ne, h->dt, inv_nu, x, nullptr, b, ws.sc,
+  DCG_HIP(launch_reconstruct(ne, ws.xh, ws.zt, ws.zb, ws.sc, x, stream));
+  DCG_HIP(launch_astar(kAstarResidual, m.Adiv, m.cols, m.M1, ne, x, nullptr, b, ws.sc,
                        nullptr, ws.w, nullptr, ws.part, stream));
   DCG_HIP(launch_reduce(ws.part, nbA, kRedRes, ws.sc, stream));
   read_scalars(h, stream);
@@ -575,9 +584,10 @@ dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* i
   const int ne = m.ne;
   const double* x = static_cast<const double*>(in);
   double* y = static_cast<double*>(out);
+  if (op == DCG_OP_ASTAR || op == DCG_OP_DEFLATED) set_params(h, st);
   switch (op) {
     case DCG_OP_ASTAR:
-      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, 1.0 / h->nu, x, nullptr,
+      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, x, nullptr,
                            nullptr, h->ws.sc, nullptr, y, nullptr, nullptr, st));
       break;
     case DCG_OP_ZT:
@@ -595,7 +605,7 @@ dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* i
       break;
     }
     case DCG_OP_DEFLATED: {
-      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, h->dt, 1.0 / h->nu, x, nullptr,
+      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, x, nullptr,
                            nullptr, h->ws.sc, nullptr, h->ws.w, h->ws.s, nullptr, st));
       inner(h, h->ws.s, h->ws.zref, h->opt.c_F * kApplyTol, st);
       DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, h->ws.zref, h->ws.w, x, y, nullptr,
