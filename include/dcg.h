@@ -87,6 +87,7 @@ typedef struct {
   int32_t x0_given;    /* 0: x0 = 0; 1: x holds the initial guess on entry    */
   int32_t use_graph;   /* 1: replay each W-cycle as a captured HIP graph [1]  */
   int64_t hbm_budget_bytes; /* server admission budget, 0 = device total      */
+  int32_t max_pending; /* server: unfinished requests before DCG_EAGAIN [4096] */
 } dcg_options;
 
 typedef struct {
@@ -98,7 +99,8 @@ typedef struct {
   double rel_res_recurrence; /* ||r_i|| / ||b|| at exit                       */
   double rel_res_true;     /* ||b - A* x|| / ||b|| after reconstruction       */
   double t_setup_ms;       /* handle setup time (mesh context build/upload)   */
-  double t_solve_ms;       /* wall time of dcg_solve                          */
+  double t_solve_ms;       /* wall time of dcg_solve; server: admission to done */
+  double t_queue_ms;       /* server: submission to admission (0 for dcg_solve) */
 } dcg_stats;
 
 typedef struct dcg_ctx* dcg_handle;
@@ -143,6 +145,12 @@ dcg_status dcg_solve(dcg_handle h, const double* b, double* x, double tol,
  *  DCG_OP_PROLONG     e  (real,m_{k-1}) -      v  (real,m_k) P_k e
  *  DCG_OP_COARSE      f  (real,m_1) -          z  (real,m_1) L_1^{-1} f (FP64 inverse)
  *  DCG_OP_WCYCLE      f  (real,m_k) z0 (real or NULL = 0)  z (real,m_k)  Wcycle_k(f, z0)
+ *  DCG_OP_RAS_BATCH   f  (real,16 m_k) z (real)  z' (real,16 m_k)  DCG_OP_RAS of 16 vectors
+ *  DCG_OP_WCYCLE_BATCH f (real,16 m_k) z0 (or NULL) z (real,16 m_k) DCG_OP_WCYCLE of 16 vectors
+ *
+ * The _BATCH operators run the kernels of the serving engine: 16 level
+ * vectors interleaved as idx = (16 e + c) 4 + j (vector c = 0..15), the RAS
+ * tile solves as MFMA products with the 16 residuals; they need post >= 1.
  *
  * Level operators act on L_k = (2/dt) Z_k (the dt-free Laplacian hierarchy);
  * the hierarchy of Algorithm 2 is Z_k = (dt/2) L_k.  m = 4 n^2, m_k = 4 n_k^2.
@@ -150,7 +158,8 @@ dcg_status dcg_solve(dcg_handle h, const double* b, double* x, double tol,
 typedef enum {
   DCG_OP_ASTAR = 0, DCG_OP_ZT = 1, DCG_OP_Z = 2, DCG_OP_ADIVZ = 3,
   DCG_OP_DEFLATED = 4, DCG_OP_INNER = 5, DCG_OP_LAPLACE = 6, DCG_OP_RAS = 7,
-  DCG_OP_RESTRICT = 8, DCG_OP_PROLONG = 9, DCG_OP_COARSE = 10, DCG_OP_WCYCLE = 11
+  DCG_OP_RESTRICT = 8, DCG_OP_PROLONG = 9, DCG_OP_COARSE = 10, DCG_OP_WCYCLE = 11,
+  DCG_OP_RAS_BATCH = 12, DCG_OP_WCYCLE_BATCH = 13
 } dcg_op;
 
 dcg_status dcg_apply(dcg_handle h, dcg_op op, int32_t level, const void* in,
@@ -200,6 +209,62 @@ dcg_status dcg_bdf2_rhs(dcg_handle h, const double* s1, const double* s2, const 
  * accumulated milliseconds and launch count since the last enable. */
 dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable);
 dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------- serving
+ * A server solves many requests A*_i x_i = b_i concurrently on the current
+ * device by continuous batching.  Requests that share (n, penalty, pre,
+ * post) share one resident mesh context and are advanced together, up to 16
+ * at a time: one launch per step of the outer iteration covers every
+ * request at that step (dt and nu are per-request scalars; A* = (1/nu) C (x)
+ * M_1 + dt A_div is never assembled per request), and the inner W-cycles of
+ * all of them run as one batched cycle whose RAS tile solves (Section 4.2)
+ * are matrix products of each tile inverse with the 16 requests' residuals
+ * (MFMA).  Each request keeps its own convergence tests, so it performs the
+ * iterations of Algorithm 2 / 3 it would perform alone, and its result does
+ * not depend on the other requests of the batch (bitwise).
+ *
+ * opt: precision, outer variant, c_F, max_outer, max_inner, use_graph for
+ * every request; hbm_budget_bytes bounds the device memory of the resident
+ * mesh contexts plus the batch workspaces (a request whose group does not
+ * fit waits until idle groups can be released; one that cannot fit even on
+ * an idle server fails with DCG_ENOMEM); max_pending bounds the unfinished
+ * requests (DCG_EAGAIN beyond).  x0_given is ignored: solves start at 0.
+ * The server runs one host thread and its own HIP streams on the device
+ * current at creation.  Requires post >= 1. */
+dcg_status dcg_server_create(const dcg_options* opt, dcg_server* out);
+
+/* Builds the mesh context of ``mesh`` ahead of traffic (as the first
+ * request of that mesh would); optional. */
+dcg_status dcg_server_prepare(dcg_server s, const dcg_mesh* mesh);
+
+/* Queues one solve; returns at once with *ticket.  b, x: device, length
+ * 16 n^2, FP64, element-major; b must hold its values when this is called
+ * and both must stay allocated until dcg_poll returns a terminal status (b
+ * is copied at admission, x is written at completion).  tol as dcg_solve.
+ * DCG_EAGAIN: max_pending requests are unfinished.  DCG_EINVAL: bad
+ * arguments (checked here, not at admission). */
+dcg_status dcg_submit(dcg_server s, const dcg_mesh* mesh, double dt, double nu,
+                      const double* b, double* x, double tol, uint64_t* ticket);
+
+/* DCG_PENDING while the request is queued or running.  Otherwise returns
+ * its terminal status (as dcg_solve would), fills *st (may be NULL; also
+ * for errors) and forgets the ticket; dcg_last_error(NULL) then gives the
+ * message of a failed request.  DCG_ENOTFOUND: unknown or already
+ * reported ticket. */
+dcg_status dcg_poll(dcg_server s, uint64_t ticket, dcg_stats* st);
+
+/* Device bytes a server group of ``mesh`` occupies in precision ``prec``:
+ * its mesh context plus the workspace of 16 request slots (the quantity the
+ * admission test charges against hbm_budget_bytes); -1 for a bad mesh. */
+int64_t dcg_server_group_bytes(const dcg_mesh* mesh, dcg_precision prec);
+
+/* Steps run so far and the occupied request slots summed over them
+ * (slot_steps / steps = mean batch occupancy). */
+dcg_status dcg_server_counters(dcg_server s, int64_t* steps, int64_t* slot_steps);
+
+/* Stops the server thread (unfinished requests are abandoned: their x is
+ * unspecified) and frees every buffer it owns. */
+dcg_status dcg_server_destroy(dcg_server s);
 
 dcg_status dcg_destroy(dcg_handle h);
 const char* dcg_strerror(dcg_status s);

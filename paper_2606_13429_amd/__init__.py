@@ -8,9 +8,9 @@ if the library has not been built.
 """
 from ._binding import *          # noqa: F401,F403  (the C entry points)
 from ._binding import (DCGError, dcg_defaults, dcg_destroy, dcg_setup, dcg_solve,
-                       DCG_FP64, DCG_MIXED, DCG_OUTER_CG, DCG_OUTER_FCG1, LIB_PATH)
+                       DCG_FP64, DCG_MIXED, DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_PENDING, LIB_PATH)
 
-__all__ = ["Solver", "DCGError", "LIB_PATH"]
+__all__ = ["Solver", "Server", "DCGError", "LIB_PATH"]
 
 
 class Solver:
@@ -41,6 +41,71 @@ class Solver:
     def close(self):
         if self.handle is not None:
             dcg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (dcg_server_create / dcg_submit / dcg_poll).
+
+    >>> srv = Server(prec="mixed")
+    >>> t = srv.submit(n=64, dt=1e-3, b=b, x=x, tol=1e-8)   # returns at once
+    >>> status, stats = srv.wait(t)
+    """
+
+    def __init__(self, prec="mixed", outer="cg", c_F=0.01, max_outer=50000, max_inner=100,
+                 use_graph=True, hbm_budget_bytes=0, max_pending=4096):
+        from ._binding import dcg_server_create
+        _, opt = dcg_defaults()
+        opt.prec = {"mixed": DCG_MIXED, "fp64": DCG_FP64}[prec]
+        opt.outer = {"cg": DCG_OUTER_CG, "fcg1": DCG_OUTER_FCG1}[outer]
+        opt.c_F, opt.max_outer, opt.max_inner = c_F, max_outer, max_inner
+        opt.use_graph, opt.hbm_budget_bytes, opt.max_pending = int(use_graph), hbm_budget_bytes, max_pending
+        self.opt = opt
+        self.handle = dcg_server_create(opt)
+
+    @staticmethod
+    def mesh(n, penalty=10.0, pre=2, post=2):
+        m, _ = dcg_defaults()
+        m.n, m.penalty, m.pre, m.post = n, penalty, pre, post
+        return m
+
+    def prepare(self, n, **mesh_kw):
+        from ._binding import dcg_server_prepare
+        dcg_server_prepare(self.handle, self.mesh(n, **mesh_kw))
+
+    def submit(self, n, dt, b, x, tol=1e-8, nu=1.0, **mesh_kw):
+        from ._binding import dcg_submit
+        return dcg_submit(self.handle, self.mesh(n, **mesh_kw), dt, nu, b, x, tol)
+
+    def poll(self, ticket):
+        from ._binding import dcg_poll
+        return dcg_poll(self.handle, ticket)
+
+    def wait(self, ticket, timeout=None, interval=2e-4):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            status, st = self.poll(ticket)
+            if status != DCG_PENDING:
+                return status, st
+            if timeout is not None and time.perf_counter() - t0 > timeout:
+                raise TimeoutError("request %d still pending" % ticket)
+            time.sleep(interval)
+
+    def counters(self):
+        from ._binding import dcg_server_counters
+        return dcg_server_counters(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            from ._binding import dcg_server_destroy
+            dcg_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -23,7 +23,9 @@ DCG_EINVAL, DCG_ENOMEM, DCG_EDEVICE, DCG_EAGAIN, DCG_ENOTFOUND, DCG_EBREAKDOWN =
 DCG_FP64, DCG_MIXED = 0, 1
 DCG_OUTER_CG, DCG_OUTER_FCG1 = 0, 1
 (DCG_OP_ASTAR, DCG_OP_ZT, DCG_OP_Z, DCG_OP_ADIVZ, DCG_OP_DEFLATED, DCG_OP_INNER, DCG_OP_LAPLACE,
- DCG_OP_RAS, DCG_OP_RESTRICT, DCG_OP_PROLONG, DCG_OP_COARSE, DCG_OP_WCYCLE) = range(12)
+ DCG_OP_RAS, DCG_OP_RESTRICT, DCG_OP_PROLONG, DCG_OP_COARSE, DCG_OP_WCYCLE, DCG_OP_RAS_BATCH,
+ DCG_OP_WCYCLE_BATCH) = range(14)
+BATCH = 16   # vectors of the _BATCH operators and requests per serving batch
 
 
 class dcg_mesh(ctypes.Structure):
@@ -35,7 +37,7 @@ class dcg_options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("outer", ctypes.c_int), ("c_F", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int32)]
 
 
 class dcg_stats(ctypes.Structure):
@@ -43,7 +45,7 @@ class dcg_stats(ctypes.Structure):
                 ("total_wcycles", ctypes.c_int32), ("inner_solves", ctypes.c_int32),
                 ("inner_per_outer", ctypes.c_double), ("rel_res_recurrence", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("t_queue_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -64,6 +66,14 @@ _SIGS = {
     "dcg_bdf2_rhs": (ctypes.c_int, [_h, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "dcg_kernel_timing": (ctypes.c_int, [_h, ctypes.c_int32]),
     "dcg_kernel_timing_read": (ctypes.c_int, [_h, _P(ctypes.c_double), _P(ctypes.c_int64)]),
+    "dcg_server_create": (ctypes.c_int, [_P(dcg_options), _P(_h)]),
+    "dcg_server_prepare": (ctypes.c_int, [_h, _P(dcg_mesh)]),
+    "dcg_submit": (ctypes.c_int, [_h, _P(dcg_mesh), ctypes.c_double, ctypes.c_double, _vp, _vp,
+                                  ctypes.c_double, _P(ctypes.c_uint64)]),
+    "dcg_poll": (ctypes.c_int, [_h, ctypes.c_uint64, _P(dcg_stats)]),
+    "dcg_server_counters": (ctypes.c_int, [_h, _P(ctypes.c_int64), _P(ctypes.c_int64)]),
+    "dcg_server_group_bytes": (ctypes.c_int64, [_P(dcg_mesh), ctypes.c_int]),
+    "dcg_server_destroy": (ctypes.c_int, [_h]),
     "dcg_destroy": (ctypes.c_int, [_h]),
     "dcg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "dcg_last_error": (ctypes.c_char_p, [_h]),
@@ -192,6 +202,50 @@ def dcg_kernel_timing_read(handle):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(_lib.dcg_kernel_timing_read(handle, ctypes.byref(ms), ctypes.byref(n)), handle)
     return ms.value, n.value
+
+
+def dcg_server_create(opt=None):
+    s = _h()
+    _check(_lib.dcg_server_create(ctypes.byref(opt) if opt is not None else None, ctypes.byref(s)))
+    return s
+
+
+def dcg_server_prepare(server, mesh):
+    return _check(_lib.dcg_server_prepare(server, ctypes.byref(mesh)))
+
+
+def dcg_submit(server, mesh, dt, nu, b, x, tol):
+    """Returns the ticket; raises DCGError (e.g. DCG_EAGAIN) on negative status."""
+    t = ctypes.c_uint64()
+    N = 16 * mesh.n * mesh.n
+    _check(_lib.dcg_submit(server, ctypes.byref(mesh), dt, nu, _ptr(b, _f64(), N, "b"),
+                           _ptr(x, _f64(), N, "x"), tol, ctypes.byref(t)))
+    return t.value
+
+
+def dcg_poll(server, ticket):
+    """Returns (status, dcg_stats); status DCG_PENDING while running.  A
+    failed request returns its negative status (no exception) with the
+    message in dcg_last_error(); an unknown ticket raises DCGError."""
+    st = dcg_stats()
+    status = _lib.dcg_poll(server, ticket, ctypes.byref(st))
+    if status == DCG_ENOTFOUND:
+        raise DCGError(status, dcg_last_error())
+    return status, st
+
+
+def dcg_server_group_bytes(mesh, prec=DCG_MIXED):
+    return _lib.dcg_server_group_bytes(ctypes.byref(mesh), prec)
+
+
+def dcg_server_counters(server):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.dcg_server_counters(server, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def dcg_server_destroy(server):
+    return _lib.dcg_server_destroy(server)
 
 
 def dcg_destroy(handle):

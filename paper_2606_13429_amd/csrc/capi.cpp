@@ -5,7 +5,7 @@
 #include <cstring>
 #include <string>
 
-#include "runtime.hpp"
+#include "server.hpp"
 
 namespace {
 
@@ -46,6 +46,15 @@ bool valid_mesh(const dcg_mesh& m, std::string& why) {
   return true;
 }
 
+dcg_status check_options(const dcg_options& o) {
+  if (o.prec != DCG_FP64 && o.prec != DCG_MIXED) return fail(nullptr, DCG_EINVAL, "bad precision");
+  if (o.outer != DCG_OUTER_CG && o.outer != DCG_OUTER_FCG1)
+    return fail(nullptr, DCG_EINVAL, "bad outer variant");
+  if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
+    return fail(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
+  return DCG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -67,6 +76,7 @@ void dcg_defaults(dcg_mesh* mesh, dcg_options* opt) {
     opt->x0_given = 0;
     opt->use_graph = 1;
     opt->hbm_budget_bytes = 0;
+    opt->max_pending = 4096;
   }
 }
 
@@ -83,10 +93,7 @@ dcg_status dcg_setup(const dcg_mesh* mesh, double dt, double nu, const dcg_optio
   dcg_options o;
   dcg_defaults(nullptr, &o);
   if (opt) o = *opt;
-  if (o.prec != DCG_FP64 && o.prec != DCG_MIXED) return fail(nullptr, DCG_EINVAL, "bad precision");
-  if (o.outer != DCG_OUTER_CG && o.outer != DCG_OUTER_FCG1) return fail(nullptr, DCG_EINVAL, "bad outer variant");
-  if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
-    return fail(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
+  if (const dcg_status cs = check_options(o); cs != DCG_OK) return cs;
   dcg_ctx* h = nullptr;
   const dcg_status st = guarded(nullptr, [&]() {
     const auto t0 = std::chrono::steady_clock::now();
@@ -209,6 +216,76 @@ dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launc
   if (total_ms) *total_ms = h->ktime_ms;
   if (launches) *launches = h->klaunches;
   return DCG_OK;
+}
+
+dcg_status dcg_server_create(const dcg_options* opt, dcg_server* out) {
+  if (!out) return fail(nullptr, DCG_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  dcg_options o;
+  dcg_defaults(nullptr, &o);
+  if (opt) o = *opt;
+  if (const dcg_status cs = check_options(o); cs != DCG_OK) return cs;
+  if (o.max_pending < 1) return fail(nullptr, DCG_EINVAL, "max_pending must be >= 1");
+  if (o.hbm_budget_bytes < 0) return fail(nullptr, DCG_EINVAL, "hbm_budget_bytes must be >= 0");
+  return guarded(nullptr, [&]() {
+    auto s = std::make_unique<dcg_srv>();
+    s->server = std::make_unique<dcg::Server>(o);
+    *out = s.release();
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg_server_prepare(dcg_server s, const dcg_mesh* mesh) {
+  if (!s || !mesh) return fail(nullptr, DCG_EINVAL, "server and mesh must not be NULL");
+  std::string why;
+  if (!valid_mesh(*mesh, why)) return fail(nullptr, DCG_EINVAL, why);
+  return guarded(nullptr, [&]() {
+    s->server->prepare(*mesh);
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg_submit(dcg_server s, const dcg_mesh* mesh, double dt, double nu, const double* b,
+                      double* x, double tol, uint64_t* ticket) {
+  if (!s || !mesh || !ticket) return fail(nullptr, DCG_EINVAL, "server, mesh and ticket must not be NULL");
+  std::string why;
+  if (!valid_mesh(*mesh, why)) return fail(nullptr, DCG_EINVAL, why);
+  if (mesh->post < 1) return fail(nullptr, DCG_EINVAL, "the server needs post >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(nullptr, DCG_EINVAL, "dt must be positive");
+  if (!(nu > 0.0) || !std::isfinite(nu)) return fail(nullptr, DCG_EINVAL, "nu must be positive");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(nullptr, DCG_EINVAL, "tol must be finite and >= 0");
+  if (!b || !x) return fail(nullptr, DCG_EINVAL, "b and x must not be NULL");
+  return guarded(nullptr, [&]() { return s->server->submit(*mesh, dt, nu, b, x, tol, ticket); });
+}
+
+dcg_status dcg_poll(dcg_server s, uint64_t ticket, dcg_stats* st) {
+  if (!s) return fail(nullptr, DCG_EINVAL, "NULL server");
+  return guarded(nullptr, [&]() {
+    std::string err;
+    const dcg_status r = s->server->poll(ticket, st, &err);
+    if (r < 0) g_last_error = err;
+    return r;
+  });
+}
+
+int64_t dcg_server_group_bytes(const dcg_mesh* mesh, dcg_precision prec) {
+  std::string why;
+  if (!mesh || !valid_mesh(*mesh, why) || (prec != DCG_FP64 && prec != DCG_MIXED)) return -1;
+  return dcg::Server::group_bytes(mesh->n, prec == DCG_MIXED);
+}
+
+dcg_status dcg_server_counters(dcg_server s, int64_t* steps, int64_t* slot_steps) {
+  if (!s) return fail(nullptr, DCG_EINVAL, "NULL server");
+  s->server->counters(steps, slot_steps);
+  return DCG_OK;
+}
+
+dcg_status dcg_server_destroy(dcg_server s) {
+  if (!s) return fail(nullptr, DCG_EINVAL, "NULL server");
+  return guarded(nullptr, [&]() {
+    delete s;
+    return DCG_OK;
+  });
 }
 
 dcg_status dcg_destroy(dcg_handle h) {

@@ -254,6 +254,14 @@ std::shared_ptr<MeshContext> get_context(int n, double penalty, bool fp32) {
   return ctx;
 }
 
+void release_context_if_unused(int n, double penalty) {
+  int device = 0;
+  DCG_HIP(hipGetDevice(&device));
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(Key{device, n, penalty});
+  if (it != g_cache.end() && it->second.use_count() == 1) g_cache.erase(it);
+}
+
 void clear_context_cache() {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache.clear();

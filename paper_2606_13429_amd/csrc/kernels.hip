@@ -450,18 +450,18 @@ __global__ __launch_bounds__(kThreads) void k_refine_residual(
     double acc = 0.0;
     if (!FIRST) {
 #pragma unroll
-      for (int slot = 0; slot < 5; ++slot) {
-        const int col = cols[slot * ne + e];
+      for (int sn = 0; sn < 5; ++sn) {
+        const int col = cols[sn * ne + e];
         if (col < 0) continue;
         double l[4], zc[4];
-        ld4(L + (((int64_t)slot * ne + e) * 4 + a) * 4, l);
+        ld4(L + (((int64_t)sn * ne + e) * 4 + a) * 4, l);
         ld4(z + 4 * (int64_t)col, zc);
         acc += l[0] * zc[0] + l[1] * zc[1] + l[2] * zc[2] + l[3] * zc[3];
       }
     }
     const int64_t i = 4 * (int64_t)e + a;
     const double rv = s[i] - acc;
-    fJ[i] = static_cast<T>(rv);
+    fJ[e * sl.lsq + a] = static_cast<T>(rv);
     nrm += rv * rv;
   }
   const double t = block_sum(nrm, lds);

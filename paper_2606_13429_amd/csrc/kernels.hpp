@@ -54,14 +54,22 @@ constexpr int64_t kSlotPart = 3 * int64_t(kPartStride);   // partial sums per re
 // Request addressing of the batched launches: blockIdx.y selects request
 // list[y], whose vectors sit at base + request * stride and whose scalars and
 // partial sums at sc + request, part + request * kSlotPart.  list == nullptr
-// addresses one request (request 0) -- the single-solve path.
+// addresses one request (request 0) -- the single-solve path.  Finest-level
+// vectors of the level type hold square e of the request at e * lsq +
+// request * lstride: lsq = 4, lstride = 0 for one request, lsq = 4 kBatch,
+// lstride = 4 for the request-interleaved layout of the batched cycle.
 struct Slots {
   const int32_t* list = nullptr;
   int64_t tstride = 0;   // tensor vectors, 16 ne FP64
   int64_t sstride = 0;   // scalar FP64 vectors, 4 ne
-  int64_t lstride = 0;   // finest-level vectors of the level type, 4 ne
-  int64_t ystride = 0;   // finest-level pending outputs, 12 ne
+  int64_t lstride = 0;   // finest-level vectors of the level type
+  int64_t lsq = 4;
 };
+
+// Requests of one batched multigrid cycle: the N dimension of the MFMA tiles
+// of the batched RAS step.  Batched level vectors are request-interleaved,
+// [square][request][4] (pending outputs [3 square + k][request][4]).
+constexpr int kBatch = 16;
 
 enum AstarMode : int {
   kAstarPlain = 0,   // w = A* x
@@ -185,8 +193,23 @@ hipError_t launch_restrict_res(const RestrictArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_resolve(int ne, bool has_z, const T* z, const T* Ye, T* out, hipStream_t st);
 // z64 = (first ? 0 : z64) + (double)((has_z ? z : 0) + (has_y ? pending Ye : 0))
+// (z and Ye addressed through sl.lsq / sl.lstride)
 template <typename T>
 hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T* z, const T* Ye,
                              double* z64, hipStream_t st, const Slots& sl = Slots(), int count = 1);
+
+// ------------------------------------------------------------ batched cycle
+// The same steps on kBatch request-interleaved columns (mg_batch.hip): the
+// RAS step multiplies each tile inverse into the 128 x kBatch residual block
+// with MFMA, the coarsest solve is a 1024 x 1024 by 1024 x kBatch FP64 MFMA
+// product.  Column c of every output depends on column c of the inputs only.
+template <typename T>
+hipError_t launch_sweep_b(const SweepArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict_res_b(const RestrictArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_coarse_b(const double* inv, const T* f, T* z, hipStream_t st);
+template <typename T>
+hipError_t launch_resolve_b(int ne, bool has_z, const T* z, const T* Ye, T* out, hipStream_t st);
 
 }  // namespace dcg

@@ -25,81 +25,16 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "mg_common.hpp"
 
 namespace dcg {
 namespace {
+using namespace mg;
 
 constexpr int kThreads = 256;
 #ifndef DCG_SWEEP_CHUNK1
 #define DCG_SWEEP_CHUNK1 8
 #endif
-
-__device__ inline void ld4(const float* p, float v[4]) {
-  const float4 t = *reinterpret_cast<const float4*>(p);
-  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-}
-__device__ inline void ld4(const double* p, double v[4]) {
-  const double2 a = reinterpret_cast<const double2*>(p)[0];
-  const double2 b = reinterpret_cast<const double2*>(p)[1];
-  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-}
-__device__ inline void st4(float* p, const float v[4]) {
-  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-__device__ inline void st4(double* p, const double v[4]) {
-  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
-  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
-}
-
-// Coefficient of coarse corner A at fine corner a of child ch (exact).
-template <typename T>
-__device__ inline T pcoef(int ch, int a, int A) {
-  const int px = (ch & 1) + (a & 1), py = (ch >> 1) + (a >> 1);
-  const int wx = (A & 1) ? px : 2 - px, wy = (A >> 1) ? py : 2 - py;
-  return T(wx * wy) * T(0.25);
-}
-
-// Position (relative to the tile origin) of block slot p < 32.
-__device__ inline void slot_pos(int p, int& px, int& py) {
-  if (p < 16) { px = p & 3; py = p >> 2; }
-  else if (p < 20) { px = -1; py = p - 16; }
-  else if (p < 24) { px = 4; py = p - 20; }
-  else if (p < 28) { px = p - 24; py = -1; }
-  else { px = p - 28; py = 4; }
-}
-
-// Extended slot (0..51) of the position, -1 outside the pattern.
-__device__ inline int pos_slot(int px, int py) {
-  const bool cx = px >= 0 && px < 4, cy = py >= 0 && py < 4;
-  if (cx && cy) return py * 4 + px;
-  if (cy) {
-    if (px == -1) return 16 + py;
-    if (px == 4) return 20 + py;
-    if (px == -2) return 32 + py;
-    if (px == 5) return 36 + py;
-    return -1;
-  }
-  if (cx) {
-    if (py == -1) return 24 + px;
-    if (py == 4) return 28 + px;
-    if (py == -2) return 40 + px;
-    if (py == 5) return 44 + px;
-    return -1;
-  }
-  if (px == -1 && py == -1) return 48;
-  if (px == 4 && py == -1) return 49;
-  if (px == -1 && py == 4) return 50;
-  if (px == 4 && py == 4) return 51;
-  return -1;
-}
-
-__device__ inline int nbr_slot(int p, int s) {
-  int px, py;
-  slot_pos(p, px, py);
-  const int dx = s == 1 ? -1 : (s == 2 ? 1 : 0);
-  const int dy = s == 3 ? -1 : (s == 4 ? 1 : 0);
-  return pos_slot(px + dx, py + dy);
-}
 
 // z of square e after the pending update (and the pending prolongation).
 // Pending tile outputs are stored per square: Ye[e][k][4] holds the output
@@ -135,25 +70,6 @@ __device__ inline void current_z(const SweepArgs<T>& a, int e, T z[4]) {
       z[j] += pcoef<T>(ch, j, 0) * ec[0] + pcoef<T>(ch, j, 1) * ec[1] +
               pcoef<T>(ch, j, 2) * ec[2] + pcoef<T>(ch, j, 3) * ec[3];
   }
-}
-
-// Position (relative to the tile origin) of extended slot q < 52.
-__device__ inline void ext_pos(int q, int& px, int& py) {
-  if (q < 32) { slot_pos(q, px, py); return; }
-  if (q < 36) { px = -2; py = q - 32; }
-  else if (q < 40) { px = 5; py = q - 36; }
-  else if (q < 44) { px = q - 40; py = -2; }
-  else if (q < 48) { px = q - 44; py = 5; }
-  else { px = (q & 1) ? 4 : -1; py = (q < 50) ? -1 : 4; }
-}
-
-// Square of extended slot q of tile t on an n x n grid (-1 outside).
-__device__ inline int ext_square(int t, int q, int n) {
-  const int tpr = n >> 2;
-  int px, py;
-  ext_pos(q, px, py);
-  const int x = 4 * (t % tpr) + px, y = 4 * (t / tpr) + py;
-  return (x < 0 || y < 0 || x >= n || y >= n) ? -1 : y * n + x;
 }
 
 // Packed symmetric tile inverse: (L_k)_t^{-1} is stored as its 36 upper
@@ -432,14 +348,15 @@ __global__ __launch_bounds__(kThreads) void k_refine_add(int ne, int first, int 
                                                          double* __restrict__ z64, Slots sl) {
   const int slot = sl.list ? sl.list[blockIdx.y] : 0;
   z += slot * sl.lstride;
-  Ye += slot * sl.ystride;
+  Ye += slot * sl.lstride;
   z64 += slot * sl.sstride;
   const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (i >= 4 * (int64_t)ne) return;
   const int64_t e = i >> 2;
   const int j = int(i & 3);
-  T v = has_z ? z[i] : T(0);
-  if (has_y) v = ((v + Ye[12 * e + j]) + Ye[12 * e + 4 + j]) + Ye[12 * e + 8 + j];
+  const int64_t q = sl.lsq;
+  T v = has_z ? z[e * q + j] : T(0);
+  if (has_y) v = ((v + Ye[3 * e * q + j]) + Ye[(3 * e + 1) * q + j]) + Ye[(3 * e + 2) * q + j];
   const double d = static_cast<double>(v);
   z64[i] = first ? d : z64[i] + d;
 }

@@ -69,8 +69,24 @@ struct MeshContext {
 // uploading it on first use.
 std::shared_ptr<MeshContext> get_context(int n, double penalty, bool fp32);
 void clear_context_cache();
+// Drops the cached context of (current device, n, penalty) when nothing but
+// the cache holds it.
+void release_context_if_unused(int n, double penalty);
 
-// Per-handle device workspace, sized for one mesh and one precision.
+struct Workspace;
+
+// Multigrid level buffers of one cycle instance (level real type, index
+// k - 1; z and Y double-buffered).  batched: kBatch request-interleaved
+// columns per vector.
+struct LevelBuffers {
+  bool batched = false;
+  std::vector<void*> f, rr, z[2], Y[2];
+  // Allocates every level of ``m`` through ws.alloc; the pending-output
+  // buffers are zeroed once (cover slots no block uses are never written).
+  void allocate(const MeshContext& m, bool fp32, bool batch, Workspace& ws);
+};
+
+// Device workspace of one solver handle (one request) or one serving batch.
 struct Workspace {
   int ne = 0;
   size_t bytes = 0;
@@ -80,8 +96,8 @@ struct Workspace {
   double* part = nullptr;                 // [3][kPartStride]
   Scalars* sc = nullptr;                  // device
   Scalars* sc_host = nullptr;             // pinned host mirror
-  // level buffers (level real type), index k - 1; z and Y double-buffered
-  std::vector<void*> f, rr, z[2], Y[2];
+  LevelBuffers lvb;                       // W-cycle level buffers
+  LevelBuffers lvb_batch;                 // batched level operators (allocated on first use)
   void* alloc(size_t bytes);
   void release();
   ~Workspace();

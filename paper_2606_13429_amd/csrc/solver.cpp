@@ -8,7 +8,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "runtime.hpp"
+#include "wcycle.hpp"
 
 namespace dcg {
 
@@ -28,6 +28,30 @@ void Workspace::release() {
 }
 
 Workspace::~Workspace() { release(); }
+
+void LevelBuffers::allocate(const MeshContext& m, bool fp32, bool batch, Workspace& ws) {
+  batched = batch;
+  const size_t rs = fp32 ? sizeof(float) : sizeof(double);
+  const size_t cols = batch ? kBatch : 1;
+  f.assign(m.J, nullptr);
+  rr.assign(m.J, nullptr);
+  for (int b = 0; b < 2; ++b) {
+    z[b].assign(m.J, nullptr);
+    Y[b].assign(m.J, nullptr);
+  }
+  for (int k = 1; k <= m.J; ++k) {
+    const size_t ne = size_t(m.lv[k - 1].ne);
+    f[k - 1] = ws.alloc(rs * 4 * ne * cols);
+    if (!batch) rr[k - 1] = ws.alloc(rs * 4 * ne);
+    for (int b = 0; b < 2; ++b) {
+      z[b][k - 1] = ws.alloc(rs * 4 * ne * cols);
+      if (k >= 2) {
+        Y[b][k - 1] = ws.alloc(rs * 12 * ne * cols);
+        DCG_HIP(hipMemset(Y[b][k - 1], 0, rs * 12 * ne * cols));
+      }
+    }
+  }
+}
 
 }  // namespace dcg
 
@@ -49,160 +73,15 @@ namespace {
 constexpr double kTwo = 2.0;   // Z^T A* Z = (dt/2) L  =>  A* Z (2/dt) = 2 A_div Z
 constexpr double kApplyTol = 1e-8;   // outer tolerance assumed by DCG_OP_INNER / DEFLATED
 
-size_t real_size(bool fp32) { return fp32 ? sizeof(float) : sizeof(double); }
-
 template <typename T>
-T* lvbuf(std::vector<void*>& v, int k) {
-  return static_cast<T*>(v[k - 1]);
-}
-
-template <typename T>
-const T* level_L(const DeviceLevel& d);
-template <>
-const float* level_L<float>(const DeviceLevel& d) { return d.L32; }
-template <>
-const double* level_L<double>(const DeviceLevel& d) { return d.L64; }
-template <typename T>
-const T* level_dw(const DeviceLevel& d);
-template <>
-const float* level_dw<float>(const DeviceLevel& d) { return d.dw32; }
-template <>
-const double* level_dw<double>(const DeviceLevel& d) { return d.dw64; }
-template <typename T>
-const T* level_F(const DeviceLevel& d);
-template <>
-const float* level_F<float>(const DeviceLevel& d) { return d.F32; }
-template <>
-const double* level_F<double>(const DeviceLevel& d) { return d.F64; }
-
-// ------------------------------------------------------------ W-cycle
-// State of a level's iterate between launches: z = (has_z ? z[zb] : 0)
-// + (has_y ? pending tile outputs Y[yb] : 0).  The host replays the same
-// deterministic state sequence for every cycle, so a captured graph stays
-// valid across replays.
-struct LvState {
-  bool has_z = false, has_y = false;
-  int zb = 0, yb = 0;
-};
-
-template <typename T>
-T* zbuf(dcg_ctx* h, int k, int b) { return static_cast<T*>(h->ws.z[b][k - 1]); }
-template <typename T>
-T* ybuf(dcg_ctx* h, int k, int b) { return static_cast<T*>(h->ws.Y[b][k - 1]); }
-
-int waves_per_tile(int tiles) { return tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4); }
-
-// One RAS step z <- z + S_k (f - L_k z) of level k; ``coarse`` (optional)
-// is the state of level k-1 whose prolongation P e is added first.
-template <typename T>
-void sweep_step(dcg_ctx* h, int k, LvState& s, const LvState* coarse, hipStream_t st) {
-  MeshContext& m = *h->mesh;
-  const DeviceLevel& d = m.lv[k - 1];
-  SweepArgs<T> a;
-  a.F = level_F<T>(d);
-  a.dw = level_dw<T>(d);
-  a.ext = d.tile_ext;
-  a.tiles = d.tiles;
-  a.n = d.n;
-  a.ne = d.ne;
-  a.L = level_L<T>(d);
-  a.cols = d.cols;
-  a.dst = d.tile_dst;
-  a.f = lvbuf<T>(h->ws.f, k);
-  a.has_z = s.has_z;
-  a.has_y = s.has_y;
-  a.z_old = zbuf<T>(h, k, s.zb);
-  a.Y_old = ybuf<T>(h, k, s.yb);
-  if (coarse) {
-    a.prol = 1;
-    a.nc = d.n / 2;
-    a.zc = zbuf<T>(h, k - 1, coarse->zb);
-    a.c_has_y = coarse->has_y;
-    if (coarse->has_y) a.Yc = ybuf<T>(h, k - 1, coarse->yb);
+Cycle<T> make_cycle(dcg_ctx* h) {
+  Cycle<T> c(*h->mesh, h->ws.lvb, h->mp.pre, h->mp.post);
+  if (h->ktime) {
+    c.timer.ev = h->kev;
+    c.timer.max = dcg_ctx::kMaxTimed;
+    c.timer.rec = &h->krec;
   }
-  const bool changes = s.has_y || coarse != nullptr;
-  const int zb_new = changes ? 1 - s.zb : s.zb;
-  a.write_z = changes;
-  a.z_new = zbuf<T>(h, k, zb_new);
-  a.Y_new = ybuf<T>(h, k, 1 - s.yb);
-  const bool timed = h->ktime && k == m.J && h->krec < dcg_ctx::kMaxTimed;
-  if (timed) DCG_HIP(hipEventRecord(h->kev[2 * h->krec], st));
-  DCG_HIP(launch_sweep<T>(a, waves_per_tile(d.tiles), st));
-  if (timed) DCG_HIP(hipEventRecord(h->kev[2 * h->krec++ + 1], st));
-  s.has_z = s.has_z || changes;
-  s.zb = zb_new;
-  s.has_y = true;
-  s.yb = 1 - s.yb;
-}
-
-// Resolves the pending update and restricts the residual:
-// f_{k-1} = P_k^T (f_k - L_k z).
-template <typename T>
-void restrict_step(dcg_ctx* h, int k, LvState& s, hipStream_t st) {
-  const DeviceLevel& d = h->mesh->lv[k - 1];
-  RestrictArgs<T> a;
-  a.n = d.n;
-  a.ne = d.ne;
-  a.L = level_L<T>(d);
-  a.cols = d.cols;
-  a.f = lvbuf<T>(h->ws.f, k);
-  a.has_z = s.has_z;
-  a.has_y = s.has_y;
-  a.z_old = zbuf<T>(h, k, s.zb);
-  a.Y_old = ybuf<T>(h, k, s.yb);
-  a.write_z = s.has_y;
-  a.z_new = zbuf<T>(h, k, 1 - s.zb);
-  a.rc = lvbuf<T>(h->ws.f, k - 1);
-  DCG_HIP(launch_restrict_res<T>(a, st));
-  if (s.has_y) {
-    s.zb = 1 - s.zb;
-    s.has_z = true;
-  }
-  s.has_y = false;
-}
-
-template <typename T>
-void coarse_correction(dcg_ctx* h, int k, LvState& c, hipStream_t st);
-
-// Level k W-cycle (Algorithm 4) on f_k from the iterate described by ``s``.
-template <typename T>
-void wcycle(dcg_ctx* h, int k, LvState& s, hipStream_t st) {
-  MeshContext& m = *h->mesh;
-  if (k == 1) {   // exact coarsest solve; the initial guess is irrelevant
-    DCG_HIP(launch_coarse<T>(m.coarse_inv, lvbuf<T>(h->ws.f, 1), zbuf<T>(h, 1, 0), st));
-    s = LvState();
-    s.has_z = true;
-    return;
-  }
-  const DeviceLevel& d = m.lv[k - 1];
-  for (int i = 0; i < h->mp.pre; ++i) sweep_step<T>(h, k, s, nullptr, st);
-  restrict_step<T>(h, k, s, st);
-  LvState c;                                     // coarse iterate starts at 0
-  coarse_correction<T>(h, k, c, st);
-  if (h->mp.post > 0) {
-    sweep_step<T>(h, k, s, &c, st);              // prolongation fused in
-    for (int i = 1; i < h->mp.post; ++i) sweep_step<T>(h, k, s, nullptr, st);
-  } else {
-    // no post-smoothing: resolve the coarse iterate, then z += P e
-    T* e = lvbuf<T>(h->ws.rr, k - 1);
-    if (c.has_y)
-      DCG_HIP(launch_resolve<T>(m.lv[k - 2].ne, c.has_z, zbuf<T>(h, k - 1, c.zb),
-                                ybuf<T>(h, k - 1, c.yb), e, st));
-    else
-      DCG_HIP(launch_copy<T>(4 * int64_t(m.lv[k - 2].ne), zbuf<T>(h, k - 1, c.zb), e, st));
-    if (!s.has_z) DCG_HIP(launch_fill<T>(4 * int64_t(d.ne), T(0), zbuf<T>(h, k, s.zb), st));
-    DCG_HIP(launch_prolong<T>(d.n / 2, e, zbuf<T>(h, k, s.zb), st));
-    s.has_z = true;
-  }
-}
-
-// The two coarse W-cycles of level k-1 (Algorithm 4: e_bar from 0, then e
-// from e_bar).  On level 1 both calls return the same exact solve, so the
-// second is skipped.
-template <typename T>
-void coarse_correction(dcg_ctx* h, int k, LvState& c, hipStream_t st) {
-  wcycle<T>(h, k - 1, c, st);
-  if (k - 1 >= 2) wcycle<T>(h, k - 1, c, st);
+  return c;
 }
 
 // Adds the elapsed times of the event pairs recorded by the last W-cycle
@@ -226,21 +105,21 @@ template <typename T>
 LvState run_wcycle_finest(dcg_ctx* h, hipStream_t st) {
   MeshContext& m = *h->mesh;
   const int J = m.J;
+  const Cycle<T> cyc = make_cycle<T>(h);
   h->krec = 0;
   LvState s;
   if (J == 1 || !h->opt.use_graph) {
-    wcycle<T>(h, J, s, st);
+    cyc.wcycle(J, s, st);
     return s;
   }
-  const DeviceLevel& d = m.lv[J - 1];
-  for (int i = 0; i < h->mp.pre; ++i) sweep_step<T>(h, J, s, nullptr, st);
-  restrict_step<T>(h, J, s, st);
+  for (int i = 0; i < h->mp.pre; ++i) cyc.sweep_step(J, s, nullptr, st);
+  cyc.restrict_step(J, s, st);
   if (!h->wgraph) {
     hipGraph_t g = nullptr;
     LvState c;
     DCG_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
     try {
-      coarse_correction<T>(h, J, c, h->capture_stream);
+      cyc.coarse_correction(J, c, h->capture_stream);
     } catch (...) {
       (void)hipStreamEndCapture(h->capture_stream, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -261,20 +140,7 @@ LvState run_wcycle_finest(dcg_ctx* h, hipStream_t st) {
   c.has_y = h->graph_state[1];
   c.zb = h->graph_state[2];
   c.yb = h->graph_state[3];
-  if (h->mp.post > 0) {
-    sweep_step<T>(h, J, s, &c, st);
-    for (int i = 1; i < h->mp.post; ++i) sweep_step<T>(h, J, s, nullptr, st);
-  } else {
-    T* e = lvbuf<T>(h->ws.rr, J - 1);
-    if (c.has_y)
-      DCG_HIP(launch_resolve<T>(m.lv[J - 2].ne, c.has_z, zbuf<T>(h, J - 1, c.zb),
-                                ybuf<T>(h, J - 1, c.yb), e, st));
-    else
-      DCG_HIP(launch_copy<T>(4 * int64_t(m.lv[J - 2].ne), zbuf<T>(h, J - 1, c.zb), e, st));
-    if (!s.has_z) DCG_HIP(launch_fill<T>(4 * int64_t(d.ne), T(0), zbuf<T>(h, J, s.zb), st));
-    DCG_HIP(launch_prolong<T>(d.n / 2, e, zbuf<T>(h, J, s.zb), st));
-    s.has_z = true;
-  }
+  cyc.post_smooth(J, s, c, st);
   return s;
 }
 
@@ -305,7 +171,7 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
   MeshContext& m = *h->mesh;
   const DeviceLevel& fine = m.lv[m.J - 1];
   const int64_t mlen = 4 * int64_t(fine.ne);
-  T* fJ = lvbuf<T>(h->ws.f, m.J);
+  T* fJ = static_cast<T*>(h->ws.lvb.f[m.J - 1]);
   const int nb = refine_blocks(fine.ne);
   DCG_HIP(launch_refine_residual<T>(true, fine.L64, fine.cols, fine.ne, s, nullptr, fJ, h->ws.part, st));
   DCG_HIP(launch_reduce(h->ws.part, nb, kRedS2, h->ws.sc, st));
@@ -318,8 +184,9 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
     const double lim = tol_c * tol_c * s2;
     while (cycles < h->opt.max_inner && r2 > lim) {
       const LvState fs = run_wcycle_finest<T>(h, st);
-      DCG_HIP(launch_refine_add<T>(fine.ne, cycles == 0, fs.has_z, fs.has_y, zbuf<T>(h, m.J, fs.zb),
-                                   ybuf<T>(h, m.J, fs.yb), z, st));
+      DCG_HIP(launch_refine_add<T>(fine.ne, cycles == 0, fs.has_z, fs.has_y,
+                                   static_cast<T*>(h->ws.lvb.z[fs.zb][m.J - 1]),
+                                   static_cast<T*>(h->ws.lvb.Y[fs.yb][m.J - 1]), z, st));
       DCG_HIP(launch_refine_residual<T>(false, fine.L64, fine.cols, fine.ne, s, z, fJ, h->ws.part, st));
       DCG_HIP(launch_reduce(h->ws.part, nb, kRedR2, h->ws.sc, st));
       read_scalars(h, st);
@@ -357,26 +224,7 @@ void handle_init(dcg_ctx* h) {
   DCG_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.sc_host), sizeof(Scalars), hipHostMallocDefault));
   std::memset(ws.sc_host, 0, sizeof(Scalars));
   DCG_HIP(hipMemcpy(ws.sc, ws.sc_host, sizeof(Scalars), hipMemcpyHostToDevice));
-  const size_t rs = real_size(h->fp32);
-  ws.f.assign(m.J, nullptr);
-  ws.rr.assign(m.J, nullptr);
-  for (int b = 0; b < 2; ++b) {
-    ws.z[b].assign(m.J, nullptr);
-    ws.Y[b].assign(m.J, nullptr);
-  }
-  for (int k = 1; k <= m.J; ++k) {
-    const DeviceLevel& d = m.lv[k - 1];
-    ws.f[k - 1] = ws.alloc(rs * 4 * d.ne);
-    ws.rr[k - 1] = ws.alloc(rs * 4 * d.ne);
-    for (int b = 0; b < 2; ++b) {
-      ws.z[b][k - 1] = ws.alloc(rs * 4 * d.ne);
-      if (k >= 2) {
-        // pending tile outputs per square [ne][3][4]; slots no block uses stay zero
-        ws.Y[b][k - 1] = ws.alloc(rs * 12 * size_t(d.ne));
-        DCG_HIP(hipMemset(ws.Y[b][k - 1], 0, rs * 12 * size_t(d.ne)));
-      }
-    }
-  }
+  ws.lvb.allocate(m, h->fp32, false, ws);
   DCG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
 }
 
@@ -527,6 +375,7 @@ void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, 
   const int64_t mk = 4 * int64_t(d.ne);
   const T* x = static_cast<const T*>(in);
   T* y = static_cast<T*>(out);
+  const Cycle<T> cyc(m, h->ws.lvb, h->mp.pre, h->mp.post);
   switch (op) {
     case DCG_OP_LAPLACE:
       DCG_HIP(launch_lap<T>(false, level_L<T>(d), d.cols, d.ne, nullptr, x, y, st));
@@ -534,12 +383,12 @@ void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, 
     case DCG_OP_RAS: {
       if (k < 2) throw Error(DCG_EINVAL, "RAS smoother exists on levels >= 2");
       check_ptr(in2, "in2 (z)");
-      DCG_HIP(launch_copy<T>(mk, x, lvbuf<T>(h->ws.f, k), st));
-      DCG_HIP(launch_copy<T>(mk, static_cast<const T*>(in2), zbuf<T>(h, k, 0), st));
+      DCG_HIP(launch_copy<T>(mk, x, cyc.f(k), st));
+      DCG_HIP(launch_copy<T>(mk, static_cast<const T*>(in2), cyc.z(k, 0), st));
       LvState s;
       s.has_z = true;
-      sweep_step<T>(h, k, s, nullptr, st);
-      DCG_HIP(launch_resolve<T>(d.ne, s.has_z, zbuf<T>(h, k, s.zb), ybuf<T>(h, k, s.yb), y, st));
+      cyc.sweep_step(k, s, nullptr, st);
+      DCG_HIP(launch_resolve<T>(d.ne, s.has_z, cyc.z(k, s.zb), cyc.Y(k, s.yb), y, st));
       break;
     }
     case DCG_OP_RESTRICT:
@@ -556,17 +405,43 @@ void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, 
       DCG_HIP(launch_coarse<T>(m.coarse_inv, x, y, st));
       break;
     case DCG_OP_WCYCLE: {
-      DCG_HIP(launch_copy<T>(mk, x, lvbuf<T>(h->ws.f, k), st));
+      DCG_HIP(launch_copy<T>(mk, x, cyc.f(k), st));
       LvState s;
       if (in2) {
-        DCG_HIP(launch_copy<T>(mk, static_cast<const T*>(in2), zbuf<T>(h, k, 0), st));
+        DCG_HIP(launch_copy<T>(mk, static_cast<const T*>(in2), cyc.z(k, 0), st));
         s.has_z = true;
       }
-      wcycle<T>(h, k, s, st);
+      cyc.wcycle(k, s, st);
       if (s.has_y)
-        DCG_HIP(launch_resolve<T>(d.ne, s.has_z, zbuf<T>(h, k, s.zb), ybuf<T>(h, k, s.yb), y, st));
+        DCG_HIP(launch_resolve<T>(d.ne, s.has_z, cyc.z(k, s.zb), cyc.Y(k, s.yb), y, st));
       else
-        DCG_HIP(launch_copy<T>(mk, zbuf<T>(h, k, s.zb), y, st));
+        DCG_HIP(launch_copy<T>(mk, cyc.z(k, s.zb), y, st));
+      break;
+    }
+    case DCG_OP_RAS_BATCH:
+    case DCG_OP_WCYCLE_BATCH: {
+      LevelBuffers& lb = h->ws.lvb_batch;
+      if (lb.f.empty()) lb.allocate(m, h->fp32, true, h->ws);
+      const Cycle<T> bc(m, lb, h->mp.pre, h->mp.post);
+      const int64_t mb = mk * kBatch;
+      const bool ras = op == DCG_OP_RAS_BATCH;
+      if (ras && k < 2) throw Error(DCG_EINVAL, "RAS smoother exists on levels >= 2");
+      if (ras) check_ptr(in2, "in2 (z)");
+      if (h->mp.post < 1) throw Error(DCG_EINVAL, "the batched cycle needs post-smoothing (m2 >= 1)");
+      DCG_HIP(launch_copy<T>(mb, x, bc.f(k), st));
+      LvState s;
+      if (in2) {
+        DCG_HIP(launch_copy<T>(mb, static_cast<const T*>(in2), bc.z(k, 0), st));
+        s.has_z = true;
+      }
+      if (ras)
+        bc.sweep_step(k, s, nullptr, st);
+      else
+        bc.wcycle(k, s, st);
+      if (s.has_y)
+        DCG_HIP(launch_resolve_b<T>(d.ne, s.has_z, bc.z(k, s.zb), bc.Y(k, s.yb), y, st));
+      else
+        DCG_HIP(launch_copy<T>(mb, bc.z(k, s.zb), y, st));
       break;
     }
     default:
