@@ -78,6 +78,128 @@ def cpu_baseline(n, dt, tol, gpu_outer, gpu_wcycles, c_F=0.01):
             "seconds_per_solve": t_solve}
 
 
+def serving_cpu_estimate(per_request, tol, c_F=0.01):
+    """The CPU oracle's cost of the trace, estimated: per mesh size, one inner
+    multigrid solve and one A* product are timed; each request is charged its
+    GPU-measured W-cycles and outer iterations at those rates."""
+    from dcg_workloads import rhs
+    from oracle import discretisation, multigrid
+    rates = {}
+    for n in sorted({r["n"] for r in per_request}):
+        As = discretisation.operator(n, 1e-4)
+        V = discretisation.deflation_basis(n)
+        H = multigrid.Hierarchy((V.T @ As @ V).tocsr(), n)
+        b = rhs(n, 0).reshape(n * n, 4, 4).transpose(1, 0, 2).reshape(-1)
+        t0 = time.time()
+        _, cycles = multigrid.multigrid(H, V.T @ b, tol=c_F * tol)
+        t_w = (time.time() - t0) / max(cycles, 1)
+        t0 = time.time()
+        As @ b
+        rates[n] = (t_w, time.time() - t0)
+        log("oracle rates n=%d: %.3f s per W-cycle, %.3f s per A* product" % (n, *rates[n]))
+    total = sum(r["wcycles"] * rates[r["n"]][0] + 2 * (r["outer"] + 2) * rates[r["n"]][1]
+                for r in per_request)
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": len(per_request) / total, "unit": "solves/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "per mesh size one oracle inner multigrid solve and one A* product timed; "
+                      "every request charged its GPU-measured W-cycles and outer iterations "
+                      "(estimate %.0f s for the trace, requests run back to back)" % total}
+
+
+def serving(args):
+    """The serving workload: a Poisson trace of requests replayed in real time
+    against one dcg server; latency = arrival to completion."""
+    import numpy as np
+    import torch
+    import paper_2606_13429_amd as dcg
+    from paper_2606_13429_amd import _binding as lib
+    from dcg_workloads import SERVING, rhs, serving_trace
+
+    sizes = tuple(SERVING["sizes"])
+    trace = serving_trace(seed=0, count=args.requests, rate=SERVING["rate"], sizes=sizes,
+                          dt_range=SERVING["dt_range"])
+    tol = SERVING["tol"]
+    torch.cuda.set_device(0)
+    srv = dcg.Server(prec="mixed", max_outer=args.serve_max_outer)
+    t0 = time.time()
+    for n in sizes:
+        srv.prepare(n)
+    log("contexts for n=%s prepared in %.1f s" % (list(sizes), time.time() - t0))
+    bs = [torch.from_numpy(rhs(r["n"], r["seed"])).cuda() for r in trace]
+    xs = [torch.empty_like(b) for b in bs]
+    torch.cuda.synchronize()
+    pending, done = {}, [None] * len(trace)
+    t_start = time.perf_counter()
+    last_log = t_start
+    i = 0
+    while i < len(trace) or pending:
+        now = time.perf_counter() - t_start
+        while i < len(trace) and trace[i]["t_arrival"] <= now:
+            r = trace[i]
+            pending[srv.submit(r["n"], r["dt"], bs[i], xs[i], tol)] = i
+            i += 1
+        for tk in list(pending):
+            status, st = srv.poll(tk)
+            if status == lib.DCG_PENDING:
+                continue
+            k = pending.pop(tk)
+            done[k] = dict(n=trace[k]["n"], dt=trace[k]["dt"], status=status,
+                           outer=st.outer_iters, wcycles=st.total_wcycles,
+                           latency=time.perf_counter() - t_start - trace[k]["t_arrival"],
+                           queue_ms=st.t_queue_ms, rel_res_true=st.rel_res_true)
+        if time.perf_counter() - last_log > 10.0:
+            last_log = time.perf_counter()
+            log("t=%.0f s: %d submitted, %d done" % (last_log - t_start, i, sum(d is not None for d in done)))
+        time.sleep(2e-4)
+    makespan = time.perf_counter() - t_start
+    steps, slot_steps = srv.counters()
+    lat = np.array([d["latency"] for d in done])
+    capped = [d for d in done if d["status"] == lib.DCG_NOT_CONVERGED]
+    failed = [d for d in done if d["status"] < 0]
+    per_n = {}
+    for n in sizes:
+        ds = [d for d in done if d["n"] == n]
+        if not ds:
+            continue
+        ln = np.array([d["latency"] for d in ds])
+        per_n[str(n)] = {"requests": len(ds),
+                         "not_converged": sum(d["status"] == lib.DCG_NOT_CONVERGED for d in ds),
+                         "p50_latency_s": round(float(np.percentile(ln, 50)), 3),
+                         "p99_latency_s": round(float(np.percentile(ln, 99)), 3),
+                         "mean_outer": round(float(np.mean([d["outer"] for d in ds])), 1),
+                         "mean_wcycles": round(float(np.mean([d["wcycles"] for d in ds])), 1)}
+    # a request alone in a fresh server gives bitwise the same x and counts
+    probe = int(np.argmin([d["wcycles"] if d["status"] == lib.DCG_OK and d["n"] == 64 else 1 << 30
+                           for d in done]))
+    alone = dcg.Server(prec="mixed", max_outer=args.serve_max_outer)
+    xa = torch.empty_like(xs[probe])
+    r = trace[probe]
+    status, st = alone.wait(alone.submit(r["n"], r["dt"], bs[probe], xa, tol))
+    alone_ok = bool(torch.equal(xa, xs[probe])) and st.outer_iters == done[probe]["outer"]
+    alone.close()
+    result = {
+        "metric": "dCG serving: solves/s and p50/p99 latency (arrival to done) over a Poisson trace",
+        "value": round(len(done) / makespan, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(trace), "warmup": 0, "ms_per_step": round(1000 * makespan / len(trace), 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 outer / f32 multigrid", "data": "synthetic: serving trace seed 0",
+        "config": {"workload": "serving trace: %d requests, Poisson %.0f/s, n in %s, dt 10^U%s, "
+                               "tol %g, mixed form, max_outer %d"
+                               % (len(trace), SERVING["rate"], list(sizes), tuple(SERVING["dt_range"]),
+                                  tol, args.serve_max_outer)},
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+        "makespan_s": round(makespan, 2), "not_converged": len(capped), "failed": len(failed),
+        "batch_occupancy": round(slot_steps / max(steps, 1), 2), "server_steps": steps,
+        "per_n": per_n, "alone_vs_mix_bitwise": alone_ok,
+    }
+    srv.close()
+    if not args.skip_cpu:
+        result["cpu_baseline"] = serving_cpu_estimate(done, tol)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +212,11 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--max-outer", type=int, default=50000,
                     help="cap on outer iterations (profiling runs only; the headline uses the default)")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving trace instead of the headline solve")
+    ap.add_argument("--requests", type=int, default=256, help="serving: trace length")
+    ap.add_argument("--serve-max-outer", type=int, default=2000,
+                    help="serving: max_outer of every request (NOT_CONVERGED beyond, reported)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,6 +224,10 @@ def main():
         print("bench.py: this build measures one GPU only; the solve is not sharded across "
               "GPUs (multi-GPU sharding is a design note).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.serving:
+        serving(args)
+        return
 
     import numpy as np
     import torch

@@ -120,7 +120,6 @@ struct Group {
   int active = 0;
   bool inflight = false;
   bool any_cycle = false;
-  uint64_t seq = 0;    // enqueue order of the step in flight
   Clock::time_point last_used;
   ~Group();
 };
@@ -181,7 +180,6 @@ struct Server::Impl {
   int unfinished = 0;
   // owned by the server thread
   std::map<GroupKey, std::unique_ptr<Group>> groups;
-  uint64_t seq = 0;
   std::atomic<int64_t> steps{0}, slot_steps{0};
   std::thread thread;
 
@@ -530,7 +528,6 @@ void Server::Impl::enqueue_step(Group& g) {
                          st));
   DCG_HIP(hipEventRecord(g.done, st));
   g.inflight = true;
-  g.seq = ++seq;
   int occupied = 0;
   for (int i = 0; i < kBatch; ++i) occupied += g.slots[i].in_step;
   steps += 1;
@@ -692,6 +689,9 @@ void Server::Impl::fail_group(Group& g, const Error& e) {
     if (s.req) finish(g, s, e.status, e.what());
 }
 
+// Scheduler loop: admit, start a step on every idle group, then process
+// every group whose step has completed (several groups' steps overlap on
+// their streams, so the first to finish is handled first).
 void Server::Impl::run() {
   (void)hipSetDevice(device);
   while (true) {
@@ -709,19 +709,26 @@ void Server::Impl::run() {
         fail_group(g, e);
       }
     }
-    Group* oldest = nullptr;
-    for (auto& kv : groups)
-      if (kv.second->inflight && (!oldest || kv.second->seq < oldest->seq)) oldest = kv.second.get();
-    if (!oldest) {
+    bool any_inflight = false, progressed = false;
+    for (auto& kv : groups) {
+      Group& g = *kv.second;
+      if (!g.inflight) continue;
+      any_inflight = true;
+      const hipError_t q = hipEventQuery(g.done);
+      if (q == hipErrorNotReady) continue;
+      progressed = true;
+      try {
+        DCG_HIP(q);
+        process(g);
+      } catch (const Error& e) {
+        fail_group(g, e);
+      }
+    }
+    if (!any_inflight) {
       std::unique_lock<std::mutex> lk(mu);
       cv.wait_for(lk, std::chrono::milliseconds(20), [&] { return stop || !queue.empty(); });
-      continue;
-    }
-    try {
-      DCG_HIP(hipEventSynchronize(oldest->done));
-      process(*oldest);
-    } catch (const Error& e) {
-      fail_group(*oldest, e);
+    } else if (!progressed) {
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
     }
   }
   for (auto& kv : groups)
