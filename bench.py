@@ -200,6 +200,86 @@ def serving(args):
     print(json.dumps(result), flush=True)
 
 
+def dt_sweep(args):
+    """Outer iterations, Tot and Inn against dt at n = 128 (the FP64 form with
+    the full preconditioner; the mixed form beside it), one solve each, and
+    the finest-level RAS step's event-timed rate."""
+    import torch
+    import paper_2606_13429_amd as dcg
+    from paper_2606_13429_amd import _binding as lib
+    from dcg_workloads import rhs
+    n, tol = args.sweep_n, args.tol
+    torch.cuda.set_device(0)
+    b = torch.from_numpy(rhs(n, 0)).cuda()
+    x = torch.empty_like(b)
+    rows = []
+    s_bytes = {"fp64": sweep_bytes_per_square(8), "mixed": sweep_bytes_per_square(4)}
+    for dt in (1e-5, 1e-4, 1e-3, 1e-2, 1e-1):
+        for prec in ("fp64", "mixed"):
+            solver = dcg.Solver(n, dt, prec=prec, max_outer=args.sweep_max_outer)
+            solver.solve(b, x, tol)                      # warm-up (graph capture)
+            lib.dcg_kernel_timing(solver.handle, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status, st = solver.solve(b, x, tol)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            k_ms, k_n = lib.dcg_kernel_timing_read(solver.handle)
+            solver.close()
+            gbs = s_bytes[prec] * n * n / (k_ms / max(k_n, 1) * 1e-3) / 1e9
+            rows.append({"dt": dt, "form": prec, "status": status, "outer": st.outer_iters,
+                         "tot": st.total_wcycles, "inn": round(st.inner_per_outer, 2),
+                         "solve_s": round(t, 3), "rel_res_true": st.rel_res_true,
+                         "finest_ras_us": round(k_ms / max(k_n, 1) * 1e3, 2),
+                         "finest_ras_GBs": round(gbs, 1)})
+            log("dt=%g %s: status %d outer %d Tot %d Inn %.2f %.2f s, finest RAS %.1f us"
+                % (dt, prec, status, st.outer_iters, st.total_wcycles, st.inner_per_outer, t,
+                   rows[-1]["finest_ras_us"]))
+    print(json.dumps({"metric": "dCG outer iterations / Tot / Inn against dt", "n": n, "tol": tol,
+                      "max_outer": args.sweep_max_outer, "rows": rows}), flush=True)
+
+
+def timestep(args):
+    """BDF2 time stepping at n = 1024 (mixed form, warm start): steps/s and
+    the true residual of every step, over --ts-steps steps."""
+    import numpy as np
+    import torch
+    from paper_2606_13429_amd import _binding as lib
+    from paper_2606_13429_amd.timestep import BDF2
+    from dcg_workloads import TIMESTEP, forcing_load, fourier_modes
+    n, dt = TIMESTEP["n"], TIMESTEP["dt"]
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    F = torch.from_numpy(forcing_load(n, fourier_modes(TIMESTEP["seed"], TIMESTEP["modes"]))).cuda()
+    stepper = BDF2(n, dt, prec="mixed", tol=args.tol)
+    log("n=%d setup + forcing %.1f s" % (n, time.time() - t0))
+    lib.dcg_kernel_timing(stepper.solver.handle, True)
+    rows = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for i in range(args.ts_steps):
+        t0 = time.perf_counter()
+        st = stepper.step(F)
+        torch.cuda.synchronize()
+        rows.append({"step": i + 1, "status": st.status, "outer": st.outer_iters,
+                     "tot": st.total_wcycles, "rel_res_true": st.rel_res_true,
+                     "seconds": round(time.perf_counter() - t0, 3)})
+        log("step %d: outer %d Tot %d res %.2e %.1f s" % (i + 1, st.outer_iters, st.total_wcycles,
+                                                           st.rel_res_true, rows[-1]["seconds"]))
+    t_all = time.perf_counter() - t_all
+    k_ms, k_n = lib.dcg_kernel_timing_read(stepper.solver.handle)
+    k_avg = k_ms / max(k_n, 1)
+    gbs = sweep_bytes_per_square(4) * n * n / (k_avg * 1e-3) / 1e9
+    print(json.dumps({"metric": "BDF2 steps/s, n=1024 dt=1e-5, mixed form, warm start",
+                      "value": round(len(rows) / t_all, 5), "unit": "steps/s", "steps": len(rows),
+                      "of_steps": TIMESTEP["steps"],
+                      "roofline": {"bound": "hbm", "kernel": "k_sweep<float,1> (finest-level RAS step)",
+                                   "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n},
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +297,11 @@ def main():
     ap.add_argument("--requests", type=int, default=256, help="serving: trace length")
     ap.add_argument("--serve-max-outer", type=int, default=2000,
                     help="serving: max_outer of every request (NOT_CONVERGED beyond, reported)")
+    ap.add_argument("--dt-sweep", action="store_true", help="run the dt sweep at --sweep-n")
+    ap.add_argument("--sweep-n", type=int, default=128)
+    ap.add_argument("--sweep-max-outer", type=int, default=20000)
+    ap.add_argument("--timestep", action="store_true", help="run BDF2 time stepping at n=1024")
+    ap.add_argument("--ts-steps", type=int, default=3)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -227,6 +312,12 @@ def main():
 
     if args.serving:
         serving(args)
+        return
+    if args.dt_sweep:
+        dt_sweep(args)
+        return
+    if args.timestep:
+        timestep(args)
         return
 
     import numpy as np
