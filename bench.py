@@ -40,6 +40,36 @@ def sweep_bytes_per_square(s):
     return (zero + 2 * pending + prolong) / 4
 
 
+# HBM traffic of one finest-level RAS launch at n = 512 (mixed form), from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; profiles/k_sweep_finest_n512_mixed_traffic.md),
+# each scaled by the reading of a plain 1 GiB copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE
+# 1 GiB).  Valid only for the kernel source it was taken on: the digest of the RAS kernel
+# sources must match, else the bench reports traffic as null.
+TRAFFIC = {"source_digest": "3144e932b1901131", "n": 512,
+           "fetch_kib": 356864.7, "fetch_scale": 2.0, "write_kib": 16457.4, "write_scale": 1.0}
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mg_kernels.hip", "mg_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2606_13429_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n):
+    """HBM bytes per finest RAS launch from the counters, or None when they
+    do not apply (other n, or the kernel changed since they were taken)."""
+    try:
+        if n != TRAFFIC["n"] or kernel_source_digest() != TRAFFIC["source_digest"]:
+            return None
+    except OSError:
+        return None
+    return int(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
+                       + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -280,6 +310,20 @@ def timestep(args):
                       "rows": rows}), flush=True)
 
 
+def copy_calibration(nbytes):
+    """A plain device-to-device copy of ``nbytes`` (torch's copy kernel),
+    repeated 5 times: the reference dispatch for scaling HBM traffic counters
+    (FETCH_SIZE and WRITE_SIZE should each read nbytes per dispatch)."""
+    import torch
+    torch.cuda.set_device(0)
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "dispatches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +346,8 @@ def main():
     ap.add_argument("--sweep-max-outer", type=int, default=20000)
     ap.add_argument("--timestep", action="store_true", help="run BDF2 time stepping at n=1024")
     ap.add_argument("--ts-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES (traffic-counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -310,6 +356,9 @@ def main():
               "GPUs (multi-GPU sharding is a design note).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.serving:
         serving(args)
         return
@@ -364,9 +413,11 @@ def main():
     achieved = tiles_bytes / (k_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_sweep<float,1> (finest-level RAS step)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(n),
                 "avg_launch_us": round(k_avg_ms * 1e3, 2), "launches": k_launches,
                 "bytes_per_launch": tiles_bytes}
+    if roofline["traffic"]:
+        roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / tiles_bytes, 3)
 
     outer = int(np.mean([s["outer_iters"] for s in stats]))
     result = {
