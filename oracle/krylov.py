@@ -31,7 +31,10 @@ Parity status: pinned.  CG against the iterates of a library CG; deflated CG
 with an exact inner solve against a dense Cholesky solution; the Kahl
 identity and the consistency of the deflated system; recurrence residual =
 true residual with exact inner solves; FCG(inf) = DCG counts with exact inner
-solves; the Delta-t trends of Tables 1-2 (tests/test_oracle_krylov.py).
+solves; the Delta-t trends of Tables 1-2; the adaptive rule of eq. (tol)
+reaching the target and the sparse direct solution with FCG(inf), and costing
+fewer cycles than the fixed rule (Table 3's finding) with late inner solves
+cheaper than early ones (tests/test_oracle_krylov.py).
 """
 import numpy as np
 import scipy.linalg as sla

@@ -163,3 +163,42 @@ def test_warm_start_and_not_converged_paths():
     assert warm.iterations <= 2
     capped = kr.dcg(As, V, f, inner, tol=1e-8, max_iter=3)
     assert capped.iterations == 3 and capped.rel_res_recurrence > 1e-8
+
+
+def _spsolve(As, f):
+    return spla.spsolve(As.tocsc(), f)
+
+
+def test_adaptive_inner_tolerance_reaches_the_target_with_fcg():
+    # eq. (tol): the inner accuracy is relaxed as the outer residual falls
+    # "while still ensuring" the outer iteration reaches the target; with the
+    # flexible outer iteration (Algorithm 1) the reconstructed x must reach
+    # the tolerance and the sparse direct solution
+    n, dt, tol = 32, 1e-3, 1e-8
+    As, V, E, f = _problem(n, dt, seed=4)
+    xs = _spsolve(As, f)
+    H = mg.Hierarchy(E, n)
+    r = kr.dcg(As, V, f, kr.mg_inner(H), tol=tol, outer='fcg', m_max=None, c_A=0.01,
+               max_iter=1000)
+    assert r.rel_res_recurrence <= tol
+    assert r.rel_res_true <= 10 * tol
+    assert np.linalg.norm(r.x - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_adaptive_inner_tolerance_costs_fewer_wcycles_than_fixed():
+    # Table 3: when both converge, the adaptive rule takes fewer multigrid
+    # cycles in total (Tot) than the fixed rule with the same constant, and
+    # the inner solves late in the iteration take fewer cycles than early ones
+    n, dt, tol = 32, 1e-3, 1e-8
+    As, V, E, f = _problem(n, dt, seed=5)
+    H = mg.Hierarchy(E, n)
+    fixed = kr.dcg(As, V, f, kr.mg_inner(H), tol=tol, outer='fcg', m_max=None, c_F=0.01,
+                   max_iter=1000)
+    adapt = kr.dcg(As, V, f, kr.mg_inner(H), tol=tol, outer='fcg', m_max=None, c_A=0.01,
+                   max_iter=1000)
+    assert fixed.rel_res_recurrence <= tol and adapt.rel_res_recurrence <= tol
+    assert adapt.total_cycles < 0.8 * fixed.total_cycles, (adapt.total_cycles, fixed.total_cycles)
+    oc = adapt.outer_cycles
+    k = len(oc) // 4
+    assert np.mean(oc[-k:]) < np.mean(oc[:k])
+    assert len(set(fixed.outer_cycles)) <= 3      # the fixed rule: about constant
