@@ -67,8 +67,13 @@ typedef enum { DCG_FP64 = 0, DCG_MIXED = 1 } dcg_precision;
 
 typedef enum {
   DCG_OUTER_CG = 0,   /* Fletcher-Reeves beta = rho_new / rho (Tables 2-3)    */
-  DCG_OUTER_FCG1 = 1  /* flexible CG with one stored direction, Algorithm 1
+  DCG_OUTER_FCG1 = 1, /* flexible CG with one stored direction, Algorithm 1
                          truncated to m_i = 1 (Remark 5, m_max = 1)           */
+  DCG_OUTER_FCG = 2   /* flexible CG, Algorithm 1 with the truncation of
+                         Remark 5, m_0 = 0, m_i = max{1, mod(i, m_max + 1)};
+                         m_max = 0 means FCG(inf), m_i = i (every direction
+                         kept: 2 vectors of 16 n^2 doubles per iteration --
+                         meant for small n).  dcg_solve only.                 */
 } dcg_outer;
 
 typedef struct {
@@ -88,6 +93,11 @@ typedef struct {
   int32_t use_graph;   /* 1: replay each W-cycle as a captured HIP graph [1]  */
   int64_t hbm_budget_bytes; /* server admission budget, 0 = device total      */
   int32_t max_pending; /* server: unfinished requests before DCG_EAGAIN [4096] */
+  double c_A;          /* > 0: adaptive inner tolerance of eq. (tol),
+                          tau^c_i = c_A tol ||b|| / ||r_i|| for the inner solve
+                          of outer iteration i and c_A tol for the prologue
+                          and epilogue solves, instead of c_F tol [0 = off]   */
+  int32_t m_max;       /* DCG_OUTER_FCG truncation, 0 = FCG(inf) [8]         */
 } dcg_options;
 
 typedef struct {

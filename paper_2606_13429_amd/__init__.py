@@ -8,7 +8,10 @@ if the library has not been built.
 """
 from ._binding import *          # noqa: F401,F403  (the C entry points)
 from ._binding import (DCGError, dcg_defaults, dcg_destroy, dcg_setup, dcg_solve,
-                       DCG_FP64, DCG_MIXED, DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_PENDING, LIB_PATH)
+                       DCG_FP64, DCG_MIXED, DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_OUTER_FCG, DCG_PENDING,
+                       LIB_PATH)
+
+_OUTER = {"cg": DCG_OUTER_CG, "fcg1": DCG_OUTER_FCG1, "fcg": DCG_OUTER_FCG}
 
 __all__ = ["Solver", "Server", "DCGError", "LIB_PATH"]
 
@@ -21,12 +24,16 @@ class Solver:
     """
 
     def __init__(self, n, dt, nu=1.0, prec="mixed", outer="cg", penalty=10.0, pre=2, post=2,
-                 c_F=0.01, max_outer=50000, max_inner=100, x0_given=False, use_graph=True):
+                 c_F=0.01, max_outer=50000, max_inner=100, x0_given=False, use_graph=True,
+                 c_A=0.0, m_max=8):
+        """outer: "cg", "fcg1" or "fcg" (truncated FCG with m_max, FCG(inf) for
+        m_max = 0); c_A > 0 selects the adaptive inner tolerance of eq. (tol)."""
         mesh, opt = dcg_defaults()
         mesh.n, mesh.penalty, mesh.pre, mesh.post = n, penalty, pre, post
         opt.prec = {"mixed": DCG_MIXED, "fp64": DCG_FP64}[prec]
-        opt.outer = {"cg": DCG_OUTER_CG, "fcg1": DCG_OUTER_FCG1}[outer]
+        opt.outer = _OUTER[outer]
         opt.c_F, opt.max_outer, opt.max_inner = c_F, max_outer, max_inner
+        opt.c_A, opt.m_max = c_A, m_max
         opt.x0_given, opt.use_graph = int(x0_given), int(use_graph)
         self.n, self.dt, self.nu, self.mesh, self.opt = n, dt, nu, mesh, opt
         self.handle = dcg_setup(mesh, dt, nu, opt)
@@ -59,12 +66,12 @@ class Server:
     """
 
     def __init__(self, prec="mixed", outer="cg", c_F=0.01, max_outer=50000, max_inner=100,
-                 use_graph=True, hbm_budget_bytes=0, max_pending=4096):
+                 use_graph=True, hbm_budget_bytes=0, max_pending=4096, c_A=0.0):
         from ._binding import dcg_server_create
         _, opt = dcg_defaults()
         opt.prec = {"mixed": DCG_MIXED, "fp64": DCG_FP64}[prec]
-        opt.outer = {"cg": DCG_OUTER_CG, "fcg1": DCG_OUTER_FCG1}[outer]
-        opt.c_F, opt.max_outer, opt.max_inner = c_F, max_outer, max_inner
+        opt.outer = _OUTER[outer]
+        opt.c_F, opt.max_outer, opt.max_inner, opt.c_A = c_F, max_outer, max_inner, c_A
         opt.use_graph, opt.hbm_budget_bytes, opt.max_pending = int(use_graph), hbm_budget_bytes, max_pending
         self.opt = opt
         self.handle = dcg_server_create(opt)

@@ -344,7 +344,55 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ 
       sc->rho = sums[0];
       sc->dr = sums[0];
       break;
+    case kRedDr:
+      sc->dr = sums[0];
+      break;
   }
+}
+
+// Partial (r, q_k) for the k-th window direction (blockIdx.y = k).
+__global__ __launch_bounds__(kThreads) void k_fcg_dot(int64_t n, const double* __restrict__ r,
+                                                      const double* const* __restrict__ qptr,
+                                                      int first, int R, double* __restrict__ part) {
+  __shared__ double lds[4];
+  const int k = blockIdx.y;
+  const double* q = qptr[(first + k) % R];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    acc += r[i] * q[i];
+  const double t = block_sum(acc, lds);
+  if (threadIdx.x == 0) part[(int64_t)k * gridDim.x + blockIdx.x] = t;
+}
+
+// coef[k] = -(sum of the k-th partials, in block order) / dq_k.
+__global__ __launch_bounds__(kThreads) void k_fcg_coef(const double* __restrict__ part, int nb,
+                                                       const double* __restrict__ dq, int first,
+                                                       int R, double* __restrict__ coef) {
+  __shared__ double lds[4];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kThreads) acc += part[(int64_t)k * nb + b];
+  const double t = block_sum(acc, lds);
+  if (threadIdx.x == 0) coef[k] = -t / dq[(first + k) % R];
+}
+
+__global__ __launch_bounds__(kThreads) void k_fcg_direction(
+    int64_t n, const double* __restrict__ r, const double* const* __restrict__ dptr, int first,
+    int m, int R, const double* __restrict__ coef, double* __restrict__ d,
+    double* __restrict__ part) {
+  __shared__ double lds[4];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double ri = r[i];
+    double di = ri;
+    for (int k = 0; k < m; ++k) di += coef[k] * dptr[(first + k) % R][i];
+    d[i] = di;
+    acc += di * ri;
+  }
+  const double t = block_sum(acc, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kThreads) void k_zt(int ne, const double* __restrict__ w,
@@ -733,6 +781,26 @@ hipError_t launch_cg_update(bool flexible, int64_t nvec, const Scalars* sc, cons
     k_cg_update<true><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part, sl);
   else
     k_cg_update<false><<<grid, kThreads, 0, st>>>(nvec, sc, p, q, x, r, part, sl);
+  return hipGetLastError();
+}
+
+int fcg_coef_blocks(int64_t n) { return grid_for(n, kThreads * 8, 128); }
+
+hipError_t launch_fcg_coef(int64_t n, const double* r, const double* const* qptr, const double* dq,
+                           int first, int m, int R, double* part, double* coef, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  const int nb = fcg_coef_blocks(n);
+  k_fcg_dot<<<dim3(nb, m), kThreads, 0, st>>>(n, r, qptr, first, R, part);
+  k_fcg_coef<<<m, kThreads, 0, st>>>(part, nb, dq, first, R, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_direction(int64_t n, const double* r, const double* const* dptr, int first,
+                                int m, int R, const double* coef, double* d, double* part,
+                                int* nblocks, hipStream_t st) {
+  const int grid = grid_for(n, kThreads * 4, 8192);
+  *nblocks = grid;
+  k_fcg_direction<<<grid, kThreads, 0, st>>>(n, r, dptr, first, m, R, coef, d, part);
   return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ enum ReduceOp : int {
   kRedRes = 5,       // slot (v,v)                  -> res2
   kRedFcgAlpha = 6,  // slot (d,q)                  -> pq, alpha = dr / pq
   kRedFcgBeta = 7,   // slots (r,r),(r,q),(d,r)     -> rho, beta = -(r,q)/pq, dr
-  kRedRho = 8        // slot (r,r)                  -> rho (and dr = rho)
+  kRedRho = 8,       // slot (r,r)                  -> rho (and dr = rho)
+  kRedDr = 9         // slot (d,r)                  -> dr
 };
 
 constexpr int kPartStride = 1 << 16;   // max blocks of a reducing launch
@@ -117,6 +118,21 @@ hipError_t launch_scale(int64_t n, double c, const double* in, double* out, hipS
 hipError_t launch_bdf2_rhs(int ne, const double* M1, double inv_nu, const double* s1,
                            const double* s2, const double* F, double c, double* f, double* x0,
                            hipStream_t st);
+
+// Flexible CG with stored directions (Algorithm 1): the window of the m
+// directions d_k, q_k = M_D d_k of slots (first + k) % R, k < m, is addressed
+// through device pointer arrays dptr / qptr and the device array dq of
+// (d_k, q_k).
+//   launch_fcg_coef:      coef[k] = -(r, q_k) / dq_k  (partials in part, then a
+//                         fixed-order reduction per k; ``part`` holds m x
+//                         fcg_coef_blocks(n) doubles)
+//   launch_fcg_direction: d = r + sum_k coef[k] d_k (k ascending), partial (d, r)
+int fcg_coef_blocks(int64_t n);
+hipError_t launch_fcg_coef(int64_t n, const double* r, const double* const* qptr, const double* dq,
+                           int first, int m, int R, double* part, double* coef, hipStream_t st);
+hipError_t launch_fcg_direction(int64_t n, const double* r, const double* const* dptr, int first,
+                                int m, int R, const double* coef, double* d, double* part,
+                                int* nblocks, hipStream_t st);
 
 // inner refinement (FP64 residual of the level-J Laplacian)
 template <typename T>

@@ -86,6 +86,22 @@ struct LevelBuffers {
   void allocate(const MeshContext& m, bool fp32, bool batch, Workspace& ws);
 };
 
+// Stored directions of the flexible outer iteration: R slots of (d, q) with
+// device pointer arrays and (d, q) values; vectors are allocated on first use.
+struct FcgStore {
+  int R = 0;
+  std::vector<double*> d, q;
+  double** dptr = nullptr;
+  double** qptr = nullptr;
+  double* dq = nullptr;
+  double* coef = nullptr;
+  double* part = nullptr;
+  std::vector<void*> vecs;
+  void* alloc(size_t bytes);
+  void release();
+  ~FcgStore() { release(); }
+};
+
 // Device workspace of one solver handle (one request) or one serving batch.
 struct Workspace {
   int ne = 0;
@@ -98,6 +114,7 @@ struct Workspace {
   Scalars* sc_host = nullptr;             // pinned host mirror
   LevelBuffers lvb;                       // W-cycle level buffers
   LevelBuffers lvb_batch;                 // batched level operators (allocated on first use)
+  FcgStore fcg;                           // DCG_OUTER_FCG directions
   void* alloc(size_t bytes);
   void release();
   ~Workspace();

@@ -549,7 +549,11 @@ void Server::Impl::after_inner_start(Group& g, Slot& s, const Scalars& sc) {
     finish(g, s, DCG_EINVAL, "non-finite inner right-hand side");
     return;
   }
-  const double tol_c = opt.c_F * s.req->tol;
+  // eq. (fixed_tol), or eq. (tol) with the outer residual of this iteration
+  const double tol = s.req->tol;
+  const double tol_c = opt.c_A <= 0.0 ? opt.c_F * tol
+                       : (s.kind == Kind::kIter ? opt.c_A * tol * std::sqrt(s.b2) / std::sqrt(s.rho)
+                                                : opt.c_A * tol);
   s.inner_lim = tol_c * tol_c * s2;
   s.cycles = 0;
   if (s2 > 0.0 && opt.max_inner > 0 && s2 > s.inner_lim) {

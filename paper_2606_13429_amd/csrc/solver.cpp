@@ -29,6 +29,26 @@ void Workspace::release() {
 
 Workspace::~Workspace() { release(); }
 
+void* FcgStore::alloc(size_t b) {
+  void* p = nullptr;
+  DCG_HIP(hipMalloc(&p, b));
+  vecs.push_back(p);
+  return p;
+}
+
+void FcgStore::release() {
+  for (void* p : vecs) (void)hipFree(p);
+  vecs.clear();
+  for (void* p : {static_cast<void*>(dptr), static_cast<void*>(qptr), static_cast<void*>(dq),
+                  static_cast<void*>(coef), static_cast<void*>(part)})
+    if (p) (void)hipFree(p);
+  dptr = qptr = nullptr;
+  dq = coef = part = nullptr;
+  d.clear();
+  q.clear();
+  R = 0;
+}
+
 void LevelBuffers::allocate(const MeshContext& m, bool fp32, bool batch, Workspace& ws) {
   batched = batch;
   const size_t rs = fp32 ? sizeof(float) : sizeof(double);
@@ -228,6 +248,79 @@ void handle_init(dcg_ctx* h) {
   DCG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
 }
 
+// ------------------------------------------------------------ flexible CG
+// Outer iterations of Algorithm 1 on the deflated system with the truncation
+// of Remark 5: m_0 = 0, m_i = max{1, mod(i, m_max + 1)} (m_i = i for
+// FCG(inf), m_max = 0).  Iteration i:
+//   d_i = r_i - sum_{k = i - m_i}^{i - 1} (r_i, q_k) / (d_k, q_k) d_k
+//   q_i = M_D d_i,  alpha = (d_i, r_i) / (d_i, q_i),  x += alpha d_i,  r -= alpha q_i.
+// The directions live in a ring of m_max + 1 slots (FCG(inf): one slot per
+// iteration, allocated as the iteration reaches it).
+template <typename TolFn>
+dcg_status outer_fcg(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_total,
+                     int& cycles_outer, int& inner_solves, TolFn tol_outer, hipStream_t st) {
+  MeshContext& m = *h->mesh;
+  Workspace& ws = h->ws;
+  FcgStore& fs = ws.fcg;
+  const int ne = m.ne;
+  const int64_t N = 16 * int64_t(ne);
+  const bool inf = h->opt.m_max == 0;
+  const int R = inf ? h->opt.max_outer + 1 : h->opt.m_max + 1;
+  if (fs.R != R) {
+    fs.release();
+    fs.R = R;
+    fs.d.assign(R, nullptr);
+    fs.q.assign(R, nullptr);
+    DCG_HIP(hipMalloc(&fs.dptr, sizeof(double*) * R));
+    DCG_HIP(hipMalloc(&fs.qptr, sizeof(double*) * R));
+    DCG_HIP(hipMalloc(&fs.dq, sizeof(double) * R));
+    DCG_HIP(hipMalloc(&fs.coef, sizeof(double) * R));
+    DCG_HIP(hipMalloc(&fs.part, sizeof(double) * size_t(R) * fcg_coef_blocks(N)));
+  }
+  const int nbA = astar_blocks(ne);
+  dcg_status status = DCG_OK;
+  while (true) {
+    if (rho <= lim) break;
+    if (it >= h->opt.max_outer) {
+      status = DCG_NOT_CONVERGED;
+      break;
+    }
+    const int mi = inf ? it : (it == 0 ? 0 : std::max(1, it % (h->opt.m_max + 1)));
+    const int slot = it % R;
+    if (!fs.d[slot]) {   // first use of the slot
+      fs.d[slot] = static_cast<double*>(fs.alloc(sizeof(double) * N));
+      fs.q[slot] = static_cast<double*>(fs.alloc(sizeof(double) * N));
+      DCG_HIP(hipMemcpy(fs.dptr + slot, &fs.d[slot], sizeof(double*), hipMemcpyHostToDevice));
+      DCG_HIP(hipMemcpy(fs.qptr + slot, &fs.q[slot], sizeof(double*), hipMemcpyHostToDevice));
+    }
+    const int first = ((it - mi) % R + R) % R;
+    DCG_HIP(launch_fcg_coef(N, ws.r, fs.qptr, fs.dq, first, mi, R, fs.part, fs.coef, st));
+    int nbd = 0;
+    DCG_HIP(launch_fcg_direction(N, ws.r, fs.dptr, first, mi, R, fs.coef, fs.d[slot], ws.part,
+                                 &nbd, st));
+    DCG_HIP(launch_reduce(ws.part, nbd, kRedDr, ws.sc, st));
+    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, fs.d[slot], nullptr, nullptr,
+                         ws.sc, nullptr, ws.w, ws.s, nullptr, st));
+    const int c = inner(h, ws.s, ws.zref, tol_outer(rho), st);
+    cycles_total += c;
+    cycles_outer += c;
+    ++inner_solves;
+    DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zref, ws.w, fs.d[slot], fs.q[slot],
+                           nullptr, ws.part, st));
+    DCG_HIP(launch_reduce(ws.part, nbA, kRedFcgAlpha, ws.sc, st));   // alpha = (d, r) / (d, q)
+    DCG_HIP(launch_copy<double>(1, &ws.sc->pq, fs.dq + slot, st));
+    int nbu = 0;
+    DCG_HIP(launch_cg_update(false, N, ws.sc, fs.d[slot], fs.q[slot], ws.xh, ws.r, ws.part, &nbu, st));
+    DCG_HIP(launch_reduce(ws.part, nbu, kRedRho, ws.sc, st));
+    ++it;
+    read_scalars(h, st);
+    if (ws.sc_host->breakdown) return DCG_EBREAKDOWN;
+    rho = ws.sc_host->rho;
+    if (!std::isfinite(rho)) return DCG_EBREAKDOWN;
+  }
+  return status;
+}
+
 // ------------------------------------------------------------ solve
 dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* st,
                  hipStream_t stream) {
@@ -240,7 +333,10 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
   const int ne = m.ne;
   const int64_t N = 16 * int64_t(ne);
   const bool flex = h->opt.outer == DCG_OUTER_FCG1;
-  const double tol_c = h->opt.c_F * tol;
+  // inner tolerances: eq. (fixed_tol) c_F tol, or eq. (tol) c_A tol ||b|| / ||r_i||
+  // inside the outer loop with c_A tol for the prologue, start and epilogue solves
+  const bool adaptive = h->opt.c_A > 0.0;
+  const double tol_c = adaptive ? h->opt.c_A * tol : h->opt.c_F * tol;
   const int nbA = astar_blocks(ne);
   dcg_stats stats{};
   int cycles_total = 0, inner_solves = 0, cycles_outer = 0;
@@ -288,40 +384,48 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
 
   const double lim = tol * tol * b2;
   double rho = ws.sc_host->rho;
+  auto tol_outer = [&](double rho_i) {
+    return adaptive ? h->opt.c_A * tol * std::sqrt(b2) / std::sqrt(rho_i) : tol_c;
+  };
   int it = 0, pidx = 0;
   dcg_status status = DCG_OK;
-  while (true) {
-    if (rho <= lim) break;
-    if (it >= h->opt.max_outer) {
-      status = DCG_NOT_CONVERGED;
-      break;
-    }
-    // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
-    DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Adiv, m.cols, m.M1, ne,
-                         ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
-                         stream));
-    pidx = 1 - pidx;
-    const int c = inner(h, ws.s, ws.zref, tol_c, stream);
-    cycles_total += c;
-    cycles_outer += c;
-    ++inner_solves;
-    // q = w - A* Z y = M_D p  (y = (2/dt) z)
-    DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zref, ws.w, ws.p[pidx], ws.q, nullptr,
-                           ws.part, stream));
-    DCG_HIP(launch_reduce(ws.part, nbA, flex ? kRedFcgAlpha : kRedAlpha, ws.sc, stream));
-    int nbu = 0;
-    DCG_HIP(launch_cg_update(flex, N, ws.sc, ws.p[pidx], ws.q, ws.xh, ws.r, ws.part, &nbu, stream));
-    DCG_HIP(launch_reduce(ws.part, nbu, flex ? kRedFcgBeta : kRedBeta, ws.sc, stream));
-    ++it;
-    read_scalars(h, stream);
-    if (ws.sc_host->breakdown) {
-      status = DCG_EBREAKDOWN;
-      break;
-    }
-    rho = ws.sc_host->rho;
-    if (!std::isfinite(rho)) {
-      status = DCG_EBREAKDOWN;
-      break;
+  if (h->opt.outer == DCG_OUTER_FCG) {
+    status = outer_fcg(h, lim, rho, it, cycles_total, cycles_outer, inner_solves, tol_outer, stream);
+  } else {
+    while (true) {
+      if (rho <= lim) break;
+      if (it >= h->opt.max_outer) {
+        status = DCG_NOT_CONVERGED;
+        break;
+      }
+      // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
+      DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Adiv, m.cols, m.M1, ne,
+                           ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
+                           stream));
+      pidx = 1 - pidx;
+      const int c = inner(h, ws.s, ws.zref, tol_outer(rho), stream);
+      cycles_total += c;
+      cycles_outer += c;
+      ++inner_solves;
+      // q = w - A* Z y = M_D p  (y = (2/dt) z)
+      DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zref, ws.w, ws.p[pidx], ws.q,
+                             nullptr, ws.part, stream));
+      DCG_HIP(launch_reduce(ws.part, nbA, flex ? kRedFcgAlpha : kRedAlpha, ws.sc, stream));
+      int nbu = 0;
+      DCG_HIP(launch_cg_update(flex, N, ws.sc, ws.p[pidx], ws.q, ws.xh, ws.r, ws.part, &nbu,
+                               stream));
+      DCG_HIP(launch_reduce(ws.part, nbu, flex ? kRedFcgBeta : kRedBeta, ws.sc, stream));
+      ++it;
+      read_scalars(h, stream);
+      if (ws.sc_host->breakdown) {
+        status = DCG_EBREAKDOWN;
+        break;
+      }
+      rho = ws.sc_host->rho;
+      if (!std::isfinite(rho)) {
+        status = DCG_EBREAKDOWN;
+        break;
+      }
     }
   }
   stats.rel_res_recurrence = std::sqrt(std::max(rho, 0.0) / b2);
