@@ -310,6 +310,36 @@ def timestep(args):
                       "rows": rows}), flush=True)
 
 
+def variants(args):
+    """The inner-tolerance rule and outer variant at the headline size: the
+    fixed rule (eq. (fixed_tol), c_F = 0.01) against the adaptive rule
+    (eq. (tol), c_A = 0.01) with CG, FCG(1) and FCG(8); one solve each."""
+    import torch
+    import paper_2606_13429_amd as dcg
+    from dcg_workloads import rhs
+    n, dt, tol = args.n, args.dt, args.tol
+    torch.cuda.set_device(0)
+    b = torch.from_numpy(rhs(n, 0)).cuda()
+    x = torch.empty_like(b)
+    rows = []
+    for outer, c_A in (("cg", 0.0), ("cg", 0.01), ("fcg1", 0.01), ("fcg", 0.01)):
+        solver = dcg.Solver(n, dt, prec="mixed", outer=outer, c_A=c_A, m_max=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, st = solver.solve(b, x, tol)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        solver.close()
+        rows.append({"outer": outer if outer != "fcg" else "fcg(8)",
+                     "inner_rule": "adaptive c_A=0.01" if c_A else "fixed c_F=0.01",
+                     "status": status, "outer_iters": st.outer_iters, "tot": st.total_wcycles,
+                     "inn": round(st.inner_per_outer, 2), "rel_res_true": st.rel_res_true,
+                     "solve_s": round(t, 2)})
+        log(str(rows[-1]))
+    print(json.dumps({"metric": "inner-tolerance rule / outer variant at n=%d dt=%g, mixed form" % (n, dt),
+                      "rows": rows}), flush=True)
+
+
 def copy_calibration(nbytes):
     """A plain device-to-device copy of ``nbytes`` (torch's copy kernel),
     repeated 5 times: the reference dispatch for scaling HBM traffic counters
@@ -346,6 +376,8 @@ def main():
     ap.add_argument("--sweep-max-outer", type=int, default=20000)
     ap.add_argument("--timestep", action="store_true", help="run BDF2 time stepping at n=1024")
     ap.add_argument("--ts-steps", type=int, default=3)
+    ap.add_argument("--variants", action="store_true",
+                    help="compare the fixed and adaptive inner tolerance at --n/--dt")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (traffic-counter calibration)")
     args = ap.parse_args()
@@ -361,6 +393,9 @@ def main():
         return
     if args.serving:
         serving(args)
+        return
+    if args.variants:
+        variants(args)
         return
     if args.dt_sweep:
         dt_sweep(args)

@@ -147,23 +147,27 @@ def test_repeated_solves_are_bitwise_identical():
 
 # Outer variants of Algorithm 1 / Remark 5 and the adaptive inner tolerance
 # of eq. (tol) against the oracle's implementation of the same rules.
-_VARIANTS = [("fcg", 4, 0.0), ("fcg", 0, 0.0), ("fcg", 0, 0.01), ("cg", 8, 0.01), ("fcg1", 8, 0.01),
-             ("fcg", 4, 0.01)]
+# At dt = 1e-2 the adaptive rule also halves the outer count of the fixed
+# rule (340 against 694 in the oracle): the case checks that the GPU follows.
+_VARIANTS = [("fcg", 4, 0.0, 1e-3), ("fcg", 0, 0.0, 1e-3), ("fcg", 0, 0.01, 1e-3),
+             ("cg", 8, 0.01, 1e-3), ("fcg1", 8, 0.01, 1e-3), ("fcg", 4, 0.01, 1e-3),
+             ("cg", 8, 0.01, 1e-2)]
 
 
-@pytest.mark.parametrize("outer,m_max,c_A", _VARIANTS,
+@pytest.mark.parametrize("outer,m_max,c_A,dt", _VARIANTS,
                          ids=["fcg4", "fcginf", "fcginf-adaptive", "cg-adaptive", "fcg1-adaptive",
-                              "fcg4-adaptive"])
-def test_outer_variants_and_adaptive_tolerance_match_oracle(outer, m_max, c_A):
-    n, dt, tol = 32, 1e-3, 1e-8
+                              "fcg4-adaptive", "cg-adaptive-dt1e-2"])
+def test_outer_variants_and_adaptive_tolerance_match_oracle(outer, m_max, c_A, dt):
+    n, tol = 32, 1e-8
     As = d.operator(n, dt)
     V = d.deflation_basis(n)
     E = (V.T @ As @ V).tocsr()
-    f = elem_to_comp(rhs(n, 6), n)
+    seed = 6 if dt == 1e-3 else 0
+    f = elem_to_comp(rhs(n, seed), n)
     kw = {"cg": dict(outer="cg"), "fcg1": dict(outer="fcg", m_max=1),
           "fcg": dict(outer="fcg", m_max=m_max or None)}[outer]
     ref = kr.dcg(As, V, f, kr.mg_inner(mg.Hierarchy(E, n)), tol=tol, c_A=c_A or None, **kw)
-    status, st, x, _ = _gpu(n, dt, 6, tol, "mixed", outer=outer, m_max=m_max, c_A=c_A)
+    status, st, x, _ = _gpu(n, dt, seed, tol, "mixed", outer=outer, m_max=m_max, c_A=c_A)
     xr = comp_to_elem(ref.x, n)
     err = np.linalg.norm(x - xr) / np.linalg.norm(xr)
     print("variant %s m_max=%d c_A=%g: gpu outer %d Tot %d, oracle outer %d Tot %d, err %.2e, "
