@@ -202,3 +202,49 @@ def test_adaptive_inner_tolerance_costs_fewer_wcycles_than_fixed():
     k = len(oc) // 4
     assert np.mean(oc[-k:]) < np.mean(oc[:k])
     assert len(set(fixed.outer_cycles)) <= 3      # the fixed rule: about constant
+
+
+def test_gmres_iterates_are_the_minimal_residual_points():
+    # GMRES's k-th iterate minimises ||f_D - M_D x|| over the k-th Krylov
+    # space of f_D (x0 = 0): brute force with a dense least-squares problem
+    n, dt = 4, 1e-2
+    As, V, E, f = _problem(n, dt, seed=7)
+    A, Vd, pi_A = _dense_projector(As, V)
+    I = np.eye(A.shape[0])
+    MD = A @ (I - pi_A)
+    fD = (I - pi_A).T @ f
+    for k in (1, 3, 6):
+        r = kr.dcg(As, V, f, kr.exact_inner(E), tol=0.0, max_iter=k, outer='gmres')
+        K = np.stack([np.linalg.matrix_power(MD, i) @ fD for i in range(k)], axis=1)
+        Q, _ = np.linalg.qr(K)
+        c, *_ = np.linalg.lstsq(MD @ Q, fD, rcond=None)
+        best = np.linalg.norm(fD - MD @ (Q @ c))
+        assert r.iterations == k
+        assert abs(r.rel_res_recurrence * np.linalg.norm(f) - best) <= 1e-9 * np.linalg.norm(f)
+        assert np.linalg.norm(r.x_hat - Q @ c) <= 1e-8 * np.linalg.norm(Q @ c)
+
+
+def test_gmres_reaches_the_dense_solution_in_no_more_steps_than_cg():
+    # exact inner solves: the minimal-residual property makes GMRES need at
+    # most as many steps as CG on the same Krylov spaces
+    n, dt = 16, 1e-2
+    As, V, E, f = _problem(n, dt, seed=8)
+    xs = np.linalg.solve(As.toarray(), f)
+    g = kr.dcg(As, V, f, kr.exact_inner(E), tol=1e-10, outer='gmres', max_iter=2000)
+    c = kr.dcg(As, V, f, kr.exact_inner(E), tol=1e-10, max_iter=2000)
+    assert np.linalg.norm(g.x - xs) <= 1e-8 * np.linalg.norm(xs)
+    assert g.rel_res_true <= 2e-10
+    assert g.iterations <= c.iterations
+
+
+def test_gmres_with_adaptive_inexact_inner_solves_converges():
+    # Remark 6: GMRES with the adaptive inner tolerance converges robustly
+    n, dt, tol = 32, 1e-3, 1e-8
+    As, V, E, f = _problem(n, dt, seed=9)
+    H = mg.Hierarchy(E, n)
+    r = kr.dcg(As, V, f, kr.mg_inner(H), tol=tol, outer='gmres', c_A=0.01, max_iter=1000)
+    assert r.rel_res_recurrence <= tol
+    assert r.rel_res_true <= 20 * tol
+    # and, as for the CG family (Table 3), the relaxed inner solves cost fewer cycles
+    fixed = kr.dcg(As, V, f, kr.mg_inner(H), tol=tol, outer='gmres', c_F=0.01, max_iter=1000)
+    assert r.total_cycles < 0.8 * fixed.total_cycles, (r.total_cycles, fixed.total_cycles)
