@@ -313,7 +313,7 @@ def timestep(args):
 def variants(args):
     """The inner-tolerance rule and outer variant at the headline size: the
     fixed rule (eq. (fixed_tol), c_F = 0.01) against the adaptive rule
-    (eq. (tol), c_A = 0.01) with CG, FCG(1) and FCG(8); one solve each."""
+    (eq. (tol), c_A = 0.01) with CG, FCG(1), FCG(8) and GMRES; one solve each."""
     import torch
     import paper_2606_13429_amd as dcg
     from dcg_workloads import rhs
@@ -322,7 +322,7 @@ def variants(args):
     b = torch.from_numpy(rhs(n, 0)).cuda()
     x = torch.empty_like(b)
     rows = []
-    for outer, c_A in (("cg", 0.0), ("cg", 0.01), ("fcg1", 0.01), ("fcg", 0.01)):
+    for outer, c_A in (("cg", 0.0), ("cg", 0.01), ("fcg1", 0.01), ("fcg", 0.01), ("gmres", 0.01)):
         solver = dcg.Solver(n, dt, prec="mixed", outer=outer, c_A=c_A, m_max=8)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -69,11 +69,16 @@ typedef enum {
   DCG_OUTER_CG = 0,   /* Fletcher-Reeves beta = rho_new / rho (Tables 2-3)    */
   DCG_OUTER_FCG1 = 1, /* flexible CG with one stored direction, Algorithm 1
                          truncated to m_i = 1 (Remark 5, m_max = 1)           */
-  DCG_OUTER_FCG = 2   /* flexible CG, Algorithm 1 with the truncation of
+  DCG_OUTER_FCG = 2,  /* flexible CG, Algorithm 1 with the truncation of
                          Remark 5, m_0 = 0, m_i = max{1, mod(i, m_max + 1)};
                          m_max = 0 means FCG(inf), m_i = i (every direction
                          kept: 2 vectors of 16 n^2 doubles per iteration --
                          meant for small n).  dcg_solve only.                 */
+  DCG_OUTER_GMRES = 3 /* unrestarted GMRES on the deflated system (Remark 6):
+                         Arnoldi basis orthogonalised by two classical
+                         Gram-Schmidt passes, stop on the minimal residual
+                         ||r_i|| <= tol ||b||; keeps one vector of 16 n^2
+                         doubles per iteration (small n).  dcg_solve only.    */
 } dcg_outer;
 
 typedef struct {

@@ -8,10 +8,10 @@ if the library has not been built.
 """
 from ._binding import *          # noqa: F401,F403  (the C entry points)
 from ._binding import (DCGError, dcg_defaults, dcg_destroy, dcg_setup, dcg_solve,
-                       DCG_FP64, DCG_MIXED, DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_OUTER_FCG, DCG_PENDING,
-                       LIB_PATH)
+                       DCG_FP64, DCG_MIXED, DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_OUTER_FCG,
+                       DCG_OUTER_GMRES, DCG_PENDING, LIB_PATH)
 
-_OUTER = {"cg": DCG_OUTER_CG, "fcg1": DCG_OUTER_FCG1, "fcg": DCG_OUTER_FCG}
+_OUTER = {"cg": DCG_OUTER_CG, "fcg1": DCG_OUTER_FCG1, "fcg": DCG_OUTER_FCG, "gmres": DCG_OUTER_GMRES}
 
 __all__ = ["Solver", "Server", "DCGError", "LIB_PATH"]
 
@@ -26,8 +26,9 @@ class Solver:
     def __init__(self, n, dt, nu=1.0, prec="mixed", outer="cg", penalty=10.0, pre=2, post=2,
                  c_F=0.01, max_outer=50000, max_inner=100, x0_given=False, use_graph=True,
                  c_A=0.0, m_max=8):
-        """outer: "cg", "fcg1" or "fcg" (truncated FCG with m_max, FCG(inf) for
-        m_max = 0); c_A > 0 selects the adaptive inner tolerance of eq. (tol)."""
+        """outer: "cg", "fcg1", "fcg" (truncated FCG with m_max, FCG(inf) for
+        m_max = 0) or "gmres"; c_A > 0 selects the adaptive inner tolerance of
+        eq. (tol)."""
         mesh, opt = dcg_defaults()
         mesh.n, mesh.penalty, mesh.pre, mesh.post = n, penalty, pre, post
         opt.prec = {"mixed": DCG_MIXED, "fp64": DCG_FP64}[prec]

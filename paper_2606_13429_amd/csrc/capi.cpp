@@ -48,7 +48,8 @@ bool valid_mesh(const dcg_mesh& m, std::string& why) {
 
 dcg_status check_options(const dcg_options& o) {
   if (o.prec != DCG_FP64 && o.prec != DCG_MIXED) return fail(nullptr, DCG_EINVAL, "bad precision");
-  if (o.outer != DCG_OUTER_CG && o.outer != DCG_OUTER_FCG1 && o.outer != DCG_OUTER_FCG)
+  if (o.outer != DCG_OUTER_CG && o.outer != DCG_OUTER_FCG1 && o.outer != DCG_OUTER_FCG &&
+      o.outer != DCG_OUTER_GMRES)
     return fail(nullptr, DCG_EINVAL, "bad outer variant");
   if (!(o.c_A >= 0.0) || !std::isfinite(o.c_A)) return fail(nullptr, DCG_EINVAL, "c_A must be >= 0");
   if (o.m_max < 0) return fail(nullptr, DCG_EINVAL, "m_max must be >= 0");
@@ -230,7 +231,7 @@ dcg_status dcg_server_create(const dcg_options* opt, dcg_server* out) {
   if (opt) o = *opt;
   if (const dcg_status cs = check_options(o); cs != DCG_OK) return cs;
   if (o.max_pending < 1) return fail(nullptr, DCG_EINVAL, "max_pending must be >= 1");
-  if (o.outer == DCG_OUTER_FCG)
+  if (o.outer == DCG_OUTER_FCG || o.outer == DCG_OUTER_GMRES)
     return fail(nullptr, DCG_EINVAL, "the server runs DCG_OUTER_CG or DCG_OUTER_FCG1");
   if (o.hbm_budget_bytes < 0) return fail(nullptr, DCG_EINVAL, "hbm_budget_bytes must be >= 0");
   return guarded(nullptr, [&]() {

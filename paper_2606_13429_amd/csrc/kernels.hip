@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_fcg_dot(int64_t n, const double* _
   if (threadIdx.x == 0) part[(int64_t)k * gridDim.x + blockIdx.x] = t;
 }
 
-// coef[k] = -(sum of the k-th partials, in block order) / dq_k.
+// coef[k] = -(sum of the k-th partials, in block order) / dq_k (dq == nullptr: -sum).
 __global__ __launch_bounds__(kThreads) void k_fcg_coef(const double* __restrict__ part, int nb,
                                                        const double* __restrict__ dq, int first,
                                                        int R, double* __restrict__ coef) {
@@ -374,13 +374,14 @@ __global__ __launch_bounds__(kThreads) void k_fcg_coef(const double* __restrict_
   double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += kThreads) acc += part[(int64_t)k * nb + b];
   const double t = block_sum(acc, lds);
-  if (threadIdx.x == 0) coef[k] = -t / dq[(first + k) % R];
+  if (threadIdx.x == 0) coef[k] = dq ? -t / dq[(first + k) % R] : -t;
 }
 
+// d may alias r (in-place Gram-Schmidt update): element i is read before it is
+// written by the same thread.
 __global__ __launch_bounds__(kThreads) void k_fcg_direction(
-    int64_t n, const double* __restrict__ r, const double* const* __restrict__ dptr, int first,
-    int m, int R, const double* __restrict__ coef, double* __restrict__ d,
-    double* __restrict__ part) {
+    int64_t n, const double* r, const double* const* __restrict__ dptr, int first, int m, int R,
+    const double* __restrict__ coef, double* d, double* __restrict__ part) {
   __shared__ double lds[4];
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;

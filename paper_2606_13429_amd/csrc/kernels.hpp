@@ -123,7 +123,8 @@ hipError_t launch_bdf2_rhs(int ne, const double* M1, double inv_nu, const double
 // directions d_k, q_k = M_D d_k of slots (first + k) % R, k < m, is addressed
 // through device pointer arrays dptr / qptr and the device array dq of
 // (d_k, q_k).
-//   launch_fcg_coef:      coef[k] = -(r, q_k) / dq_k  (partials in part, then a
+//   launch_fcg_coef:      coef[k] = -(r, q_k) / dq_k, or -(r, q_k) when dq is
+//                         nullptr (the Gram-Schmidt coefficients of GMRES) (partials in part, then a
 //                         fixed-order reduction per k; ``part`` holds m x
 //                         fcg_coef_blocks(n) doubles)
 //   launch_fcg_direction: d = r + sum_k coef[k] d_k (k ascending), partial (d, r)

@@ -86,8 +86,9 @@ struct LevelBuffers {
   void allocate(const MeshContext& m, bool fp32, bool batch, Workspace& ws);
 };
 
-// Stored directions of the flexible outer iteration: R slots of (d, q) with
-// device pointer arrays and (d, q) values; vectors are allocated on first use.
+// Stored directions of the flexible outer iteration (R slots of (d, q) with
+// device pointer arrays and (d, q) values) or the Arnoldi basis of GMRES (d
+// only); vectors are allocated on first use.
 struct FcgStore {
   int R = 0;
   std::vector<double*> d, q;
@@ -95,6 +96,7 @@ struct FcgStore {
   double** qptr = nullptr;
   double* dq = nullptr;
   double* coef = nullptr;
+  double* coef2 = nullptr;
   double* part = nullptr;
   std::vector<void*> vecs;
   void* alloc(size_t bytes);

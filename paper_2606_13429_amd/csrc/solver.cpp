@@ -40,10 +40,10 @@ void FcgStore::release() {
   for (void* p : vecs) (void)hipFree(p);
   vecs.clear();
   for (void* p : {static_cast<void*>(dptr), static_cast<void*>(qptr), static_cast<void*>(dq),
-                  static_cast<void*>(coef), static_cast<void*>(part)})
+                  static_cast<void*>(coef), static_cast<void*>(coef2), static_cast<void*>(part)})
     if (p) (void)hipFree(p);
   dptr = qptr = nullptr;
-  dq = coef = part = nullptr;
+  dq = coef = coef2 = part = nullptr;
   d.clear();
   q.clear();
   R = 0;
@@ -248,6 +248,35 @@ void handle_init(dcg_ctx* h) {
   DCG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
 }
 
+// ------------------------------------------------------------ stored directions
+// (Re)sizes the slot tables of ``fs`` for R slots of vectors of length N.
+void store_reserve(FcgStore& fs, int R, int64_t N) {
+  if (fs.R == R) return;
+  fs.release();
+  fs.R = R;
+  fs.d.assign(R, nullptr);
+  fs.q.assign(R, nullptr);
+  DCG_HIP(hipMalloc(&fs.dptr, sizeof(double*) * R));
+  DCG_HIP(hipMalloc(&fs.qptr, sizeof(double*) * R));
+  DCG_HIP(hipMalloc(&fs.dq, sizeof(double) * R));
+  DCG_HIP(hipMalloc(&fs.coef, sizeof(double) * R));
+  DCG_HIP(hipMalloc(&fs.coef2, sizeof(double) * R));
+  DCG_HIP(hipMalloc(&fs.part, sizeof(double) * size_t(R) * fcg_coef_blocks(N)));
+}
+
+// Allocates the vectors of ``slot`` on first use (d, and q when ``with_q``)
+// and publishes their addresses in the device pointer tables.
+void store_slot(FcgStore& fs, int slot, int64_t N, bool with_q) {
+  if (!fs.d[slot]) {
+    fs.d[slot] = static_cast<double*>(fs.alloc(sizeof(double) * N));
+    DCG_HIP(hipMemcpy(fs.dptr + slot, &fs.d[slot], sizeof(double*), hipMemcpyHostToDevice));
+  }
+  if (with_q && !fs.q[slot]) {
+    fs.q[slot] = static_cast<double*>(fs.alloc(sizeof(double) * N));
+    DCG_HIP(hipMemcpy(fs.qptr + slot, &fs.q[slot], sizeof(double*), hipMemcpyHostToDevice));
+  }
+}
+
 // ------------------------------------------------------------ flexible CG
 // Outer iterations of Algorithm 1 on the deflated system with the truncation
 // of Remark 5: m_0 = 0, m_i = max{1, mod(i, m_max + 1)} (m_i = i for
@@ -266,17 +295,7 @@ dcg_status outer_fcg(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_t
   const int64_t N = 16 * int64_t(ne);
   const bool inf = h->opt.m_max == 0;
   const int R = inf ? h->opt.max_outer + 1 : h->opt.m_max + 1;
-  if (fs.R != R) {
-    fs.release();
-    fs.R = R;
-    fs.d.assign(R, nullptr);
-    fs.q.assign(R, nullptr);
-    DCG_HIP(hipMalloc(&fs.dptr, sizeof(double*) * R));
-    DCG_HIP(hipMalloc(&fs.qptr, sizeof(double*) * R));
-    DCG_HIP(hipMalloc(&fs.dq, sizeof(double) * R));
-    DCG_HIP(hipMalloc(&fs.coef, sizeof(double) * R));
-    DCG_HIP(hipMalloc(&fs.part, sizeof(double) * size_t(R) * fcg_coef_blocks(N)));
-  }
+  store_reserve(fs, R, N);
   const int nbA = astar_blocks(ne);
   dcg_status status = DCG_OK;
   while (true) {
@@ -287,12 +306,7 @@ dcg_status outer_fcg(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_t
     }
     const int mi = inf ? it : (it == 0 ? 0 : std::max(1, it % (h->opt.m_max + 1)));
     const int slot = it % R;
-    if (!fs.d[slot]) {   // first use of the slot
-      fs.d[slot] = static_cast<double*>(fs.alloc(sizeof(double) * N));
-      fs.q[slot] = static_cast<double*>(fs.alloc(sizeof(double) * N));
-      DCG_HIP(hipMemcpy(fs.dptr + slot, &fs.d[slot], sizeof(double*), hipMemcpyHostToDevice));
-      DCG_HIP(hipMemcpy(fs.qptr + slot, &fs.q[slot], sizeof(double*), hipMemcpyHostToDevice));
-    }
+    store_slot(fs, slot, N, true);
     const int first = ((it - mi) % R + R) % R;
     DCG_HIP(launch_fcg_coef(N, ws.r, fs.qptr, fs.dq, first, mi, R, fs.part, fs.coef, st));
     int nbd = 0;
@@ -317,6 +331,107 @@ dcg_status outer_fcg(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_t
     if (ws.sc_host->breakdown) return DCG_EBREAKDOWN;
     rho = ws.sc_host->rho;
     if (!std::isfinite(rho)) return DCG_EBREAKDOWN;
+  }
+  return status;
+}
+
+// ------------------------------------------------------------ GMRES
+// Unrestarted GMRES on the deflated system M_D x = f_D (Remark 6).  The
+// Arnoldi basis v_0 = r / ||r||, v_{j+1} = (M_D v_j - sum_i h_ij v_i) / h_{j+1,j}
+// lives on the device; each new vector is orthogonalised against the basis
+// by two classical Gram-Schmidt passes (multi-dot, then one combined update,
+// twice), which is as stable as modified Gram-Schmidt and needs two global
+// reductions instead of j + 1.  The (j + 2) x (j + 1) Hessenberg column and
+// its Givens rotations are handled on the host; the stopping test is the
+// minimal residual |g_{j+1}| <= tol ||f||, and the inner tolerance of each
+// product follows the current minimal residual.  x_hat = x_0 + V y at the end.
+template <typename TolFn>
+dcg_status outer_gmres(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_total,
+                       int& cycles_outer, int& inner_solves, TolFn tol_outer, hipStream_t st) {
+  MeshContext& m = *h->mesh;
+  Workspace& ws = h->ws;
+  FcgStore& fs = ws.fcg;
+  const int ne = m.ne;
+  const int64_t N = 16 * int64_t(ne);
+  const int R = h->opt.max_outer + 2;
+  store_reserve(fs, R, N);
+  double rnorm = std::sqrt(std::max(rho, 0.0));
+  if (rho <= lim || h->opt.max_outer == 0)
+    return rho <= lim ? DCG_OK : DCG_NOT_CONVERGED;
+  store_slot(fs, 0, N, false);
+  DCG_HIP(launch_scale(N, 1.0 / rnorm, ws.r, fs.d[0], st));
+  std::vector<std::vector<double>> H;     // rotated Hessenberg columns
+  std::vector<double> cs, sn, g{rnorm};
+  std::vector<double> c1, c2;
+  dcg_status status = DCG_OK;
+  while (true) {
+    if (rnorm * rnorm <= lim) break;
+    if (it >= h->opt.max_outer) {
+      status = DCG_NOT_CONVERGED;
+      break;
+    }
+    const int j = it;
+    // q = M_D v_j
+    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, fs.d[j], nullptr, nullptr, ws.sc,
+                         nullptr, ws.w, ws.s, nullptr, st));
+    const int c = inner(h, ws.s, ws.zref, tol_outer(rnorm * rnorm), st);
+    cycles_total += c;
+    cycles_outer += c;
+    ++inner_solves;
+    DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zref, ws.w, fs.d[j], ws.q, nullptr,
+                           ws.part, st));
+    // two Gram-Schmidt passes in place on q, then ||q||^2
+    int nbd = 0;
+    DCG_HIP(launch_fcg_coef(N, ws.q, fs.dptr, nullptr, 0, j + 1, R, fs.part, fs.coef, st));
+    DCG_HIP(launch_fcg_direction(N, ws.q, fs.dptr, 0, j + 1, R, fs.coef, ws.q, ws.part, &nbd, st));
+    DCG_HIP(launch_fcg_coef(N, ws.q, fs.dptr, nullptr, 0, j + 1, R, fs.part, fs.coef2, st));
+    DCG_HIP(launch_fcg_direction(N, ws.q, fs.dptr, 0, j + 1, R, fs.coef2, ws.q, ws.part, &nbd, st));
+    int nbu = 0;
+    DCG_HIP(launch_axpy_dot(N, 0.0, ws.q, ws.q, ws.part, &nbu, st));
+    DCG_HIP(launch_reduce(ws.part, nbu, kRedRho, ws.sc, st));
+    read_scalars(h, st);
+    c1.resize(j + 1);
+    c2.resize(j + 1);
+    DCG_HIP(hipMemcpy(c1.data(), fs.coef, sizeof(double) * (j + 1), hipMemcpyDeviceToHost));
+    DCG_HIP(hipMemcpy(c2.data(), fs.coef2, sizeof(double) * (j + 1), hipMemcpyDeviceToHost));
+    const double hn = std::sqrt(std::max(ws.sc_host->rho, 0.0));
+    if (!std::isfinite(hn)) return DCG_EBREAKDOWN;
+    std::vector<double> col(j + 2);
+    for (int i = 0; i <= j; ++i) col[i] = -(c1[i] + c2[i]);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {           // earlier rotations
+      const double a = col[i], b = col[i + 1];
+      col[i] = cs[i] * a + sn[i] * b;
+      col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double den = std::hypot(col[j], col[j + 1]);
+    if (!(den > 0.0)) return DCG_EBREAKDOWN;
+    cs.push_back(col[j] / den);
+    sn.push_back(col[j + 1] / den);
+    col[j] = den;
+    col[j + 1] = 0.0;
+    g.push_back(-sn[j] * g[j]);
+    g[j] = cs[j] * g[j];
+    H.push_back(std::move(col));
+    rnorm = std::fabs(g[j + 1]);
+    ++it;
+    if (hn > 0.0) {                          // hn = 0: invariant space, residual 0
+      store_slot(fs, j + 1, N, false);
+      DCG_HIP(launch_scale(N, 1.0 / hn, ws.q, fs.d[j + 1], st));
+    }
+  }
+  rho = rnorm * rnorm;
+  const int k = it;
+  if (k > 0) {                               // y = R^{-1} g, x_hat += V y
+    std::vector<double> y(k);
+    for (int r = k - 1; r >= 0; --r) {
+      double acc = g[r];
+      for (int cc = r + 1; cc < k; ++cc) acc -= H[cc][r] * y[cc];
+      y[r] = acc / H[r][r];
+    }
+    DCG_HIP(hipMemcpy(fs.coef, y.data(), sizeof(double) * k, hipMemcpyHostToDevice));
+    int nbd = 0;
+    DCG_HIP(launch_fcg_direction(N, ws.xh, fs.dptr, 0, k, R, fs.coef, ws.xh, ws.part, &nbd, st));
   }
   return status;
 }
@@ -391,6 +506,9 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
   dcg_status status = DCG_OK;
   if (h->opt.outer == DCG_OUTER_FCG) {
     status = outer_fcg(h, lim, rho, it, cycles_total, cycles_outer, inner_solves, tol_outer, stream);
+  } else if (h->opt.outer == DCG_OUTER_GMRES) {
+    status = outer_gmres(h, lim, rho, it, cycles_total, cycles_outer, inner_solves, tol_outer,
+                         stream);
   } else {
     while (true) {
       if (rho <= lim) break;

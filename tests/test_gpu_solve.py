@@ -151,12 +151,12 @@ def test_repeated_solves_are_bitwise_identical():
 # rule (340 against 694 in the oracle): the case checks that the GPU follows.
 _VARIANTS = [("fcg", 4, 0.0, 1e-3), ("fcg", 0, 0.0, 1e-3), ("fcg", 0, 0.01, 1e-3),
              ("cg", 8, 0.01, 1e-3), ("fcg1", 8, 0.01, 1e-3), ("fcg", 4, 0.01, 1e-3),
-             ("cg", 8, 0.01, 1e-2)]
+             ("cg", 8, 0.01, 1e-2), ("gmres", 8, 0.0, 1e-3), ("gmres", 8, 0.01, 1e-3)]
 
 
 @pytest.mark.parametrize("outer,m_max,c_A,dt", _VARIANTS,
                          ids=["fcg4", "fcginf", "fcginf-adaptive", "cg-adaptive", "fcg1-adaptive",
-                              "fcg4-adaptive", "cg-adaptive-dt1e-2"])
+                              "fcg4-adaptive", "cg-adaptive-dt1e-2", "gmres", "gmres-adaptive"])
 def test_outer_variants_and_adaptive_tolerance_match_oracle(outer, m_max, c_A, dt):
     n, tol = 32, 1e-8
     As = d.operator(n, dt)
@@ -165,7 +165,7 @@ def test_outer_variants_and_adaptive_tolerance_match_oracle(outer, m_max, c_A, d
     seed = 6 if dt == 1e-3 else 0
     f = elem_to_comp(rhs(n, seed), n)
     kw = {"cg": dict(outer="cg"), "fcg1": dict(outer="fcg", m_max=1),
-          "fcg": dict(outer="fcg", m_max=m_max or None)}[outer]
+          "fcg": dict(outer="fcg", m_max=m_max or None), "gmres": dict(outer="gmres")}[outer]
     ref = kr.dcg(As, V, f, kr.mg_inner(mg.Hierarchy(E, n)), tol=tol, c_A=c_A or None, **kw)
     status, st, x, _ = _gpu(n, dt, seed, tol, "mixed", outer=outer, m_max=m_max, c_A=c_A)
     xr = comp_to_elem(ref.x, n)
