@@ -47,7 +47,7 @@ def _gpu(n, dt, seed, tol, prec, outer="cg", **kw):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("n,dt", [(16, 1e-2), (32, 1e-3), (64, 1e-5)])
+@pytest.mark.parametrize("n,dt", [(16, 1e-2), (32, 1e-3), (64, 1e-5), (128, 1e-5)])
 def test_solve_matches_oracle(n, dt, prec):
     ref = _oracle(n, dt, 0, 1e-8)
     status, st, x, _ = _gpu(n, dt, 0, 1e-8, prec)
