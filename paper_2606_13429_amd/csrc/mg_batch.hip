@@ -87,7 +87,8 @@ __device__ __forceinline__ void current_z_b(const SweepArgs<T>& a, int e, int c,
 //      the step streams from HBM);
 //   2. z on the 52 squares near the tile: z_old + pending Y [+ P e_coarse],
 //      kept in LDS; the core squares are written to z_new;
-//   3. U = f - L_k z on the 32 block squares (128 x kBatch), in LDS;
+//   3. U = f - L_k z on the 32 block squares (128 x kBatch), in LDS, each
+//      operator row loaded once for four requests;
 //   4. wavefront w computes the row blocks P = w and P = 7 - w of
 //      (L_k)_t^{-1} U: 8 column blocks Q x 4 MFMA k-steps each.  Blocks
 //      with P <= Q are read as stored (row r, columns 4k..4k+3 as one
@@ -105,23 +106,25 @@ __global__ __launch_bounds__(kThreads) void k_sweep_b(SweepArgs<T> a) {
   const bool need_z = a.has_z || a.has_y || a.prol;
 
   // MFMA A operands: lane (r, k) of k-step kk holds row 16 P + r, column
-  // 16 Q + 4 k + kk of the tile inverse
+  // 16 Q + 4 k + kk of the tile inverse; column blocks are loaded two ahead
+  // of their use (the first two before the gather and residual phases)
   const T* Ft = a.F + (int64_t)t * (36 * 256);
-  T av[2][8][4];
-#pragma unroll
-  for (int Q = 0; Q < 8; ++Q) {
+  auto load_q = [&](int Q, T (&dst)[2][4]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int P = Pw[h];
       if (P <= Q) {
-        ld4(Ft + blk_index(P, Q) * 256 + r * 16 + 4 * k, av[h][Q]);
+        ld4(Ft + blk_index(P, Q) * 256 + r * 16 + 4 * k, dst[h]);
       } else {
         const T* bt = Ft + blk_index(Q, P) * 256 + 64 * k + r;
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) av[h][Q][kk] = bt[16 * kk];
+        for (int kk = 0; kk < 4; ++kk) dst[h][kk] = bt[16 * kk];
       }
     }
-  }
+  };
+  T av[3][2][4];
+  load_q(0, av[0]);
+  load_q(1, av[1]);
 
   for (int it = tid; it < 52 * B; it += kThreads) {
     const int q = it / B, c = it % B;
@@ -138,12 +141,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep_b(SweepArgs<T> a) {
     ld4(&zn[q][c][0], z);
     st4(a.z_new + at(e, c), z);
   }
-  for (int it = tid; it < 32 * B; it += kThreads) {
-    const int p = it / B, c = it % B;
+  // U = f - L_k z: thread (block square p, row j, requests 4 g .. 4 g + 3), so
+  // that each operator row is loaded once and applied to four requests' z
+  // from LDS
+#pragma unroll
+  for (int k2 = 0; k2 < 32 * 16 / kThreads; ++k2) {
+    const int it = tid + k2 * kThreads;
+    const int p = it >> 4, j = (it >> 2) & 3, g = it & 3;
     const int e = ext_square(t, p, a.n);
     T u[4] = {T(0), T(0), T(0), T(0)};
     if (e >= 0) {
-      ld4(a.f + at(e, c), u);
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) u[cc] = a.f[at(e, 4 * g + cc) + j];
       if (need_z) {
         const int ex = e % a.n, ey = e / a.n;
         T acc[4] = {T(0), T(0), T(0), T(0)};
@@ -151,20 +160,22 @@ __global__ __launch_bounds__(kThreads) void k_sweep_b(SweepArgs<T> a) {
         for (int s = 0; s < 5; ++s) {
           const int dx = s == 1 ? -1 : (s == 2 ? 1 : 0), dy = s == 3 ? -1 : (s == 4 ? 1 : 0);
           if (ex + dx < 0 || ex + dx >= a.n || ey + dy < 0 || ey + dy >= a.n) continue;
-          T zq[4];
-          ld4(&zn[nbr_slot(p, s)][c][0], zq);
+          T l[4];
+          ld4(a.L + (((int64_t)s * a.ne + e) * 4 + j) * 4, l);
+          const int q = nbr_slot(p, s);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            T l[4];
-            ld4(a.L + (((int64_t)s * a.ne + e) * 4 + j) * 4, l);
-            acc[j] += l[0] * zq[0] + l[1] * zq[1] + l[2] * zq[2] + l[3] * zq[3];
+          for (int cc = 0; cc < 4; ++cc) {
+            T zq[4];
+            ld4(&zn[q][4 * g + cc][0], zq);
+            acc[cc] += l[0] * zq[0] + l[1] * zq[1] + l[2] * zq[2] + l[3] * zq[3];
           }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) u[j] -= acc[j];
+        for (int cc = 0; cc < 4; ++cc) u[cc] -= acc[cc];
       }
     }
-    st4(&ul[p][c][0], u);
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) ul[p][4 * g + cc][j] = u[cc];
   }
   __syncthreads();
 
@@ -172,12 +183,14 @@ __global__ __launch_bounds__(kThreads) void k_sweep_b(SweepArgs<T> a) {
   V acc0 = {T(0), T(0), T(0), T(0)}, acc1 = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int Q = 0; Q < 8; ++Q) {
+    if (Q + 2 < 8) load_q(Q + 2, av[(Q + 2) % 3]);
     T bq[4];
     ld4(&ul[4 * Q + k][r][0], bq);
+    const T (&aq)[2][4] = av[Q % 3];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      acc0 = Mfma<T>::mac(av[0][Q][kk], bq[kk], acc0);
-      acc1 = Mfma<T>::mac(av[1][Q][kk], bq[kk], acc1);
+      acc0 = Mfma<T>::mac(aq[0][kk], bq[kk], acc0);
+      acc1 = Mfma<T>::mac(aq[1][kk], bq[kk], acc1);
     }
   }
 
