@@ -10,6 +10,7 @@ operators and vectors resident in HBM; ``value`` is solves per second.
 
 Also reported on the same JSON line:
   fp64          one solve of the all-FP64 form (same RHS), for the comparison
+  adaptive_inner_tol  one solve with the adaptive inner tolerance of eq. (tol)
   roofline      the dominant kernel (finest-level RAS tile solves): algorithmic
                 bytes per launch / average launch time measured with HIP events
                 around every launch inside the timed solves
@@ -151,7 +152,7 @@ def serving(args):
                           dt_range=SERVING["dt_range"])
     tol = SERVING["tol"]
     torch.cuda.set_device(0)
-    srv = dcg.Server(prec="mixed", max_outer=args.serve_max_outer)
+    srv = dcg.Server(prec="mixed", max_outer=args.serve_max_outer, c_A=args.serve_c_A)
     t0 = time.time()
     for n in sizes:
         srv.prepare(n)
@@ -202,7 +203,7 @@ def serving(args):
     # a request alone in a fresh server gives bitwise the same x and counts
     probe = int(np.argmin([d["wcycles"] if d["status"] == lib.DCG_OK and d["n"] == 64 else 1 << 30
                            for d in done]))
-    alone = dcg.Server(prec="mixed", max_outer=args.serve_max_outer)
+    alone = dcg.Server(prec="mixed", max_outer=args.serve_max_outer, c_A=args.serve_c_A)
     xa = torch.empty_like(xs[probe])
     r = trace[probe]
     status, st = alone.wait(alone.submit(r["n"], r["dt"], bs[probe], xa, tol))
@@ -215,9 +216,10 @@ def serving(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 outer / f32 multigrid", "data": "synthetic: serving trace seed 0",
         "config": {"workload": "serving trace: %d requests, Poisson %.0f/s, n in %s, dt 10^U%s, "
-                               "tol %g, mixed form, max_outer %d"
+                               "tol %g, mixed form, max_outer %d, inner tolerance %s"
                                % (len(trace), SERVING["rate"], list(sizes), tuple(SERVING["dt_range"]),
-                                  tol, args.serve_max_outer)},
+                                  tol, args.serve_max_outer,
+                                  "adaptive c_A=%g" % args.serve_c_A if args.serve_c_A else "fixed c_F=0.01")},
         "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
         "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
         "makespan_s": round(makespan, 2), "not_converged": len(capped), "failed": len(failed),
@@ -371,6 +373,8 @@ def main():
     ap.add_argument("--requests", type=int, default=256, help="serving: trace length")
     ap.add_argument("--serve-max-outer", type=int, default=2000,
                     help="serving: max_outer of every request (NOT_CONVERGED beyond, reported)")
+    ap.add_argument("--serve-c-A", type=float, default=0.0,
+                    help="serving: adaptive inner tolerance constant (0 = the fixed rule)")
     ap.add_argument("--dt-sweep", action="store_true", help="run the dt sweep at --sweep-n")
     ap.add_argument("--sweep-n", type=int, default=128)
     ap.add_argument("--sweep-max-outer", type=int, default=20000)
@@ -489,6 +493,23 @@ def main():
         if rel is not None:
             result["fp64"]["mixed_vs_fp64_rel_diff"] = rel
         s64.close()
+
+    if not args.skip_fp64:
+        # the paper's adaptive inner tolerance (eq. (tol), c_A = 0.01) on the same
+        # solve, for reference; the headline keeps the fixed rule of the workload
+        log("adaptive inner tolerance: one solve")
+        sa = dcg.Solver(n, dt, prec="mixed", c_A=0.01, max_outer=args.max_outer)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, sta = sa.solve(bs[0], x, tol)
+        torch.cuda.synchronize()
+        ta = time.time() - t0
+        result["adaptive_inner_tol"] = {"c_A": 0.01, "solves_per_s": round(1.0 / ta, 5),
+                                        "outer_iters": sta.outer_iters,
+                                        "total_wcycles": sta.total_wcycles,
+                                        "rel_res_true": sta.rel_res_true,
+                                        "speedup_vs_fixed_rule": round(1.0 / (value * ta), 3)}
+        sa.close()
 
     if not args.skip_cpu:
         log("CPU oracle baseline (setup is not counted)")

@@ -184,6 +184,7 @@ struct Server::Impl {
   std::thread thread;
 
   void run();
+  void step_all();
   void admit();
   bool make_room(size_t need);
   size_t used_bytes() const;
@@ -703,41 +704,53 @@ void Server::Impl::run() {
       std::unique_lock<std::mutex> lk(mu);
       if (stop) break;
     }
-    admit();
-    for (auto& kv : groups) {
-      Group& g = *kv.second;
-      if (g.inflight || g.active == 0) continue;
-      try {
-        enqueue_step(g);
-      } catch (const Error& e) {
-        fail_group(g, e);
-      }
-    }
-    bool any_inflight = false, progressed = false;
-    for (auto& kv : groups) {
-      Group& g = *kv.second;
-      if (!g.inflight) continue;
-      any_inflight = true;
-      const hipError_t q = hipEventQuery(g.done);
-      if (q == hipErrorNotReady) continue;
-      progressed = true;
-      try {
-        DCG_HIP(q);
-        process(g);
-      } catch (const Error& e) {
-        fail_group(g, e);
-      }
-    }
-    if (!any_inflight) {
-      std::unique_lock<std::mutex> lk(mu);
-      cv.wait_for(lk, std::chrono::milliseconds(20), [&] { return stop || !queue.empty(); });
-    } else if (!progressed) {
-      std::this_thread::sleep_for(std::chrono::microseconds(5));
+    try {
+      step_all();
+    } catch (const std::exception& ex) {
+      // anything but a library error (host allocation, ...): every running
+      // request ends with it; the server keeps serving
+      const Error e(dynamic_cast<const std::bad_alloc*>(&ex) ? DCG_ENOMEM : DCG_EDEVICE, ex.what());
+      for (auto& kv : groups) fail_group(*kv.second, e);
     }
   }
   for (auto& kv : groups)
     if (kv.second->inflight) (void)hipStreamSynchronize(kv.second->stream);
   groups.clear();
+}
+
+// One pass of the scheduler loop.
+void Server::Impl::step_all() {
+  admit();
+  for (auto& kv : groups) {
+    Group& g = *kv.second;
+    if (g.inflight || g.active == 0) continue;
+    try {
+      enqueue_step(g);
+    } catch (const Error& e) {
+      fail_group(g, e);
+    }
+  }
+  bool any_inflight = false, progressed = false;
+  for (auto& kv : groups) {
+    Group& g = *kv.second;
+    if (!g.inflight) continue;
+    any_inflight = true;
+    const hipError_t q = hipEventQuery(g.done);
+    if (q == hipErrorNotReady) continue;
+    progressed = true;
+    try {
+      DCG_HIP(q);
+      process(g);
+    } catch (const Error& e) {
+      fail_group(g, e);
+    }
+  }
+  if (!any_inflight) {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait_for(lk, std::chrono::milliseconds(20), [&] { return stop || !queue.empty(); });
+  } else if (!progressed) {
+    std::this_thread::sleep_for(std::chrono::microseconds(5));
+  }
 }
 
 Server::Server(const dcg_options& opt) : impl(new Impl()) {
