@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_b(SweepArgs<T> a) {
   using V = typename Mfma<T>::v4;
   __shared__ __align__(16) T zn[52][B][4];
   __shared__ __align__(16) T ul[32][B][4];
-  const int t = blockIdx.x;
+  const int t = xcd_band_index(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, k = lane >> 4;
   const int Pw[2] = {wave, 7 - wave};
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_b(SweepArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict_res_b(RestrictArgs<T> a) {
   const int nc = a.n >> 1;
-  const int E = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int E = xcd_band_index(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (E >= nc * nc) return;   // whole wavefronts
   const int ch = (threadIdx.x >> 4) & 3, c = threadIdx.x & 15;
   const int EX = E % nc, EY = E / nc;

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs<T> a) {
   const int tl = threadIdx.x / G;       // tile within the workgroup
   const int g = threadIdx.x % G;        // thread within the tile group
   const int wave = g >> 6, lane = threadIdx.x & 63;
-  const int t = blockIdx.x * TPB + tl;
+  const int t = xcd_band_index(blockIdx.x, gridDim.x) * TPB + tl;
   const bool live = t < a.tiles;
   const bool need_z = a.has_z || a.has_y || a.prol;
 
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict_res(RestrictArgs<T> a) {
   __shared__ T rl[kThreads];
-  const int E = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int E = xcd_band_index(blockIdx.x, gridDim.x) * 16 + (threadIdx.x >> 4);
   const int ch = (threadIdx.x >> 2) & 3, j = threadIdx.x & 3;
   const int nc = a.n >> 1;
   const bool live = E < nc * nc;
