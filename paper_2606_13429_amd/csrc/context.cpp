@@ -172,17 +172,11 @@ std::shared_ptr<MeshContext> build_context(int device, int n, double penalty) {
     upload_level_L<double>(hl, dl.L64);
     if (k >= 2) {
       dl.tiles = hl.tiles;
-      dl.tile_elems = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_elems.size()));
-      DCG_HIP(hipMemcpy(dl.tile_elems, hl.tile_elems.data(), sizeof(int32_t) * hl.tile_elems.size(),
-                        hipMemcpyHostToDevice));
       dl.tile_ext = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_ext.size()));
       DCG_HIP(hipMemcpy(dl.tile_ext, hl.tile_ext.data(), sizeof(int32_t) * hl.tile_ext.size(),
                         hipMemcpyHostToDevice));
       dl.tile_dst = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_dst.size()));
       DCG_HIP(hipMemcpy(dl.tile_dst, hl.tile_dst.data(), sizeof(int32_t) * hl.tile_dst.size(),
-                        hipMemcpyHostToDevice));
-      dl.cover = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.cover.size()));
-      DCG_HIP(hipMemcpy(dl.cover, hl.cover.data(), sizeof(int32_t) * hl.cover.size(),
                         hipMemcpyHostToDevice));
     }
   }

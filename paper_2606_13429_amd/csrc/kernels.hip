@@ -517,14 +517,6 @@ __global__ __launch_bounds__(kThreads) void k_refine_residual(
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-template <typename T, bool FIRST>
-__global__ __launch_bounds__(kThreads) void k_refine_update(int64_t m, const T* __restrict__ zJ,
-                                                            double* __restrict__ z) {
-  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (i >= m) return;
-  const double d = static_cast<double>(zJ[i]);
-  z[i] = FIRST ? d : z[i] + d;
-}
 
 // ============================================================ multigrid levels
 // out = L z (RES = false) or out = f - L z (RES = true); thread (square, row).
@@ -548,94 +540,6 @@ __global__ __launch_bounds__(kThreads) void k_lap(const T* __restrict__ L,
   }
   const int64_t i = 4 * (int64_t)e + a;
   out[i] = RES ? f[i] - acc : acc;
-}
-
-// Y_t = F_t^T-weighted solve of tile t: Y[t][i] = sum_j F[t][j][i] r[g(t, j)],
-// i.e. D_t (L_k)_t^{-1} R_t r.  One wavefront per tile; the 128-value gather
-// of r is staged in LDS and broadcast, each lane owns 4 (FP32) or 2 (FP64)
-// output columns and streams the factor row by row with 16-byte loads.
-__global__ __launch_bounds__(kThreads) void k_ras_tiles_f32(const float* __restrict__ F,
-                                                            const int32_t* __restrict__ te,
-                                                            int tiles, const float* __restrict__ r,
-                                                            float* __restrict__ Y) {
-  __shared__ float rl[4][128];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + wave;
-  if (t < tiles && lane < 32) {
-    const int e = te[t * 32 + lane];
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
-    if (e >= 0) ld4(r + 4 * (int64_t)e, v);
-    st4(&rl[wave][4 * lane], v);
-  }
-  __syncthreads();
-  if (t >= tiles) return;
-  const int half = lane >> 5, c4 = lane & 31;
-  const float4* Ft = reinterpret_cast<const float4*>(F + (int64_t)t * 16384);
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll 16
-  for (int m = 0; m < 64; ++m) {
-    const int j = 2 * m + half;
-    const float4 fv = Ft[j * 32 + c4];
-    const float rj = rl[wave][j];
-    a0 += fv.x * rj;
-    a1 += fv.y * rj;
-    a2 += fv.z * rj;
-    a3 += fv.w * rj;
-  }
-  a0 += __shfl_xor(a0, 32, 64);
-  a1 += __shfl_xor(a1, 32, 64);
-  a2 += __shfl_xor(a2, 32, 64);
-  a3 += __shfl_xor(a3, 32, 64);
-  if (half == 0) {
-    const float v[4] = {a0, a1, a2, a3};
-    st4(Y + (int64_t)t * 128 + 4 * c4, v);
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_ras_tiles_f64(const double* __restrict__ F,
-                                                            const int32_t* __restrict__ te,
-                                                            int tiles, const double* __restrict__ r,
-                                                            double* __restrict__ Y) {
-  __shared__ double rl[4][128];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + wave;
-  if (t < tiles && lane < 32) {
-    const int e = te[t * 32 + lane];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (e >= 0) ld4(r + 4 * (int64_t)e, v);
-    st4(&rl[wave][4 * lane], v);
-  }
-  __syncthreads();
-  if (t >= tiles) return;
-  const double2* Ft = reinterpret_cast<const double2*>(F + (int64_t)t * 16384);
-  double a0 = 0.0, a1 = 0.0;
-#pragma unroll 16
-  for (int j = 0; j < 128; ++j) {
-    const double2 fv = Ft[j * 64 + lane];
-    const double rj = rl[wave][j];
-    a0 += fv.x * rj;
-    a1 += fv.y * rj;
-  }
-  reinterpret_cast<double2*>(Y + (int64_t)t * 128)[lane] = make_double2(a0, a1);
-}
-
-// z = (zero ? 0 : z) + sum over the (at most 3) blocks covering the square,
-// in increasing block order (R_i^T D_i summation of the RAS update).
-template <typename T, bool ZERO>
-__global__ __launch_bounds__(kThreads) void k_ras_update(const int32_t* __restrict__ cover, int ne,
-                                                         const T* __restrict__ Y,
-                                                         T* __restrict__ z) {
-  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (i >= 4 * (int64_t)ne) return;
-  const int64_t e = i >> 2;
-  const int j = int(i & 3);
-  T v = ZERO ? T(0) : z[i];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int c = cover[e * 3 + k];
-    if (c >= 0) v += Y[4 * (int64_t)c + j];
-  }
-  z[i] = v;
 }
 
 // Coefficient of coarse corner A at fine corner a of child ch: the coarse
@@ -864,15 +768,6 @@ hipError_t launch_refine_residual(bool first, const double* L64, const int32_t* 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_refine_update(bool first, int64_t m, const T* zJ, double* z, hipStream_t st) {
-  const int grid = grid_for(m, kThreads, 1 << 30);
-  if (first)
-    k_refine_update<T, true><<<grid, kThreads, 0, st>>>(m, zJ, z);
-  else
-    k_refine_update<T, false><<<grid, kThreads, 0, st>>>(m, zJ, z);
-  return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_lap(bool residual, const T* L, const int32_t* cols, int ne, const T* f, const T* z,
@@ -885,29 +780,7 @@ hipError_t launch_lap(bool residual, const T* L, const int32_t* cols, int ne, co
   return hipGetLastError();
 }
 
-template <>
-hipError_t launch_ras_tiles<float>(const float* F, const int32_t* te, int tiles, const float* r,
-                                   float* Y, hipStream_t st) {
-  k_ras_tiles_f32<<<grid_for(tiles, 4, 1 << 30), kThreads, 0, st>>>(F, te, tiles, r, Y);
-  return hipGetLastError();
-}
-template <>
-hipError_t launch_ras_tiles<double>(const double* F, const int32_t* te, int tiles, const double* r,
-                                    double* Y, hipStream_t st) {
-  k_ras_tiles_f64<<<grid_for(tiles, 4, 1 << 30), kThreads, 0, st>>>(F, te, tiles, r, Y);
-  return hipGetLastError();
-}
 
-template <typename T>
-hipError_t launch_ras_update(bool zero, const int32_t* cover, int ne, const T* Y, T* z,
-                             hipStream_t st) {
-  const int grid = grid_for(4 * (int64_t)ne, kThreads, 1 << 30);
-  if (zero)
-    k_ras_update<T, true><<<grid, kThreads, 0, st>>>(cover, ne, Y, z);
-  else
-    k_ras_update<T, false><<<grid, kThreads, 0, st>>>(cover, ne, Y, z);
-  return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_restrict(int nc, const T* r, T* rc, hipStream_t st) {
@@ -943,10 +816,8 @@ hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st) {
   template hipError_t launch_refine_residual<T>(bool, const double*, const int32_t*, int,      \
                                                 const double*, const double*, T*, double*,     \
                                                 hipStream_t, const Slots&, int);               \
-  template hipError_t launch_refine_update<T>(bool, int64_t, const T*, double*, hipStream_t);  \
   template hipError_t launch_lap<T>(bool, const T*, const int32_t*, int, const T*, const T*, T*, \
                                     hipStream_t);                                              \
-  template hipError_t launch_ras_update<T>(bool, const int32_t*, int, const T*, T*, hipStream_t); \
   template hipError_t launch_restrict<T>(int, const T*, T*, hipStream_t);                      \
   template hipError_t launch_prolong<T>(int, const T*, T*, hipStream_t);                       \
   template hipError_t launch_coarse<T>(const double*, const T*, T*, hipStream_t);              \

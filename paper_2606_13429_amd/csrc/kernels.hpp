@@ -10,9 +10,10 @@
 //   M_1              double  [Ne][16]
 //   L_k              T       [slot][Ne][row=4][4]
 //   cols             int32   [slot][Ne]               -1 = none
-//   RAS factors      T       [tile][j=128][i=128]     F[j][i] = (L_k)_i^{-1}[j][i] d_i
-//   tile squares     int32   [tile][32]
-//   cover            int32   [Ne][3]                  tile * 32 + slot, -1 = none
+//   RAS factors      T       [tile][36 blocks P <= Q][16][16]  packed upper blocks of the
+//                                                     symmetric (L_k)_t^{-1}, row-major
+//   RAS weights      T       [Ne]                     1 / #blocks containing the square
+//   pending slots    int32   [tile][32]               3 e + k for block square e
 //   coarsest inverse double  [1024][1024]
 #pragma once
 #include <hip/hip_runtime.h>
@@ -140,19 +141,11 @@ template <typename T>
 hipError_t launch_refine_residual(bool first, const double* L64, const int32_t* cols, int ne,
                                   const double* s, const double* z, T* fJ, double* part,
                                   hipStream_t st, const Slots& sl = Slots(), int count = 1);
-template <typename T>
-hipError_t launch_refine_update(bool first, int64_t m, const T* zJ, double* z, hipStream_t st);
 
 // multigrid level kernels
 template <typename T>
 hipError_t launch_lap(bool residual, const T* L, const int32_t* cols, int ne, const T* f, const T* z,
                       T* out, hipStream_t st);
-template <typename T>
-hipError_t launch_ras_tiles(const T* F, const int32_t* tile_elems, int tiles, const T* r, T* Y,
-                            hipStream_t st);
-template <typename T>
-hipError_t launch_ras_update(bool zero, const int32_t* cover, int ne, const T* Y, T* z,
-                             hipStream_t st);
 template <typename T>
 hipError_t launch_restrict(int nc, const T* r, T* rc, hipStream_t st);
 template <typename T>

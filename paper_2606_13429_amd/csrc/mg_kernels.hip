@@ -32,9 +32,6 @@ namespace {
 using namespace mg;
 
 constexpr int kThreads = 256;
-#ifndef DCG_SWEEP_CHUNK1
-#define DCG_SWEEP_CHUNK1 8
-#endif
 
 // z of square e after the pending update (and the pending prolongation).
 // Pending tile outputs are stored per square: Ye[e][k][4] holds the output

@@ -31,9 +31,7 @@ struct DeviceLevel {
   double* L64 = nullptr;          // [5][ne][4][4]
   float* L32 = nullptr;
   int tiles = 0;                  // levels >= 2
-  int32_t* tile_elems = nullptr;  // [tiles][32]
   int32_t* tile_ext = nullptr;    // [tiles][52]
-  int32_t* cover = nullptr;       // [ne][3]
   int32_t* tile_dst = nullptr;    // [tiles][32]
   float* F32 = nullptr;           // [tiles][36][16][16] packed symmetric inverses
   double* F64 = nullptr;

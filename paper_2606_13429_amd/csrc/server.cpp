@@ -157,7 +157,7 @@ size_t context_bytes(int n, bool fp32) {
     b += nek * kSlots * (sizeof(int32_t) + 16 * sizeof(double) + (fp32 ? 16 * sizeof(float) : 0));
     if (nk > kCoarsestN) {
       const size_t tiles = nek / 16;
-      b += tiles * (32 + 52 + 32) * sizeof(int32_t) + nek * 3 * sizeof(int32_t);
+      b += tiles * (52 + 32) * sizeof(int32_t);
       b += (tiles * 36 * 256 + nek) * (fp32 ? sizeof(float) : sizeof(double));
     }
   }
