@@ -72,6 +72,28 @@ void upload_blocks_pairs(const std::vector<double>& host, int64_t ne, int rows, 
   }
 }
 
+// The div-div form acts on each row sigma_k = (sigma_k1, sigma_k2) of the
+// stress separately and identically (Section 3.3.2), so every 16 x 16 block of
+// A_div is diag(C, C) in the ordering (sigma_11, sigma_12 | sigma_21, sigma_22)
+// x 4 corners, C 8 x 8.  Returns the C blocks [ne][slot][8][8] after checking
+// that structure exactly.
+std::vector<double> row_blocks(const std::vector<double>& A, int64_t ne) {
+  std::vector<double> C(size_t(ne) * kSlots * 64);
+  for (int64_t b = 0; b < ne * kSlots; ++b) {
+    const double* a = &A[size_t(b) * 256];
+    for (int r = 0; r < 16; ++r)
+      for (int c = 0; c < 16; ++c) {
+        const bool diag = (r < 8) == (c < 8);
+        const double v = a[r * 16 + c];
+        if (!diag ? v != 0.0 : v != a[(r % 8) * 16 + (c % 8)])
+          throw Error(DCG_EDEVICE, "A_div block is not diag(C, C)");
+      }
+    for (int r = 0; r < 8; ++r)
+      for (int c = 0; c < 8; ++c) C[size_t(b) * 64 + r * 8 + c] = a[r * 16 + c];
+  }
+  return C;
+}
+
 void upload_cols(const std::vector<int32_t>& host, int64_t ne, int32_t* dev) {
   std::vector<int32_t> t(size_t(ne) * kSlots);
   for (int64_t e = 0; e < ne; ++e)
@@ -146,11 +168,11 @@ std::shared_ptr<MeshContext> build_context(int device, int n, double penalty) {
   ctx->ne = n * n;
   ctx->penalty = penalty;
   const int64_t ne = ctx->ne;
-  ctx->Adiv = static_cast<double2*>(ctx->alloc(sizeof(double) * ne * kSlots * 256));
+  ctx->Cdiv = static_cast<double2*>(ctx->alloc(sizeof(double) * ne * kSlots * 64));
   ctx->AdivZ = static_cast<double2*>(ctx->alloc(sizeof(double) * ne * kSlots * 64));
   ctx->M1 = static_cast<double*>(ctx->alloc(sizeof(double) * ne * 16));
   ctx->cols = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * ne * kSlots));
-  upload_blocks_pairs(hc.Adiv, ne, 16, 16, ctx->Adiv);
+  upload_blocks_pairs(row_blocks(hc.Adiv, ne), ne, 8, 8, ctx->Cdiv);
   upload_blocks_pairs(hc.AdivZ, ne, 16, 4, ctx->AdivZ);
   DCG_HIP(hipMemcpy(ctx->M1, hc.M1.data(), sizeof(double) * ne * 16, hipMemcpyHostToDevice));
   upload_cols(hc.cols, ne, ctx->cols);

@@ -68,7 +68,7 @@ __device__ inline int slot_id(const Slots& sl) { return sl.list ? sl.list[blockI
 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_astar(
-    const double2* __restrict__ A, const int32_t* __restrict__ cols, const double* __restrict__ M1,
+    const double2* __restrict__ C, const int32_t* __restrict__ cols, const double* __restrict__ M1,
     int ne, const double* __restrict__ x, const double* __restrict__ p_old,
     const double* __restrict__ b, const Scalars* __restrict__ sc, double* __restrict__ p_new,
     double* __restrict__ w, double* __restrict__ s, double* __restrict__ part, Slots sl) {
@@ -110,11 +110,13 @@ __global__ __launch_bounds__(kThreads) void k_astar(
           u[2 * kc] = v.x;
           u[2 * kc + 1] = v.y;
         }
-        const double2* Ab = A + ((int64_t)slot * 8 * ne + e) * 16 + r;
+        // row r of diag(C, C): row r % 8 of C on the 8 values of stress row r / 8
+        const double2* Cb = C + ((int64_t)slot * 4 * ne + e) * 8 + (r & 7);
+        const int o = (r >> 3) * 8;
 #pragma unroll
-        for (int kc = 0; kc < 8; ++kc) {
-          const double2 a = Ab[(int64_t)kc * ne * 16];
-          acc += a.x * u[2 * kc] + a.y * u[2 * kc + 1];
+        for (int kc = 0; kc < 4; ++kc) {
+          const double2 a = Cb[(int64_t)kc * ne * 8];
+          acc += a.x * u[o + 2 * kc] + a.y * u[o + 2 * kc + 1];
         }
         if (slot == 0) {
 #pragma unroll
@@ -629,26 +631,26 @@ __global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const T* __restric
 }  // namespace
 
 // ============================================================ launchers
-hipError_t launch_astar(int mode, const double2* A, const int32_t* cols, const double* M1, int ne,
+hipError_t launch_astar(int mode, const double2* C, const int32_t* cols, const double* M1, int ne,
                         const double* x, const double* p_old, const double* b, const Scalars* sc,
                         double* p_new, double* w, double* s, double* part, hipStream_t st,
                         const Slots& sl, int count) {
   const dim3 grid(grid_for(ne, 16, kPartStride), count);
   switch (mode) {
     case kAstarPlain:
-      k_astar<kAstarPlain><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
+      k_astar<kAstarPlain><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
                                                       part, sl);
       break;
     case kAstarDir:
-      k_astar<kAstarDir><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
+      k_astar<kAstarDir><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
                                                     part, sl);
       break;
     case kAstarFirst:
-      k_astar<kAstarFirst><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
+      k_astar<kAstarFirst><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
                                                       part, sl);
       break;
     case kAstarResidual:
-      k_astar<kAstarResidual><<<grid, kThreads, 0, st>>>(A, cols, M1, ne, x, p_old, b, sc, p_new, w,
+      k_astar<kAstarResidual><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w,
                                                          s, part, sl);
       break;
     default:

@@ -5,7 +5,8 @@
 // a product can exceed 2^31):
 //   tensor vectors   [16 e + 4 c + j]                 (FP64)
 //   scalar vectors   [4 e + j]                        (FP64 or level real T)
-//   A_div            double2 [slot][kc=8][Ne][row=16]  row r, columns 2kc, 2kc+1
+//   A_div = diag(C, C) per block (one C for each stress row), stored as
+//   C                double2 [slot][kc=4][Ne][row=8]   row r, columns 2kc, 2kc+1
 //   A_div Z          double2 [slot][kc=2][Ne][row=16]
 //   M_1              double  [Ne][16]
 //   L_k              T       [slot][Ne][row=4][4]
@@ -84,7 +85,7 @@ enum AstarMode : int {
 int astar_blocks(int ne);     // launch_astar and launch_deflate
 int refine_blocks(int ne);    // launch_refine_residual
 
-hipError_t launch_astar(int mode, const double2* A, const int32_t* cols, const double* M1, int ne,
+hipError_t launch_astar(int mode, const double2* C, const int32_t* cols, const double* M1, int ne,
                         const double* x, const double* p_old, const double* b, const Scalars* sc,
                         double* p_new, double* w, double* s, double* part, hipStream_t st,
                         const Slots& sl = Slots(), int count = 1);

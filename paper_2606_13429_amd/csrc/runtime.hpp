@@ -45,7 +45,7 @@ struct MeshContext {
   int device = 0;
   int n = 0, J = 0, ne = 0;
   double penalty = 10.0;
-  double2* Adiv = nullptr;        // [5][8][ne][16]
+  double2* Cdiv = nullptr;        // [5][4][ne][8]: A_div = diag(C, C) per block
   double2* AdivZ = nullptr;       // [5][2][ne][16]
   double* M1 = nullptr;           // [ne][16]
   int32_t* cols = nullptr;        // [5][ne]

@@ -150,7 +150,7 @@ size_t workspace_bytes(int n, bool fp32) {
 // Bytes of a mesh context (the allocations of the context upload).
 size_t context_bytes(int n, bool fp32) {
   const size_t ne = size_t(n) * n;
-  size_t b = ne * kSlots * (256 + 64) * sizeof(double) + ne * 16 * sizeof(double) +
+  size_t b = ne * kSlots * (64 + 64) * sizeof(double) + ne * 16 * sizeof(double) +
              ne * kSlots * sizeof(int32_t);
   for (int nk = n; nk >= kCoarsestN; nk /= 2) {
     const size_t nek = size_t(nk) * nk;
@@ -445,7 +445,7 @@ void Server::Impl::enqueue_step(Group& g) {
   if (cnt(kLPostEpi)) {
     const int c = cnt(kLPostEpi);
     DCG_HIP(launch_reconstruct(ne, g.xh, g.zref, g.zb, g.ws.sc, g.q, st, sl(kLPostEpi), c));
-    DCG_HIP(launch_astar(kAstarResidual, m.Adiv, m.cols, m.M1, ne, g.q, nullptr, g.b, g.ws.sc,
+    DCG_HIP(launch_astar(kAstarResidual, m.Cdiv, m.cols, m.M1, ne, g.q, nullptr, g.b, g.ws.sc,
                          nullptr, g.w, nullptr, g.ws.part, st, sl(kLPostEpi), c));
     DCG_HIP(launch_reduce(g.ws.part, nbA, kRedRes, g.ws.sc, st, sl(kLPostEpi), c));
     for (int k = 0; k < c; ++k) {
@@ -457,16 +457,16 @@ void Server::Impl::enqueue_step(Group& g) {
   // the next inner right-hand side s = Z^T (...)
   if (cnt(kLZt)) DCG_HIP(launch_zt(ne, g.b, g.s, st, sl(kLZt), cnt(kLZt)));
   if (cnt(kLAstarFirst))
-    DCG_HIP(launch_astar(kAstarFirst, m.Adiv, m.cols, m.M1, ne, g.r, g.p[0], nullptr, g.ws.sc,
+    DCG_HIP(launch_astar(kAstarFirst, m.Cdiv, m.cols, m.M1, ne, g.r, g.p[0], nullptr, g.ws.sc,
                          g.p[1], g.w, g.s, nullptr, st, sl(kLAstarFirst), cnt(kLAstarFirst)));
   for (int pi = 0; pi < 2; ++pi) {
     const int list = pi ? kLAstarDir1 : kLAstarDir0;
     if (!cnt(list)) continue;
-    DCG_HIP(launch_astar(kAstarDir, m.Adiv, m.cols, m.M1, ne, g.r, g.p[pi], nullptr, g.ws.sc,
+    DCG_HIP(launch_astar(kAstarDir, m.Cdiv, m.cols, m.M1, ne, g.r, g.p[pi], nullptr, g.ws.sc,
                          g.p[1 - pi], g.w, g.s, nullptr, st, sl(list), cnt(list)));
   }
   if (cnt(kLAstarPlain))
-    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, g.xh, nullptr, nullptr, g.ws.sc,
+    DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, g.xh, nullptr, nullptr, g.ws.sc,
                          nullptr, g.w, g.s, nullptr, st, sl(kLAstarPlain), cnt(kLAstarPlain)));
 
   // inner Multigrid iteration: starts, one batched W-cycle, refinement

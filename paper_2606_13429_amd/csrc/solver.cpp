@@ -313,7 +313,7 @@ dcg_status outer_fcg(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_t
     DCG_HIP(launch_fcg_direction(N, ws.r, fs.dptr, first, mi, R, fs.coef, fs.d[slot], ws.part,
                                  &nbd, st));
     DCG_HIP(launch_reduce(ws.part, nbd, kRedDr, ws.sc, st));
-    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, fs.d[slot], nullptr, nullptr,
+    DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, fs.d[slot], nullptr, nullptr,
                          ws.sc, nullptr, ws.w, ws.s, nullptr, st));
     const int c = inner(h, ws.s, ws.zref, tol_outer(rho), st);
     cycles_total += c;
@@ -372,7 +372,7 @@ dcg_status outer_gmres(dcg_ctx* h, double lim, double& rho, int& it, int& cycles
     }
     const int j = it;
     // q = M_D v_j
-    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, fs.d[j], nullptr, nullptr, ws.sc,
+    DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, fs.d[j], nullptr, nullptr, ws.sc,
                          nullptr, ws.w, ws.s, nullptr, st));
     const int c = inner(h, ws.s, ws.zref, tol_outer(rnorm * rnorm), st);
     cycles_total += c;
@@ -483,7 +483,7 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
     // x_hat_0 = x_0, r_0 = f_D - M_D x_0 with M_D x_0 = A* x_0 - A* Z y_0,
     // y_0 = E^{-1} Z^T A* x_0 (Algorithm 1 applied to the deflated system)
     DCG_HIP(launch_copy<double>(N, x, ws.xh, stream));
-    DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
+    DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
                          ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
     cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
     ++inner_solves;
@@ -517,7 +517,7 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
         break;
       }
       // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
-      DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Adiv, m.cols, m.M1, ne,
+      DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Cdiv, m.cols, m.M1, ne,
                            ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
                            stream));
       pidx = 1 - pidx;
@@ -549,12 +549,12 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
   stats.rel_res_recurrence = std::sqrt(std::max(rho, 0.0) / b2);
 
   // epilogue: x = (x_hat - pi(A* x_hat)) + pi(b)  (eq. (x_defl))
-  DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
+  DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
                        ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
   cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
   ++inner_solves;
   DCG_HIP(launch_reconstruct(ne, ws.xh, ws.zt, ws.zb, ws.sc, x, stream));
-  DCG_HIP(launch_astar(kAstarResidual, m.Adiv, m.cols, m.M1, ne, x, nullptr, b, ws.sc,
+  DCG_HIP(launch_astar(kAstarResidual, m.Cdiv, m.cols, m.M1, ne, x, nullptr, b, ws.sc,
                        nullptr, ws.w, nullptr, ws.part, stream));
   DCG_HIP(launch_reduce(ws.part, nbA, kRedRes, ws.sc, stream));
   read_scalars(h, stream);
@@ -684,7 +684,7 @@ dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* i
   if (op == DCG_OP_ASTAR || op == DCG_OP_DEFLATED) set_params(h, st);
   switch (op) {
     case DCG_OP_ASTAR:
-      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, x, nullptr,
+      DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, x, nullptr,
                            nullptr, h->ws.sc, nullptr, y, nullptr, nullptr, st));
       break;
     case DCG_OP_ZT:
@@ -702,7 +702,7 @@ dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* i
       break;
     }
     case DCG_OP_DEFLATED: {
-      DCG_HIP(launch_astar(kAstarPlain, m.Adiv, m.cols, m.M1, ne, x, nullptr,
+      DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, x, nullptr,
                            nullptr, h->ws.sc, nullptr, h->ws.w, h->ws.s, nullptr, st));
       inner(h, h->ws.s, h->ws.zref, h->opt.c_F * kApplyTol, st);
       DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, h->ws.zref, h->ws.w, x, y, nullptr,

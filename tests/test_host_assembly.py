@@ -108,3 +108,22 @@ def test_invalid_mesh_rejected():
             lib.dcg_host_assemble(_mesh(bad), 0)
         assert ei.value.status == lib.DCG_EINVAL
     assert [lib.dcg_num_levels(n) for n in (16, 32, 512, 1024, 12)] == [1, 2, 6, 7, -1]
+
+
+def test_divdiv_blocks_act_on_each_stress_row_alike():
+    # the div-div form couples sigma_k1 with sigma_k2 of the same row k only,
+    # with the same matrix for k = 1, 2 (Section 3.3.2): every 16 x 16 block is
+    # diag(C, C); the device stores C alone and A_div Z follows from its
+    # sigma_11 / sigma_22 columns
+    lib = pytest.importorskip("paper_2606_13429_amd._binding")
+    mesh, _ = lib.dcg_defaults()
+    mesh.n = 16
+    A, _ = lib.dcg_host_assemble(mesh, 0)
+    A = A.reshape(-1, 5, 16, 16)
+    assert not A[:, :, :8, 8:].any() and not A[:, :, 8:, :8].any()
+    assert np.array_equal(A[:, :, :8, :8], A[:, :, 8:, 8:])
+    AZ, _ = lib.dcg_host_assemble(mesh, 1)
+    AZ = AZ.reshape(-1, 5, 16, 4)
+    C = A[:, :, :8, :8]
+    assert np.allclose(AZ[:, :, :8], C[..., :4] / np.sqrt(2), atol=1e-15, rtol=0)
+    assert np.allclose(AZ[:, :, 8:], C[..., 4:] / np.sqrt(2), atol=1e-15, rtol=0)
