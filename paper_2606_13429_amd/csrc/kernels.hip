@@ -91,50 +91,58 @@ __global__ __launch_bounds__(kThreads) void k_astar(
     const int e = (g << 4) + (threadIdx.x >> 4);
     const bool valid = e < ne;
     double acc = 0.0, wv = 0.0;
-    double self[16];
+    // Lane r of a square loads value r of each vector it needs; the 16 lanes of
+    // the square exchange values by shuffles (the neighbour of a slot is the
+    // same for all 16, so the branches and shuffles are uniform within the
+    // group).  u0 = the direction at the own square.
+    double u0 = 0.0;
     if (valid) {
+      u0 = x[16 * (int64_t)e + r];
+      if (MODE == kAstarDir) u0 += beta * p_old[16 * (int64_t)e + r];
+    }
+    // A_div part, row r of diag(C, C): row r % 8 of C applied to the 8 values
+    // of stress row r / 8 of each neighbour
+    const int o = (r >> 3) * 8;
 #pragma unroll
-      for (int slot = 0; slot < 5; ++slot) {
-        const int c = cols[slot * ne + e];
-        if (c < 0) continue;
-        double u[16];
-        const double2* xs = reinterpret_cast<const double2*>(x + 16 * (int64_t)c);
+    for (int slot = 0; slot < 5; ++slot) {
+      const int c = valid ? cols[slot * ne + e] : -1;
+      double ur = u0;
+      if (slot != 0 && c >= 0) {
+        ur = x[16 * (int64_t)c + r];
+        if (MODE == kAstarDir) ur += beta * p_old[16 * (int64_t)c + r];
+      }
+      double u[8];
 #pragma unroll
-        for (int kc = 0; kc < 8; ++kc) {
-          double2 v = xs[kc];
-          if (MODE == kAstarDir) {
-            const double2 po = reinterpret_cast<const double2*>(p_old + 16 * (int64_t)c)[kc];
-            v.x = v.x + beta * po.x;
-            v.y = v.y + beta * po.y;
-          }
-          u[2 * kc] = v.x;
-          u[2 * kc + 1] = v.y;
-        }
-        // row r of diag(C, C): row r % 8 of C on the 8 values of stress row r / 8
+      for (int m = 0; m < 8; ++m) u[m] = __shfl(ur, o + m, 16);
+      if (c >= 0) {
         const double2* Cb = C + ((int64_t)slot * 4 * ne + e) * 8 + (r & 7);
-        const int o = (r >> 3) * 8;
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) {
           const double2 a = Cb[(int64_t)kc * ne * 8];
-          acc += a.x * u[o + 2 * kc] + a.y * u[o + 2 * kc + 1];
-        }
-        if (slot == 0) {
-#pragma unroll
-          for (int k = 0; k < 16; ++k) self[k] = u[k];
+          acc += a.x * u[2 * kc] + a.y * u[2 * kc + 1];
         }
       }
-      const int cc = r >> 2, j = r & 3;
-      double m[4];
-      ld4(M1 + 16 * (int64_t)e + 4 * j, m);
+    }
+    // mass part (1/nu)(C_dev (x) M_1) u of the own square: row (cc, j) needs
+    // the corners of sigma_11 and sigma_22 (cc = 0, 3) or of sigma_cc (cc = 1, 2)
+    const int cc = r >> 2, j = r & 3;
+    double s11[4], s22[4], sc4[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      s11[m] = __shfl(u0, m, 16);
+      s22[m] = __shfl(u0, 12 + m, 16);
+      sc4[m] = __shfl(u0, 4 * cc + m, 16);
+    }
+    if (valid) {
+      double m1[4];
+      ld4(M1 + 16 * (int64_t)e + 4 * j, m1);
       double mu;
       if (cc == 0 || cc == 3) {
-        const double d0 = self[0] - self[12], d1 = self[1] - self[13];
-        const double d2 = self[2] - self[14], d3 = self[3] - self[15];
-        mu = 0.5 * (m[0] * d0 + m[1] * d1 + m[2] * d2 + m[3] * d3);
+        mu = 0.5 * (m1[0] * (s11[0] - s22[0]) + m1[1] * (s11[1] - s22[1]) +
+                    m1[2] * (s11[2] - s22[2]) + m1[3] * (s11[3] - s22[3]));
         if (cc == 3) mu = -mu;
       } else {
-        const int o = 4 * cc;
-        mu = m[0] * self[o] + m[1] * self[o + 1] + m[2] * self[o + 2] + m[3] * self[o + 3];
+        mu = m1[0] * sc4[0] + m1[1] * sc4[1] + m1[2] * sc4[2] + m1[3] * sc4[3];
       }
       wv = inv_nu * mu + dt * acc;
       if (MODE == kAstarResidual) {
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_astar(
         dot += wv * wv;
       }
       if (w) w[16 * (int64_t)e + r] = wv;
-      if (MODE == kAstarDir || MODE == kAstarFirst) p_new[16 * (int64_t)e + r] = self[r];
+      if (MODE == kAstarDir || MODE == kAstarFirst) p_new[16 * (int64_t)e + r] = u0;
     }
     // s = Z^T w: lanes r = j and r = 12 + j of the same square
     const double w22 = __shfl_down(wv, 12, 16);
