@@ -175,6 +175,9 @@ def serving(args):
             if status == lib.DCG_PENDING:
                 continue
             k = pending.pop(tk)
+            if status < 0:
+                log("request %d (n=%d dt=%.3g) failed: status %d, %s"
+                    % (k, trace[k]["n"], trace[k]["dt"], status, lib.dcg_last_error()))
             done[k] = dict(n=trace[k]["n"], dt=trace[k]["dt"], status=status,
                            outer=st.outer_iters, wcycles=st.total_wcycles,
                            latency=time.perf_counter() - t_start - trace[k]["t_arrival"],
@@ -223,6 +226,7 @@ def serving(args):
         "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
         "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
         "makespan_s": round(makespan, 2), "not_converged": len(capped), "failed": len(failed),
+        "failures": [{"n": d["n"], "dt": d["dt"], "status": d["status"]} for d in failed],
         "batch_occupancy": round(slot_steps / max(steps, 1), 2), "server_steps": steps,
         "per_n": per_n, "alone_vs_mix_bitwise": alone_ok,
     }
