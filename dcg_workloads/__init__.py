@@ -19,11 +19,19 @@ SWEEP = dict(n=128, dts=(1e-1, 1e-2, 1e-3, 1e-4, 1e-5), tol=1e-8)
 HEADLINE = dict(n=512, dt=1e-4, tol=1e-8)                    # FP64 vs mixed form
 SERVING = dict(count=256, rate=50.0, sizes=(32, 64, 128, 256), dt_range=(-6.0, -1.0), tol=1e-8)
 TIMESTEP = dict(n=1024, dt=1e-5, steps=100, modes=8, seed=0)
+# three-dimensional solver: n^3 cubes, penalty and mu of the 3D test of the paper
+THREE_D = dict(n=32, dt=1e-3, tol=1e-8, penalty=40.0, nu=0.5)
 
 
 def rhs(n, seed):
     """b ~ N(0, 1), length 16 n^2, element-major."""
     return np.random.default_rng(seed).standard_normal(16 * n * n)
+
+
+def rhs3d(n, seed):
+    """b ~ N(0, 1), length 72 n^3, in the 3D element-major layout
+    idx = 72 e + 8 c + a."""
+    return np.random.default_rng(seed).standard_normal(72 * n ** 3)
 
 
 def serving_trace(seed=0, count=256, rate=50.0, sizes=(32, 64, 128, 256),

@@ -289,6 +289,75 @@ const char* dcg_last_error(dcg_handle h);
  * reference; call after destroying them to return the memory. */
 void dcg_clear_cache(void);
 
+/* ---------------------------------------------------------------------------
+ * Three-dimensional solver: the d = 3 block structure of Section 3.1.
+ *
+ * Unknowns: the nine components sigma_ki (Section 3.1, d = 3), discontinuous
+ * Q1 on the grid of n x n x n cubes of the unit cube; M = mu^{-1} C_9 (x) M_1
+ * with the printed 9 x 9 coefficient matrix, A = blockdiag(C_3, C_3, C_3),
+ * C_3 = [B_ij] from the SIPG forms a^h_ij, i, j in {1, 2, 3}
+ * (Section 3.3.2), penalty gamma = penalty * n, SIPG face terms on interior
+ * faces and on the outflow face {x = 1} (where the 3D test of Section 4.2
+ * imposes sigma n = 0).  Deflation basis Z = V of eq. (Vmatrix) for d = 3,
+ * so Z^T A* Z = (dt/3)(B_11 + B_22 + B_33) (Corollary 1).
+ *
+ * Solve: Algorithm 2 with the CG outer iteration; the inner system is solved
+ * by block-Jacobi preconditioned CG to the relative residual c_F * tol
+ * (eq. (fixed_tol)), at most max_inner steps per inner solve.  Everything runs
+ * in FP64 on the device; dcg_stats.total_wcycles counts inner CG steps.
+ *
+ * Layout (device pointers, FP64): tensor vectors 72 n^3 values, element-major,
+ * idx = 72 e + 8 c + a with e = (ez n + ey) n + ex, c = 3 k + i for
+ * sigma_{k+1,i+1}, a = ix + 2 iy + 4 iz the corner (ex + ix, ey + iy, ez + iz)/n;
+ * scalar (inner) vectors 8 n^3 values, idx = 8 e + a.  All work is enqueued
+ * on the legacy default stream and the calls return after it has finished.
+ * The caller owns the vectors, the handle owns its operators (about
+ * 33 KB per element) and workspaces.  Errors as above; dcg3d_last_error. */
+#define DCG3D_MAX_N 64
+#define DCG3D_DEFAULT_MAX_INNER 20000
+
+typedef struct dcg3d_ctx* dcg3d_handle;
+
+typedef enum {
+  DCG3D_OP_ASTAR = 0,     /* out = A* in            (tensor -> tensor), eq. (pb_study)        */
+  DCG3D_OP_ZT = 1,        /* out = Z^T in           (tensor -> scalar), eq. (Vmatrix)         */
+  DCG3D_OP_Z = 2,         /* out = Z in             (scalar -> tensor)                        */
+  DCG3D_OP_DEFLATED = 3,  /* out = M_D in = A*(in - Z E^{-1} Z^T A* in), inner to tol, Alg. 2 */
+  DCG3D_OP_REDUCED = 4,   /* out = E in, E = Z^T A* Z (scalar), Corollary 1                   */
+  DCG3D_OP_INNER = 5,     /* out = E^{-1} in by the inner solver to relative residual tol     */
+  DCG3D_OP_ADIVZ = 6      /* out = A_div Z in       (scalar -> tensor), Corollary 1 (proof)   */
+} dcg3d_op;
+
+/* Assembles the operators on the host and uploads them (2 <= n <= 64,
+ * penalty > 0, dt > 0, nu = mu > 0).  opt may be NULL (defaults of
+ * dcg_defaults with prec = DCG_FP64 and max_inner = DCG3D_DEFAULT_MAX_INNER);
+ * the 3D solver takes prec = DCG_FP64, outer = DCG_OUTER_CG, c_A = 0 and
+ * x0_given = 0 and rejects other values with DCG_EINVAL. */
+dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, const dcg_options* opt,
+                       dcg3d_handle* out);
+/* Solves A* x = b to ||r|| <= tol ||b|| (the recurrence residual of the
+ * deflated system, Section 4.1); st (may be NULL) receives the counts and the
+ * true residual of the reconstructed x. */
+dcg_status dcg3d_solve(dcg3d_handle h, const double* b, double* x, double tol, dcg_stats* st);
+/* One operator of the path (tol is used by DCG3D_OP_DEFLATED and
+ * DCG3D_OP_INNER only). */
+dcg_status dcg3d_apply(dcg3d_handle h, dcg3d_op op, const double* in, double* out, double tol);
+dcg_status dcg3d_destroy(dcg3d_handle h);
+const char* dcg3d_last_error(dcg3d_handle h);
+
+/* Host only (no device call, 2 <= n <= 16): copies the blocks the 3D path
+ * assembles into the HOST buffer out, for checks of the assembly without a
+ * GPU.  which = 0: the blocks C_3 of A_div, [7][n^3][24][24] (face slot 0 the
+ * element, 1 / 2 its -x / +x neighbour, 3 / 4 -y / +y, 5 / 6 -z / +z), entry
+ * (row 8 j + a, column 8 i + b) = a^h_ij(phi_b on the neighbour, phi_a on the
+ * element) at index (slot n^3 + e) 576 + (8 i + b) 24 + 8 j + a, zero where the
+ * neighbour does not exist; 1: B_11 + B_22 + B_33 in the same slots,
+ * [7][n^3][8][8], entry (a, b) at (slot n^3 + e) 64 + 8 b + a; 2: the inverses
+ * of the diagonal blocks of (dt/3)(B_11 + B_22 + B_33), [n^3][8][8], entry
+ * (a, b) at 64 e + 8 b + a; 3: the element mass matrix of M_1, [8][8]. */
+#define DCG3D_MAX_HOST_BLOCKS_N 16
+dcg_status dcg3d_host_blocks(int32_t n, double penalty, double dt, int32_t which, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,9 @@ DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_OUTER_FCG, DCG_OUTER_GMRES = 0, 1, 2, 3
  DCG_OP_RAS, DCG_OP_RESTRICT, DCG_OP_PROLONG, DCG_OP_COARSE, DCG_OP_WCYCLE, DCG_OP_RAS_BATCH,
  DCG_OP_WCYCLE_BATCH) = range(14)
 BATCH = 16   # vectors of the _BATCH operators and requests per serving batch
+(DCG3D_OP_ASTAR, DCG3D_OP_ZT, DCG3D_OP_Z, DCG3D_OP_DEFLATED, DCG3D_OP_REDUCED, DCG3D_OP_INNER,
+ DCG3D_OP_ADIVZ) = range(7)
+DCG3D_MAX_N, DCG3D_DEFAULT_MAX_INNER, DCG3D_MAX_HOST_BLOCKS_N = 64, 20000, 16
 
 
 class dcg_mesh(ctypes.Structure):
@@ -79,6 +82,14 @@ _SIGS = {
     "dcg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "dcg_last_error": (ctypes.c_char_p, [_h]),
     "dcg_clear_cache": (None, []),
+    "dcg3d_setup": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   _P(dcg_options), _P(_h)]),
+    "dcg3d_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.c_double, _P(dcg_stats)]),
+    "dcg3d_apply": (ctypes.c_int, [_h, ctypes.c_int, _vp, _vp, ctypes.c_double]),
+    "dcg3d_destroy": (ctypes.c_int, [_h]),
+    "dcg3d_last_error": (ctypes.c_char_p, [_h]),
+    "dcg3d_host_blocks": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                         _P(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -260,3 +271,62 @@ def dcg_clear_cache():
 def _f64():
     import torch
     return torch.float64
+
+
+# ------------------------------------------------------------------ 3D solver
+def _check3(status, handle=None):
+    if status < 0:
+        msg = _lib.dcg3d_last_error(handle)
+        raise DCGError(status, msg.decode() if msg else "")
+    return status
+
+
+def _sync_torch_stream():
+    # the 3D entry points run on the legacy default stream: order them after
+    # work torch queued on another current stream
+    import torch
+    cs = torch.cuda.current_stream()
+    if cs.cuda_stream != 0:
+        cs.synchronize()
+
+
+def dcg3d_setup(n, penalty, dt, nu=1.0, opt=None):
+    h = _h()
+    _check3(_lib.dcg3d_setup(n, penalty, dt, nu, ctypes.byref(opt) if opt is not None else None,
+                             ctypes.byref(h)))
+    return h
+
+
+def dcg3d_solve(handle, b, x, tol):
+    """Returns (status, dcg_stats); raises DCGError on negative status."""
+    st = dcg_stats()
+    _sync_torch_stream()
+    status = _lib.dcg3d_solve(handle, _ptr(b, _f64(), None, "b"), _ptr(x, _f64(), None, "x"), tol,
+                              ctypes.byref(st))
+    _check3(status, handle)
+    return status, st
+
+
+def dcg3d_apply(handle, op, inp, out, tol=0.0):
+    _sync_torch_stream()
+    return _check3(_lib.dcg3d_apply(handle, op, _ptr(inp, _f64(), None, "in"), _ptr(out, _f64(), None, "out"),
+                                    tol), handle)
+
+
+def dcg3d_destroy(handle):
+    return _lib.dcg3d_destroy(handle)
+
+
+def dcg3d_last_error(handle=None):
+    msg = _lib.dcg3d_last_error(handle)
+    return msg.decode() if msg else ""
+
+
+def dcg3d_host_blocks(n, penalty, dt, which):
+    """Host copy of the assembled 3D blocks (no device call): a flat float64 array."""
+    import numpy as np
+    ne = n ** 3
+    size = {0: 7 * ne * 576, 1: 7 * ne * 64, 2: ne * 64, 3: 64}[which]
+    out = np.empty(size, dtype=np.float64)
+    _check3(_lib.dcg3d_host_blocks(n, penalty, dt, which, out.ctypes.data_as(_P(ctypes.c_double))))
+    return out

@@ -1,0 +1,540 @@
+// Three-dimensional deflated CG on the device (the d = 3 case of Section 3.1):
+// host assembly of the DG-Q1 element blocks, the resident device context, the
+// outer iteration of Algorithm 2 and the extern "C" entry points dcg3d_*.
+//
+// Discretisation: the unit cube in n^3 cubes of side h = 1/n, discontinuous
+// Q1 per stress component, 2x2x2 Gauss in elements and 2x2 Gauss on faces,
+// penalty gamma = penalty / h, SIPG face terms (Section 3.3.2, the component
+// reading of jumps and averages) on interior faces and on the outflow face
+// {x = 1}, where the three-dimensional test of Section 4.2 imposes sigma n = 0.
+//
+// Solve: deflated CG with V of eq. (Vmatrix) for d = 3 (called Z), whose
+// inner system Z^T A* Z = (dt/3)(B_11 + B_22 + B_33) (Corollary 1) is solved
+// by block-Jacobi preconditioned CG to the relative tolerance c_F * tol
+// (eq. (fixed_tol)); every vector operation runs in the kernels of dcg3d_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dcg.h"
+#include "dcg3d.hpp"
+
+namespace {
+
+using dcg3::kDof;
+using dcg3::kNb;
+using dcg3::kSlots;
+
+struct Err3 : std::runtime_error {
+  dcg_status status;
+  Err3(dcg_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+void hipck(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  (void)hipGetLastError();
+  throw Err3(e == hipErrorOutOfMemory ? DCG_ENOMEM : DCG_EDEVICE,
+             std::string(what) + ": " + hipGetErrorString(e));
+}
+#define H3(expr) hipck((expr), #expr)
+
+thread_local std::string g_last_error3;
+
+// ---------------------------------------------------------------------------
+// element and face blocks of the uniform hexahedral grid
+// ---------------------------------------------------------------------------
+struct CubeForms {
+  double mass[kNb][kNb];
+  double vol[3][3][kNb][kNb];                 // [i][j][test a][trial b]
+  double face[3][2][2][3][3][kNb][kNb];       // [axis][test side][trial side][i][j][a][b]
+  double out[3][3][kNb][kNb];                 // the x = 1 face of Gamma_out, one side
+};
+
+double bval(int i, double t) { return i ? t : 1.0 - t; }
+double bder(int i) { return i ? 1.0 : -1.0; }
+
+// Values and physical gradients of the 8 trilinear corner functions.
+void basis(const double p[3], double h, double v[kNb], double g[kNb][3]) {
+  for (int j = 0; j < kNb; ++j) {
+    const int c[3] = {j & 1, (j >> 1) & 1, j >> 2};
+    const double b0 = bval(c[0], p[0]), b1 = bval(c[1], p[1]), b2 = bval(c[2], p[2]);
+    v[j] = b0 * b1 * b2;
+    g[j][0] = bder(c[0]) * b1 * b2 / h;
+    g[j][1] = b0 * bder(c[1]) * b2 / h;
+    g[j][2] = b0 * b1 * bder(c[2]) / h;
+  }
+}
+
+void build_forms(int n, double penalty, CubeForms& F) {
+  std::memset(&F, 0, sizeof(F));
+  const double h = 1.0 / n, gamma = penalty / h;
+  const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  // volume: 2x2x2 Gauss, weight h^3 / 8 per point
+  for (int qz = 0; qz < 2; ++qz)
+    for (int qy = 0; qy < 2; ++qy)
+      for (int qx = 0; qx < 2; ++qx) {
+        const double p[3] = {gp[qx], gp[qy], gp[qz]};
+        double v[kNb], g[kNb][3];
+        basis(p, h, v, g);
+        const double w = h * h * h / 8.0;
+        for (int a = 0; a < kNb; ++a)
+          for (int b = 0; b < kNb; ++b) {
+            F.mass[a][b] += w * v[a] * v[b];
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j) F.vol[i][j][a][b] += w * g[b][i] * g[a][j];
+          }
+      }
+  // faces: 2x2 Gauss, weight h^2 / 4 per point.  Side 0 is the element below
+  // the face (its x_axis = 1 side, normal +e_axis), side 1 the element above
+  // (x_axis = 0, normal -e_axis).  For test side t and trial side s:
+  //   -{d_i sigma}[[tau]]_j - {d_j tau}[[sigma]]_i + gamma [[sigma]]_i [[tau]]_j
+  for (int axis = 0; axis < 3; ++axis) {
+    const int o0 = (axis + 1) % 3, o1 = (axis + 2) % 3;
+    for (int q0 = 0; q0 < 2; ++q0)
+      for (int q1 = 0; q1 < 2; ++q1) {
+        double v[2][kNb], g[2][kNb][3], nrm[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        for (int side = 0; side < 2; ++side) {
+          double p[3];
+          p[axis] = side == 0 ? 1.0 : 0.0;
+          p[o0] = gp[q0];
+          p[o1] = gp[q1];
+          basis(p, h, v[side], g[side]);
+          nrm[side][axis] = side == 0 ? 1.0 : -1.0;
+        }
+        const double w = h * h / 4.0;
+        for (int t = 0; t < 2; ++t)
+          for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j)
+                for (int a = 0; a < kNb; ++a)
+                  for (int b = 0; b < kNb; ++b)
+                    F.face[axis][t][s][i][j][a][b] +=
+                        w * (-0.5 * v[t][a] * nrm[t][j] * g[s][b][i] -
+                             0.5 * g[t][a][j] * v[s][b] * nrm[s][i] +
+                             gamma * v[t][a] * nrm[t][j] * v[s][b] * nrm[s][i]);
+        if (axis == 0) {   // the outflow face x = 1: single trace, outward +e_x
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              for (int a = 0; a < kNb; ++a)
+                for (int b = 0; b < kNb; ++b)
+                  F.out[i][j][a][b] +=
+                      w * (-v[0][a] * nrm[0][j] * g[0][b][i] - g[0][a][j] * v[0][b] * nrm[0][i] +
+                           gamma * v[0][a] * nrm[0][j] * v[0][b] * nrm[0][i]);
+        }
+      }
+  }
+}
+
+// Inverse of an SPD 8 x 8 matrix by Gauss-Jordan elimination with partial
+// pivoting; throws if it is singular.
+void invert8(const double A[kNb][kNb], double X[kNb][kNb]) {
+  double M[kNb][2 * kNb];
+  for (int i = 0; i < kNb; ++i)
+    for (int j = 0; j < kNb; ++j) {
+      M[i][j] = A[i][j];
+      M[i][kNb + j] = i == j ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < kNb; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < kNb; ++i)
+      if (std::fabs(M[i][c]) > std::fabs(M[piv][c])) piv = i;
+    if (!(std::fabs(M[piv][c]) > 0.0)) throw Err3(DCG_EINVAL, "singular diagonal block");
+    if (piv != c)
+      for (int j = 0; j < 2 * kNb; ++j) std::swap(M[c][j], M[piv][j]);
+    const double d = M[c][c];
+    for (int j = 0; j < 2 * kNb; ++j) M[c][j] /= d;
+    for (int i = 0; i < kNb; ++i) {
+      if (i == c) continue;
+      const double f = M[i][c];
+      for (int j = 0; j < 2 * kNb; ++j) M[i][j] -= f * M[c][j];
+    }
+  }
+  for (int i = 0; i < kNb; ++i)
+    for (int j = 0; j < kNb; ++j) X[i][j] = M[i][kNb + j];
+}
+
+// Host assembly of every block the device path uses (layouts in dcg3d.hpp).
+void assemble3d(int n, double penalty, double dt, std::vector<double>& cd, std::vector<double>& ld,
+                std::vector<double>& dinv, std::vector<double>& me) {
+  const int64_t ne = (int64_t)n * n * n;
+  auto forms = std::make_unique<CubeForms>();   // 60 KB: keep it off the stack
+  CubeForms& F = *forms;
+  build_forms(n, penalty, F);
+  cd.assign((size_t)kSlots * ne * 576, 0.0);
+  ld.assign((size_t)kSlots * ne * 64, 0.0);
+  dinv.assign((size_t)ne * 64, 0.0);
+  me.assign(64, 0.0);
+  for (int a = 0; a < kNb; ++a)
+    for (int b = 0; b < kNb; ++b) me[a * kNb + b] = F.mass[a][b];
+  double self[3][3][kNb][kNb];
+  for (int ez = 0; ez < n; ++ez)
+    for (int ey = 0; ey < n; ++ey)
+      for (int ex = 0; ex < n; ++ex) {
+        const int64_t e = ((int64_t)ez * n + ey) * n + ex;
+        const int c[3] = {ex, ey, ez};
+        std::memcpy(self, F.vol, sizeof(self));
+        auto add = [&](const double (&B)[3][3][kNb][kNb]) {
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              for (int a = 0; a < kNb; ++a)
+                for (int b = 0; b < kNb; ++b) self[i][j][a][b] += B[i][j][a][b];
+        };
+        auto put = [&](int slot, const double (&B)[3][3][kNb][kNb]) {
+          double* blk = cd.data() + ((size_t)slot * ne + e) * 576;
+          double* lb = ld.data() + ((size_t)slot * ne + e) * 64;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              for (int a = 0; a < kNb; ++a)
+                for (int b = 0; b < kNb; ++b) {
+                  // row 8 j + a (test component j), column 8 i + b (trial i)
+                  blk[(8 * i + b) * 24 + 8 * j + a] = B[i][j][a][b];
+                  if (i == j) lb[b * 8 + a] += B[i][j][a][b];
+                }
+        };
+        for (int axis = 0; axis < 3; ++axis) {
+          if (c[axis] + 1 < n) {           // element is the lower side of the +axis face
+            add(F.face[axis][0][0]);
+            put(2 + 2 * axis, F.face[axis][0][1]);
+          }
+          if (c[axis] > 0) {               // upper side of the -axis face
+            add(F.face[axis][1][1]);
+            put(1 + 2 * axis, F.face[axis][1][0]);
+          }
+        }
+        if (ex == n - 1) add(F.out);
+        put(0, self);
+        // block-Jacobi: inverse of the diagonal block of (dt/3) L
+        double dblk[kNb][kNb], inv[kNb][kNb];
+        for (int a = 0; a < kNb; ++a)
+          for (int b = 0; b < kNb; ++b)
+            dblk[a][b] = dt / 3.0 * (self[0][0][a][b] + self[1][1][a][b] + self[2][2][a][b]);
+        invert8(dblk, inv);
+        for (int a = 0; a < kNb; ++a)
+          for (int b = 0; b < kNb; ++b) dinv[(size_t)e * 64 + b * 8 + a] = inv[a][b];
+      }
+}
+
+template <typename T>
+T* dev_alloc(size_t count) {
+  void* p = nullptr;
+  H3(hipMalloc(&p, count * sizeof(T)));
+  return static_cast<T*>(p);
+}
+
+}  // namespace
+
+struct dcg3d_ctx {
+  int n = 0;
+  int64_t ne = 0, nt = 0, ns = 0;     // elements, tensor length, scalar length
+  double dt = 0, nu = 1, penalty = 0;
+  dcg_options opt{};
+  double* Cd = nullptr;
+  double* Ld = nullptr;
+  double* Dinv = nullptr;
+  double* Me = nullptr;
+  // tensor workspace
+  double *w = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *xh = nullptr, *pf = nullptr,
+         *tz = nullptr;
+  // scalar workspace
+  double *s = nullptr, *yh = nullptr, *ir = nullptr, *iz = nullptr, *ip = nullptr, *iq = nullptr;
+  double *part = nullptr, *part2 = nullptr, *dots = nullptr;
+  dcg3::PcgScalars* sc = nullptr;
+  dcg3::PcgScalars* sc_host = nullptr;
+  double* dots_host = nullptr;
+  std::string last_error;
+  double t_setup_ms = 0;
+  int64_t inner_total = 0, inner_solves = 0;
+
+  ~dcg3d_ctx() {
+    for (double* b : {Cd, Ld, Dinv, Me, w, r, p, q, xh, pf, tz, s, yh, ir, iz, ip, iq, part, part2, dots})
+      if (b) (void)hipFree(b);
+    if (sc) (void)hipFree(sc);
+    if (sc_host) (void)hipHostFree(sc_host);
+    if (dots_host) (void)hipHostFree(dots_host);
+  }
+
+  void setup() {
+    ne = (int64_t)n * n * n;
+    nt = ne * kDof;
+    ns = ne * kNb;
+    std::vector<double> cd, ld, dinv, me;
+    assemble3d(n, penalty, dt, cd, ld, dinv, me);
+    Cd = dev_alloc<double>(cd.size());
+    Ld = dev_alloc<double>(ld.size());
+    Dinv = dev_alloc<double>(dinv.size());
+    Me = dev_alloc<double>(64);
+    H3(hipMemcpy(Cd, cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice));
+    H3(hipMemcpy(Ld, ld.data(), ld.size() * sizeof(double), hipMemcpyHostToDevice));
+    H3(hipMemcpy(Dinv, dinv.data(), dinv.size() * sizeof(double), hipMemcpyHostToDevice));
+    H3(hipMemcpy(Me, me.data(), 64 * sizeof(double), hipMemcpyHostToDevice));
+    for (double** b : {&w, &r, &p, &q, &xh, &pf, &tz}) *b = dev_alloc<double>(nt);
+    for (double** b : {&s, &yh, &ir, &iz, &ip, &iq}) *b = dev_alloc<double>(ns);
+    const int64_t np = 2 * ((ns + 255) / 256) + 1024;
+    part = dev_alloc<double>(np);
+    part2 = dev_alloc<double>(np);
+    dots = dev_alloc<double>(8);
+    H3(hipMalloc(&sc, sizeof(dcg3::PcgScalars)));
+    H3(hipHostMalloc(&sc_host, sizeof(dcg3::PcgScalars), hipHostMallocDefault));
+    H3(hipHostMalloc(&dots_host, 8 * sizeof(double), hipHostMallocDefault));
+  }
+
+  // ---- building blocks on the legacy default stream
+  double dot(const double* x, const double* y, int64_t len) {
+    H3(dcg3::launch_dot(len, x, y, part, dots, nullptr));
+    H3(hipMemcpyAsync(dots_host, dots, sizeof(double), hipMemcpyDeviceToHost, nullptr));
+    H3(hipStreamSynchronize(nullptr));
+    return dots_host[0];
+  }
+  void copy(const double* x, double* y, int64_t len) {
+    H3(hipMemcpyAsync(y, x, len * sizeof(double), hipMemcpyDeviceToDevice, nullptr));
+  }
+  void astar(const double* x, double* y) {
+    H3(dcg3::launch_astar3(n, Cd, Me, 1.0 / nu, dt, x, y, nullptr));
+  }
+
+  // yh = E^{-1} s to ||s - E yh|| <= rel ||s|| by block-Jacobi CG; returns the
+  // number of steps.
+  int inner(const double* rhs, double* out, double rel) {
+    H3(dcg3::launch_pcg_start(ne, Dinv, rhs, out, ir, iz, ip, part, sc, rel * rel, nullptr));
+    H3(hipMemcpyAsync(sc_host, sc, sizeof(*sc), hipMemcpyDeviceToHost, nullptr));
+    H3(hipStreamSynchronize(nullptr));
+    const int nblk = int((ns + 255) / 256);
+    int done = 0;
+    while (sc_host->active && done < opt.max_inner) {
+      const int chunk = std::min(8, opt.max_inner - done);
+      for (int c = 0; c < chunk; ++c) {
+        H3(dcg3::launch_lap3(n, Ld, dt / 3.0, ip, iq, part, nullptr));
+        H3(dcg3::launch_pcg_step(ne, Dinv, out, ir, iz, ip, iq, part, part2, nblk, sc, nullptr));
+      }
+      done += chunk;
+      H3(hipMemcpyAsync(sc_host, sc, sizeof(*sc), hipMemcpyDeviceToHost, nullptr));
+      H3(hipStreamSynchronize(nullptr));
+    }
+    inner_total += sc_host->iters;
+    inner_solves += 1;
+    return sc_host->iters;
+  }
+
+  // Algorithm 2 with the CG outer iteration (d = 3).
+  dcg_status solve(const double* f, double* x, double tol, dcg_stats* st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    inner_total = inner_solves = 0;
+    const double rel_in = opt.c_F * tol;
+    const double fnorm = std::sqrt(dot(f, f, nt));
+    dcg_stats out{};
+    out.t_setup_ms = t_setup_ms;
+    if (!std::isfinite(fnorm)) throw Err3(DCG_EINVAL, "right-hand side is not finite");
+    if (fnorm == 0.0) {
+      H3(dcg3::launch_fill(nt, 0.0, x, nullptr));
+      H3(hipStreamSynchronize(nullptr));
+      if (st) *st = out;
+      return DCG_OK;
+    }
+    // prologue: pf = pi(f) = Z E^{-1} Z^T f, f_D = f - A* pf
+    H3(dcg3::launch_zt3(ne, f, s, nullptr));
+    inner(s, yh, rel_in);
+    H3(dcg3::launch_fill(nt, 0.0, pf, nullptr));
+    H3(dcg3::launch_zaxpy3(ne, 1.0, yh, pf, nullptr));
+    astar(pf, w);
+    copy(f, r, nt);
+    H3(dcg3::launch_axpy(nt, -1.0, w, r, nullptr));
+    H3(dcg3::launch_fill(nt, 0.0, xh, nullptr));
+    copy(r, p, nt);
+    double rho = dot(r, r, nt);
+    int it = 0;
+    dcg_status status = DCG_OK;
+    while (it < opt.max_outer && std::sqrt(rho) > tol * fnorm) {
+      // q = M_D p = w - dt A_div Z E^{-1} Z^T w, w = A* p
+      astar(p, w);
+      H3(dcg3::launch_zt3(ne, w, s, nullptr));
+      inner(s, yh, rel_in);
+      H3(dcg3::launch_adivz3(n, Cd, dt, w, yh, q, nullptr));
+      const double pq = dot(p, q, nt);
+      if (!(pq > 0.0) || !std::isfinite(pq)) {
+        status = DCG_EBREAKDOWN;
+        break;
+      }
+      const double alpha = rho / pq;
+      H3(dcg3::launch_axpy(nt, alpha, p, xh, nullptr));
+      H3(dcg3::launch_axpy(nt, -alpha, q, r, nullptr));
+      const double rho_new = dot(r, r, nt);
+      H3(dcg3::launch_xpby(nt, r, rho_new / rho, p, nullptr));
+      rho = rho_new;
+      ++it;
+    }
+    if (status == DCG_OK && std::sqrt(rho) > tol * fnorm) status = DCG_NOT_CONVERGED;
+    // epilogue: x = (x_hat - pi(A* x_hat)) + pi(f)
+    astar(xh, w);
+    H3(dcg3::launch_zt3(ne, w, s, nullptr));
+    inner(s, yh, rel_in);
+    copy(xh, x, nt);
+    H3(dcg3::launch_zaxpy3(ne, -1.0, yh, x, nullptr));
+    H3(dcg3::launch_axpy(nt, 1.0, pf, x, nullptr));
+    // true residual of the reconstructed x
+    astar(x, w);
+    copy(f, tz, nt);
+    H3(dcg3::launch_axpy(nt, -1.0, w, tz, nullptr));
+    const double res = std::sqrt(dot(tz, tz, nt));
+    out.status = status;
+    out.outer_iters = it;
+    out.total_wcycles = int32_t(inner_total);
+    out.inner_solves = int32_t(inner_solves);
+    out.inner_per_outer = it > 0 ? double(inner_total) / it : 0.0;
+    out.rel_res_recurrence = std::sqrt(rho) / fnorm;
+    out.rel_res_true = res / fnorm;
+    out.t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = out;
+    return status;
+  }
+
+  void apply(int op, const double* in, double* outv, double tol) {
+    switch (op) {
+      case DCG3D_OP_ASTAR:
+        astar(in, outv);
+        break;
+      case DCG3D_OP_ZT:
+        H3(dcg3::launch_zt3(ne, in, outv, nullptr));
+        break;
+      case DCG3D_OP_Z:
+        H3(dcg3::launch_fill(nt, 0.0, outv, nullptr));
+        H3(dcg3::launch_zaxpy3(ne, 1.0, in, outv, nullptr));
+        break;
+      case DCG3D_OP_DEFLATED:
+        astar(in, w);
+        H3(dcg3::launch_zt3(ne, w, s, nullptr));
+        inner(s, yh, tol);
+        H3(dcg3::launch_adivz3(n, Cd, dt, w, yh, outv, nullptr));
+        break;
+      case DCG3D_OP_REDUCED:
+        H3(dcg3::launch_lap3(n, Ld, dt / 3.0, in, outv, part, nullptr));
+        break;
+      case DCG3D_OP_INNER:
+        inner(in, outv, tol);
+        break;
+      case DCG3D_OP_ADIVZ:
+        H3(dcg3::launch_fill(nt, 0.0, tz, nullptr));
+        H3(dcg3::launch_adivz3(n, Cd, -1.0, tz, in, outv, nullptr));
+        break;
+      default:
+        throw Err3(DCG_EINVAL, "unknown operator");
+    }
+    H3(hipStreamSynchronize(nullptr));
+  }
+};
+
+namespace {
+
+dcg_status fail3(dcg3d_ctx* h, dcg_status s, const std::string& msg) {
+  g_last_error3 = msg;
+  if (h) h->last_error = msg;
+  return s;
+}
+
+template <typename Fn>
+dcg_status guarded3(dcg3d_ctx* h, Fn fn) {
+  try {
+    return fn();
+  } catch (const Err3& e) {
+    return fail3(h, e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail3(h, DCG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail3(h, DCG_EINVAL, e.what());
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, const dcg_options* opt,
+                       dcg3d_handle* out) {
+  if (!out) return fail3(nullptr, DCG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 2 || n > DCG3D_MAX_N) return fail3(nullptr, DCG_EINVAL, "n must be in [2, 64]");
+  if (!(penalty > 0.0) || !std::isfinite(penalty)) return fail3(nullptr, DCG_EINVAL, "penalty must be positive");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(nu > 0.0) || !std::isfinite(nu))
+    return fail3(nullptr, DCG_EINVAL, "dt and nu must be positive");
+  dcg_options o{};
+  if (opt) {
+    o = *opt;
+  } else {
+    dcg_mesh m{};
+    dcg_defaults(&m, &o);
+    o.prec = DCG_FP64;
+    o.max_inner = DCG3D_DEFAULT_MAX_INNER;
+  }
+  if (o.prec != DCG_FP64) return fail3(nullptr, DCG_EINVAL, "the 3D solver computes in FP64 only");
+  if (o.outer != DCG_OUTER_CG) return fail3(nullptr, DCG_EINVAL, "the 3D solver runs the CG outer iteration");
+  if (o.c_A != 0.0) return fail3(nullptr, DCG_EINVAL, "the 3D solver uses the fixed inner tolerance (c_A = 0)");
+  if (o.x0_given) return fail3(nullptr, DCG_EINVAL, "the 3D solver starts from x0 = 0");
+  if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
+    return fail3(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
+  auto* h = new (std::nothrow) dcg3d_ctx();
+  if (!h) return fail3(nullptr, DCG_ENOMEM, "host allocation failed");
+  h->n = n;
+  h->dt = dt;
+  h->nu = nu;
+  h->penalty = penalty;
+  h->opt = o;
+  const auto t0 = std::chrono::steady_clock::now();
+  const dcg_status s = guarded3(h, [&] {
+    h->setup();
+    H3(hipDeviceSynchronize());
+    return DCG_OK;
+  });
+  if (s != DCG_OK) {
+    delete h;
+    return s;
+  }
+  h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return DCG_OK;
+}
+
+dcg_status dcg3d_solve(dcg3d_handle h, const double* b, double* x, double tol, dcg_stats* st) {
+  if (!h || !b || !x) return fail3(h, DCG_EINVAL, "NULL argument");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail3(h, DCG_EINVAL, "tol must be positive");
+  return guarded3(h, [&] { return h->solve(b, x, tol, st); });
+}
+
+dcg_status dcg3d_apply(dcg3d_handle h, dcg3d_op op, const double* in, double* out, double tol) {
+  if (!h || !in || !out) return fail3(h, DCG_EINVAL, "NULL argument");
+  if ((op == DCG3D_OP_DEFLATED || op == DCG3D_OP_INNER) && (!(tol > 0.0) || !std::isfinite(tol)))
+    return fail3(h, DCG_EINVAL, "tol must be positive");
+  return guarded3(h, [&] {
+    h->apply(op, in, out, tol);
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg3d_destroy(dcg3d_handle h) {
+  delete h;
+  return DCG_OK;
+}
+
+dcg_status dcg3d_host_blocks(int32_t n, double penalty, double dt, int32_t which, double* out) {
+  if (!out) return fail3(nullptr, DCG_EINVAL, "out is NULL");
+  if (n < 2 || n > DCG3D_MAX_HOST_BLOCKS_N) return fail3(nullptr, DCG_EINVAL, "n must be in [2, 16]");
+  if (!(penalty > 0.0) || !(dt > 0.0)) return fail3(nullptr, DCG_EINVAL, "penalty and dt must be positive");
+  if (which < 0 || which > 3) return fail3(nullptr, DCG_EINVAL, "which must be 0..3");
+  return guarded3(nullptr, [&] {
+    std::vector<double> cd, ld, dinv, me;
+    assemble3d(n, penalty, dt, cd, ld, dinv, me);
+    const std::vector<double>* src[4] = {&cd, &ld, &dinv, &me};
+    std::memcpy(out, src[which]->data(), src[which]->size() * sizeof(double));
+    return DCG_OK;
+  });
+}
+
+const char* dcg3d_last_error(dcg3d_handle h) { return h ? h->last_error.c_str() : g_last_error3.c_str(); }
+
+}  // extern "C"

@@ -37,3 +37,13 @@ def block_ell_to_csr(vals, cols, ne, rows, ncols, ne_cols=None):
         V.append(v[ok, s].ravel())
     return sp.csr_matrix((np.concatenate(V), (np.concatenate(R), np.concatenate(C))),
                          shape=(ne * rows, ne_cols * ncols))
+
+
+def elem_to_comp3(v, n):
+    """3D tensor vector [72 e + 8 c + a] -> [c * 8 n^3 + 8 e + a]."""
+    return np.asarray(v).reshape(n ** 3, 9, 8).transpose(1, 0, 2).reshape(-1)
+
+
+def comp_to_elem3(v, n):
+    """[c * 8 n^3 + 8 e + a] -> [72 e + 8 c + a]."""
+    return np.asarray(v).reshape(9, n ** 3, 8).transpose(1, 0, 2).reshape(-1)

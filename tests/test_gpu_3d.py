@@ -1,0 +1,174 @@
+"""The 3D path (dcg3d_*) against the oracle's 3D discretisation and Algorithm 2.
+
+Operators: every dcg3d_apply operator element by element against the
+oracle's sparse matrices, at sizes that leave a ragged last workgroup
+(8 elements per A* workgroup, 32 per scalar workgroup).  Bar: max abs
+difference <= 1e-12 x max |oracle| (FP64, different summation order); the
+inner solve to its residual tolerance.  Solve: outer iteration counts within
+max(2, 2 %) of the oracle's deflated CG with an exact inner solve, x within 1e-6 of
+the direct solution (inner residual 1e-12, tol 1e-10) and the true residual
+at the requested tolerance.  At the benchmark size (n = 32) the operators
+are checked through identities that hold at any size (symmetry, M Z = 0,
+Corollary 1) and the solve for convergence and bitwise repeatability."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from dcg_workloads import THREE_D, rhs3d
+from layout import comp_to_elem3, elem_to_comp3
+from oracle import discretisation3d as d3
+from oracle import krylov as kr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lib = pytest.importorskip("paper_2606_13429_amd._binding")
+import paper_2606_13429_amd as dcg  # noqa: E402
+
+PEN, NU = THREE_D["penalty"], THREE_D["nu"]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _close(got, ref, rel=1e-12):
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(got - ref).max() / scale
+    assert err <= rel, "max rel error %.3e" % err
+
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_operators_match_oracle(n):
+    dt = 3e-3
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN)
+    m = 8 * n ** 3
+    print("3d operators n=%d" % n, flush=True)
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(9 * m)                  # element-major tensor
+    y = rng.standard_normal(m)                      # scalar
+    As = d3.operator(n, dt, nu=NU, penalty=PEN)
+    V = d3.deflation_basis(n)
+    out_t = torch.empty(9 * m, dtype=torch.float64, device="cuda")
+    out_s = torch.empty(m, dtype=torch.float64, device="cuda")
+    # A*
+    s.apply(lib.DCG3D_OP_ASTAR, _dev(x), out_t)
+    _close(_host(out_t), comp_to_elem3(As @ elem_to_comp3(x, n), n))
+    # Z^T and Z
+    s.apply(lib.DCG3D_OP_ZT, _dev(x), out_s)
+    _close(_host(out_s), V.T @ elem_to_comp3(x, n))
+    s.apply(lib.DCG3D_OP_Z, _dev(y), out_t)
+    _close(_host(out_t), comp_to_elem3(V @ y, n))
+    # A_div Z (assembled directly in the oracle, Corollary 1 proof)
+    s.apply(lib.DCG3D_OP_ADIVZ, _dev(y), out_t)
+    _close(_host(out_t), comp_to_elem3(d3.divdiv_on_identity(n, PEN) @ y, n))
+    # E = Z^T A* Z = (dt / 3) L
+    E = (V.T @ As @ V).tocsc()
+    s.apply(lib.DCG3D_OP_REDUCED, _dev(y), out_s)
+    _close(_host(out_s), E @ y)
+    # inner solve to a relative residual of 1e-12
+    s.apply(lib.DCG3D_OP_INNER, _dev(y), out_s, 1e-12)
+    z = _host(out_s)
+    assert np.linalg.norm(E @ z - y) <= 1.5e-12 * np.linalg.norm(y)
+    _close(z, spla.spsolve(E, y), rel=1e-8)
+    # deflated operator M_D x = A* (x - pi(A* x))
+    s.apply(lib.DCG3D_OP_DEFLATED, _dev(x), out_t, 1e-13)
+    w = As @ elem_to_comp3(x, n)
+    ref = As @ (elem_to_comp3(x, n) - V @ spla.spsolve(E, V.T @ w))
+    _close(_host(out_t), comp_to_elem3(ref, n), rel=1e-9)
+    s.close()
+
+
+_ORACLE = {}
+
+
+def _oracle(n, dt, seed, tol):
+    key = (n, dt, seed, tol)
+    if key not in _ORACLE:
+        As = d3.operator(n, dt, nu=NU, penalty=PEN)
+        V = d3.deflation_basis(n)
+        E = (V.T @ As @ V).tocsr()
+        f = elem_to_comp3(rhs3d(n, seed), n)
+        res = kr.dcg(As, V, f, kr.exact_inner(E), tol=tol)
+        _ORACLE[key] = (res, spla.spsolve(As.tocsc(), f))
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("n,dt", [(3, 1e-1), (4, 1e-3), (4, 1e-5), (5, 1e-2)])
+def test_solve_matches_oracle(n, dt):
+    tol = 1e-10
+    res, x_direct = _oracle(n, dt, 11, tol)
+    print("3d solve n=%d dt=%g" % (n, dt), flush=True)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, c_F=1e-2)
+    b = _dev(rhs3d(n, 11))
+    x = torch.empty_like(b)
+    status, st = s.solve(b, x, tol)
+    s.close()
+    assert status == lib.DCG_OK
+    # finite-precision CG: counts of long runs drift with rounding and with the
+    # 1e-12 inner residual, so the bar is +-2 or 2 % of the oracle's count
+    assert abs(st.outer_iters - res.iterations) <= max(2, 0.02 * res.iterations), \
+        (st.outer_iters, res.iterations)
+    xg = elem_to_comp3(_host(x), n)
+    assert np.linalg.norm(xg - x_direct) <= 1e-6 * np.linalg.norm(x_direct)
+    assert np.linalg.norm(xg - res.x) <= 1e-6 * np.linalg.norm(res.x)
+    assert st.rel_res_recurrence <= tol
+    assert st.rel_res_true <= 10 * tol
+    assert st.inner_solves == st.outer_iters + 2
+
+
+def test_zero_rhs_and_argument_errors():
+    s = dcg.Solver3D(2, 1e-3)
+    b = torch.zeros(72 * 8, dtype=torch.float64, device="cuda")
+    x = torch.full_like(b, 7.0)
+    status, st = s.solve(b, x, 1e-8)
+    assert status == lib.DCG_OK and st.outer_iters == 0 and float(x.abs().max()) == 0.0
+    with pytest.raises(lib.DCGError):
+        s.solve(b, x, -1.0)
+    with pytest.raises(lib.DCGError):
+        s.apply(lib.DCG3D_OP_INNER, b[:64], x[:64], 0.0)
+    s.close()
+    with pytest.raises(lib.DCGError):
+        dcg.Solver3D(1, 1e-3)
+    with pytest.raises(lib.DCGError):
+        dcg.Solver3D(4, -1.0)
+    _, opt = lib.dcg_defaults()
+    opt.prec = lib.DCG_MIXED
+    with pytest.raises(lib.DCGError):
+        lib.dcg3d_setup(4, PEN, 1e-3, 1.0, opt)
+
+
+def test_full_size_identities_and_solve():
+    n, dt, tol = THREE_D["n"], THREE_D["dt"], THREE_D["tol"]
+    print("3d full size n=%d" % n, flush=True)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN)
+    m = 8 * n ** 3
+    rng = np.random.default_rng(3)
+    u, v = _dev(rng.standard_normal(9 * m)), _dev(rng.standard_normal(9 * m))
+    y = _dev(rng.standard_normal(m))
+    Au, Av = torch.empty_like(u), torch.empty_like(v)
+    s.apply(lib.DCG3D_OP_ASTAR, u, Au)
+    s.apply(lib.DCG3D_OP_ASTAR, v, Av)
+    a, b_ = float(torch.dot(v, Au)), float(torch.dot(u, Av))
+    assert abs(a - b_) <= 1e-12 * (float(u.norm() * Av.norm()))          # A* symmetric
+    Zy, AZy, AdZy = torch.empty_like(u), torch.empty_like(u), torch.empty_like(u)
+    s.apply(lib.DCG3D_OP_Z, y, Zy)
+    s.apply(lib.DCG3D_OP_ASTAR, Zy, AZy)
+    s.apply(lib.DCG3D_OP_ADIVZ, y, AdZy)
+    _close(_host(AZy), dt * _host(AdZy), rel=1e-12)                       # M Z = 0
+    ZtAdZy, Ey = torch.empty_like(y), torch.empty_like(y)
+    s.apply(lib.DCG3D_OP_ZT, AdZy, ZtAdZy)
+    s.apply(lib.DCG3D_OP_REDUCED, y, Ey)
+    _close(dt * _host(ZtAdZy), _host(Ey), rel=1e-12)                      # Corollary 1
+    b = _dev(rhs3d(n, 0))
+    x1, x2 = torch.empty_like(b), torch.empty_like(b)
+    status, st = s.solve(b, x1, tol)
+    assert status == lib.DCG_OK and st.rel_res_true <= 10 * tol
+    status, st2 = s.solve(b, x2, tol)
+    assert torch.equal(x1, x2) and st2.outer_iters == st.outer_iters
+    s.close()
