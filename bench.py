@@ -316,6 +316,67 @@ def timestep(args):
                       "rows": rows}), flush=True)
 
 
+def lap3_bytes(n):
+    """Algorithmic HBM bytes of one k_lap3 launch (the inner Laplacian of the
+    3D solver): the 8 x 8 FP64 blocks that exist (the element and its face
+    neighbours inside the cube) plus p read and q written once."""
+    ne = n ** 3
+    nblocks = ne + 6 * n * n * (n - 1)
+    return 8 * (64 * nblocks + 16 * ne)
+
+
+def three_d(args):
+    """The 3D solver (d = 3 block structure) at n^3 = 32^3 cubes, dt = 1e-3,
+    FP64: solves/s, outer and inner counts, and the roofline of the inner
+    Laplacian product, timed with HIP events inside the library."""
+    import torch
+    import paper_2606_13429_amd as dcg
+    from paper_2606_13429_amd import _binding as lib
+    from dcg_workloads import THREE_D, rhs3d
+    n, dt, tol = args.n3, THREE_D["dt"], THREE_D["tol"]
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"])
+    log("3d setup n=%d (%d elements) %.1f s" % (n, n ** 3, time.time() - t0))
+    bs = [torch.from_numpy(rhs3d(n, i)).cuda() for i in range(max(args.steps, 1))]
+    x = torch.empty_like(bs[0])
+    for i in range(args.warmup):
+        st = s.solve(bs[0], x, tol)[1]
+        log("3d warmup %d: outer=%d inner steps=%d %.1f ms" % (i, st.outer_iters, st.total_wcycles,
+                                                                 st.t_solve_ms))
+    lib.dcg3d_kernel_timing(s.handle, True)
+    rows = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        status, st = s.solve(bs[i], x, tol)
+        rows.append({"status": status, "outer": st.outer_iters, "inner_steps": st.total_wcycles,
+                     "inner_per_outer": round(st.inner_per_outer, 2), "rel_res_true": st.rel_res_true,
+                     "ms": round(st.t_solve_ms, 1)})
+        log("3d step %d: status=%d outer=%d inner steps=%d res=%.2e %.1f ms"
+            % (i, status, st.outer_iters, st.total_wcycles, st.rel_res_true, st.t_solve_ms))
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all
+    k_ms, k_n = lib.dcg3d_kernel_timing_read(s.handle)
+    lib.dcg3d_kernel_timing(s.handle, False)
+    k_avg = k_ms / max(k_n, 1)
+    nbytes = lap3_bytes(n)
+    gbs = nbytes / (k_avg * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "3D dCG solves/s, %d^3 DG-Q1 cubes, dt=%g, FP64" % (n, dt),
+        "value": round(args.steps / t_all, 5), "unit": "solves/s", "steps": args.steps,
+        "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D pseudo-stress A* x = b, n=%d, dt=%g, nu=%g, penalty=%g, tol=%g"
+                   % (n, dt, THREE_D["nu"], THREE_D["penalty"], tol)},
+        "roofline": {"bound": "hbm", "kernel": "k_lap3 (inner Laplacian product)",
+                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n,
+                     "bytes_per_launch": nbytes},
+        "rows": rows}), flush=True)
+    s.close()
+
+
 def variants(args):
     """The inner-tolerance rule and outer variant at the headline size: the
     fixed rule (eq. (fixed_tol), c_F = 0.01) against the adaptive rule
@@ -384,6 +445,9 @@ def main():
     ap.add_argument("--sweep-max-outer", type=int, default=20000)
     ap.add_argument("--timestep", action="store_true", help="run BDF2 time stepping at n=1024")
     ap.add_argument("--ts-steps", type=int, default=3)
+    ap.add_argument("--3d", dest="three_d", action="store_true",
+                    help="run the 3D solver at --n3 cubes per side")
+    ap.add_argument("--n3", type=int, default=32)
     ap.add_argument("--variants", action="store_true",
                     help="compare the fixed and adaptive inner tolerance at --n/--dt")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -410,6 +474,9 @@ def main():
         return
     if args.timestep:
         timestep(args)
+        return
+    if args.three_d:
+        three_d(args)
         return
 
     import numpy as np

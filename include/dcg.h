@@ -344,6 +344,12 @@ dcg_status dcg3d_solve(dcg3d_handle h, const double* b, double* x, double tol, d
 dcg_status dcg3d_apply(dcg3d_handle h, dcg3d_op op, const double* in, double* out, double tol);
 dcg_status dcg3d_destroy(dcg3d_handle h);
 const char* dcg3d_last_error(dcg3d_handle h);
+/* Measurement: while enabled, every launch of the inner solve's Laplacian
+ * product (the dominant kernel of the 3D solve) is bracketed by HIP events on
+ * the legacy default stream; _read returns their summed duration and count
+ * since the last enable / read and restarts the count. */
+dcg_status dcg3d_kernel_timing(dcg3d_handle h, int32_t enable);
+dcg_status dcg3d_kernel_timing_read(dcg3d_handle h, double* total_ms, int64_t* launches);
 
 /* Host only (no device call, 2 <= n <= 16): copies the blocks the 3D path
  * assembles into the HOST buffer out, for checks of the assembly without a

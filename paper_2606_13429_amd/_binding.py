@@ -87,6 +87,8 @@ _SIGS = {
     "dcg3d_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.c_double, _P(dcg_stats)]),
     "dcg3d_apply": (ctypes.c_int, [_h, ctypes.c_int, _vp, _vp, ctypes.c_double]),
     "dcg3d_destroy": (ctypes.c_int, [_h]),
+    "dcg3d_kernel_timing": (ctypes.c_int, [_h, ctypes.c_int32]),
+    "dcg3d_kernel_timing_read": (ctypes.c_int, [_h, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "dcg3d_last_error": (ctypes.c_char_p, [_h]),
     "dcg3d_host_blocks": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                          _P(ctypes.c_double)]),
@@ -330,3 +332,14 @@ def dcg3d_host_blocks(n, penalty, dt, which):
     out = np.empty(size, dtype=np.float64)
     _check3(_lib.dcg3d_host_blocks(n, penalty, dt, which, out.ctypes.data_as(_P(ctypes.c_double))))
     return out
+
+
+def dcg3d_kernel_timing(handle, enable):
+    return _check3(_lib.dcg3d_kernel_timing(handle, int(bool(enable))), handle)
+
+
+def dcg3d_kernel_timing_read(handle):
+    """Returns (total ms, launches) of the timed Laplacian launches."""
+    ms, k = ctypes.c_double(), ctypes.c_int64()
+    _check3(_lib.dcg3d_kernel_timing_read(handle, ctypes.byref(ms), ctypes.byref(k)), handle)
+    return ms.value, k.value

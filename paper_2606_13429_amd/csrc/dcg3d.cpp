@@ -251,10 +251,24 @@ struct dcg3d_ctx {
   std::string last_error;
   double t_setup_ms = 0;
   int64_t inner_total = 0, inner_solves = 0;
+  // optional HIP-event timing of the Laplacian launches of the inner solves
+  bool timing = false;
+  std::vector<hipEvent_t> evs;
+  size_t ev_used = 0;
+
+  void time_mark() {
+    if (ev_used == evs.size()) {
+      hipEvent_t e;
+      H3(hipEventCreate(&e));
+      evs.push_back(e);
+    }
+    H3(hipEventRecord(evs[ev_used++], nullptr));
+  }
 
   ~dcg3d_ctx() {
     for (double* b : {Cd, Ld, Dinv, Me, w, r, p, q, xh, pf, tz, s, yh, ir, iz, ip, iq, part, part2, dots})
       if (b) (void)hipFree(b);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     if (sc) (void)hipFree(sc);
     if (sc_host) (void)hipHostFree(sc_host);
     if (dots_host) (void)hipHostFree(dots_host);
@@ -310,7 +324,9 @@ struct dcg3d_ctx {
     while (sc_host->active && done < opt.max_inner) {
       const int chunk = std::min(8, opt.max_inner - done);
       for (int c = 0; c < chunk; ++c) {
+        if (timing) time_mark();
         H3(dcg3::launch_lap3(n, Ld, dt / 3.0, ip, iq, part, nullptr));
+        if (timing) time_mark();
         H3(dcg3::launch_pcg_step(ne, Dinv, out, ir, iz, ip, iq, part, part2, nblk, sc, nullptr));
       }
       done += chunk;
@@ -531,6 +547,33 @@ dcg_status dcg3d_host_blocks(int32_t n, double penalty, double dt, int32_t which
     assemble3d(n, penalty, dt, cd, ld, dinv, me);
     const std::vector<double>* src[4] = {&cd, &ld, &dinv, &me};
     std::memcpy(out, src[which]->data(), src[which]->size() * sizeof(double));
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg3d_kernel_timing(dcg3d_handle h, int32_t enable) {
+  if (!h) return fail3(nullptr, DCG_EINVAL, "NULL handle");
+  return guarded3(h, [&] {
+    H3(hipStreamSynchronize(nullptr));
+    h->timing = enable != 0;
+    h->ev_used = 0;
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg3d_kernel_timing_read(dcg3d_handle h, double* total_ms, int64_t* launches) {
+  if (!h || !total_ms || !launches) return fail3(h, DCG_EINVAL, "NULL argument");
+  return guarded3(h, [&] {
+    H3(hipStreamSynchronize(nullptr));
+    double sum = 0.0;
+    for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+      float ms = 0.0f;
+      H3(hipEventElapsedTime(&ms, h->evs[i], h->evs[i + 1]));
+      sum += ms;
+    }
+    *total_ms = sum;
+    *launches = int64_t(h->ev_used / 2);
+    h->ev_used = 0;
     return DCG_OK;
   });
 }
