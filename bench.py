@@ -325,10 +325,20 @@ def lap3_bytes(n):
     return 8 * (64 * nblocks + 16 * ne)
 
 
+def astar3_bytes(n):
+    """Algorithmic HBM bytes of one k_astar3 launch (the 3D A* product): the
+    24 x 24 FP64 blocks C_3 that exist, plus x read and y written once."""
+    ne = n ** 3
+    nblocks = ne + 6 * n * n * (n - 1)
+    return 8 * (576 * nblocks + 144 * ne)
+
+
 def three_d(args):
     """The 3D solver (d = 3 block structure) at n^3 = 32^3 cubes, dt = 1e-3,
-    FP64: solves/s, outer and inner counts, and the roofline of the inner
-    Laplacian product, timed with HIP events inside the library."""
+    FP64, with the exact inner solve (fast diagonalisation, the setting of
+    Table 5 left) or block-Jacobi CG (--3d-inner cg): solves/s, outer and
+    inner counts, and the roofline of the dominant kernel (A* resp. the inner
+    Laplacian product), timed with HIP events inside the library."""
     import torch
     import paper_2606_13429_amd as dcg
     from paper_2606_13429_amd import _binding as lib
@@ -336,7 +346,7 @@ def three_d(args):
     n, dt, tol = args.n3, THREE_D["dt"], THREE_D["tol"]
     torch.cuda.set_device(0)
     t0 = time.time()
-    s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"])
+    s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], inner=args.inner3)
     log("3d setup n=%d (%d elements) %.1f s" % (n, n ** 3, time.time() - t0))
     bs = [torch.from_numpy(rhs3d(n, i)).cuda() for i in range(max(args.steps, 1))]
     x = torch.empty_like(bs[0])
@@ -360,15 +370,18 @@ def three_d(args):
     k_ms, k_n = lib.dcg3d_kernel_timing_read(s.handle)
     lib.dcg3d_kernel_timing(s.handle, False)
     k_avg = k_ms / max(k_n, 1)
-    nbytes = lap3_bytes(n)
+    exact = args.inner3 == "exact"
+    nbytes = astar3_bytes(n) if exact else lap3_bytes(n)
+    kname = "k_astar3 (A* product)" if exact else "k_lap3 (inner Laplacian product)"
     gbs = nbytes / (k_avg * 1e-3) / 1e9
     print(json.dumps({
-        "metric": "3D dCG solves/s, %d^3 DG-Q1 cubes, dt=%g, FP64" % (n, dt),
+        "metric": "3D dCG solves/s, %d^3 DG-Q1 cubes, dt=%g, FP64, inner %s"
+                  % (n, dt, "exact (fast diagonalisation)" if exact else "block-Jacobi CG"),
         "value": round(args.steps / t_all, 5), "unit": "solves/s", "steps": args.steps,
         "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "3D pseudo-stress A* x = b, n=%d, dt=%g, nu=%g, penalty=%g, tol=%g"
                    % (n, dt, THREE_D["nu"], THREE_D["penalty"], tol)},
-        "roofline": {"bound": "hbm", "kernel": "k_lap3 (inner Laplacian product)",
+        "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n,
@@ -448,6 +461,7 @@ def main():
     ap.add_argument("--3d", dest="three_d", action="store_true",
                     help="run the 3D solver at --n3 cubes per side")
     ap.add_argument("--n3", type=int, default=32)
+    ap.add_argument("--3d-inner", dest="inner3", choices=("exact", "cg"), default="exact")
     ap.add_argument("--variants", action="store_true",
                     help="compare the fixed and adaptive inner tolerance at --n/--dt")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

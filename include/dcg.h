@@ -301,10 +301,16 @@ void dcg_clear_cache(void);
  * imposes sigma n = 0).  Deflation basis Z = V of eq. (Vmatrix) for d = 3,
  * so Z^T A* Z = (dt/3)(B_11 + B_22 + B_33) (Corollary 1).
  *
- * Solve: Algorithm 2 with the CG outer iteration; the inner system is solved
- * by block-Jacobi preconditioned CG to the relative residual c_F * tol
- * (eq. (fixed_tol)), at most max_inner steps per inner solve.  Everything runs
- * in FP64 on the device; dcg_stats.total_wcycles counts inner CG steps.
+ * Solve: Algorithm 2 with the CG outer iteration.  The inner system
+ * E = Z^T A* Z = (dt/3) L is solved either exactly (DCG3D_INNER_FDM, the
+ * setting of Table 5, left): on this uniform grid L is the Kronecker sum of
+ * one-dimensional DG matrices, L = M (x) M (x) K_x + M (x) K_y (x) M +
+ * K_z (x) M (x) M, so L^{-1} = V diag(1/(lx + ly + lz)) V^T with the
+ * generalised eigenvectors of each axis (fast diagonalisation, six axis
+ * passes); or by block-Jacobi preconditioned CG to the relative residual
+ * c_F * tol (eq. (fixed_tol)), at most max_inner steps (DCG3D_INNER_PCG).
+ * Everything runs in FP64 on the device; dcg_stats.total_wcycles counts inner
+ * CG steps (0 for the exact solve).
  *
  * Layout (device pointers, FP64): tensor vectors 72 n^3 values, element-major,
  * idx = 72 e + 8 c + a with e = (ez n + ey) n + ex, c = 3 k + i for
@@ -319,22 +325,27 @@ void dcg_clear_cache(void);
 typedef struct dcg3d_ctx* dcg3d_handle;
 
 typedef enum {
+  DCG3D_INNER_FDM = 0,    /* exact inner solve by fast diagonalisation (default)  */
+  DCG3D_INNER_PCG = 1     /* block-Jacobi CG to c_F * tol                           */
+} dcg3d_inner;
+
+typedef enum {
   DCG3D_OP_ASTAR = 0,     /* out = A* in            (tensor -> tensor), eq. (pb_study)        */
   DCG3D_OP_ZT = 1,        /* out = Z^T in           (tensor -> scalar), eq. (Vmatrix)         */
   DCG3D_OP_Z = 2,         /* out = Z in             (scalar -> tensor)                        */
   DCG3D_OP_DEFLATED = 3,  /* out = M_D in = A*(in - Z E^{-1} Z^T A* in), inner to tol, Alg. 2 */
   DCG3D_OP_REDUCED = 4,   /* out = E in, E = Z^T A* Z (scalar), Corollary 1                   */
-  DCG3D_OP_INNER = 5,     /* out = E^{-1} in by the inner solver to relative residual tol     */
+  DCG3D_OP_INNER = 5,     /* out = E^{-1} in by the inner solver (PCG: to relative residual tol) */
   DCG3D_OP_ADIVZ = 6      /* out = A_div Z in       (scalar -> tensor), Corollary 1 (proof)   */
 } dcg3d_op;
 
 /* Assembles the operators on the host and uploads them (2 <= n <= 64,
- * penalty > 0, dt > 0, nu = mu > 0).  opt may be NULL (defaults of
+ * penalty > 0, dt > 0, nu = mu > 0, inner a dcg3d_inner).  opt may be NULL (defaults of
  * dcg_defaults with prec = DCG_FP64 and max_inner = DCG3D_DEFAULT_MAX_INNER);
  * the 3D solver takes prec = DCG_FP64, outer = DCG_OUTER_CG, c_A = 0 and
  * x0_given = 0 and rejects other values with DCG_EINVAL. */
-dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, const dcg_options* opt,
-                       dcg3d_handle* out);
+dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, int32_t inner,
+                       const dcg_options* opt, dcg3d_handle* out);
 /* Solves A* x = b to ||r|| <= tol ||b|| (the recurrence residual of the
  * deflated system, Section 4.1); st (may be NULL) receives the counts and the
  * true residual of the reconstructed x. */
@@ -344,8 +355,9 @@ dcg_status dcg3d_solve(dcg3d_handle h, const double* b, double* x, double tol, d
 dcg_status dcg3d_apply(dcg3d_handle h, dcg3d_op op, const double* in, double* out, double tol);
 dcg_status dcg3d_destroy(dcg3d_handle h);
 const char* dcg3d_last_error(dcg3d_handle h);
-/* Measurement: while enabled, every launch of the inner solve's Laplacian
- * product (the dominant kernel of the 3D solve) is bracketed by HIP events on
+/* Measurement: while enabled, every launch of the dominant kernel of the 3D
+ * solve -- the A* product with the exact inner solve, the inner Laplacian
+ * product with block-Jacobi CG -- is bracketed by HIP events on
  * the legacy default stream; _read returns their summed duration and count
  * since the last enable / read and restarts the count. */
 dcg_status dcg3d_kernel_timing(dcg3d_handle h, int32_t enable);
@@ -360,7 +372,9 @@ dcg_status dcg3d_kernel_timing_read(dcg3d_handle h, double* total_ms, int64_t* l
  * neighbour does not exist; 1: B_11 + B_22 + B_33 in the same slots,
  * [7][n^3][8][8], entry (a, b) at (slot n^3 + e) 64 + 8 b + a; 2: the inverses
  * of the diagonal blocks of (dt/3)(B_11 + B_22 + B_33), [n^3][8][8], entry
- * (a, b) at 64 e + 8 b + a; 3: the element mass matrix of M_1, [8][8]. */
+ * (a, b) at 64 e + 8 b + a; 3: the element mass matrix of M_1, [8][8];
+ * 4: the fast-diagonalisation factors of the exact inner solve, V_x [2n][2n]
+ * row-major (column i = eigenvector i), lambda_x [2n], then V_y, lambda_y. */
 #define DCG3D_MAX_HOST_BLOCKS_N 16
 dcg_status dcg3d_host_blocks(int32_t n, double penalty, double dt, int32_t which, double* out);
 

@@ -18,20 +18,23 @@ __all__ = ["Solver", "Solver3D", "Server", "DCGError", "LIB_PATH"]
 
 class Solver3D:
     """The three-dimensional solver (dcg3d_setup / dcg3d_solve): deflated CG
-    for the d = 3 block structure on n^3 cubes, FP64, inner system solved by
-    block-Jacobi CG to c_F * tol.
+    for the d = 3 block structure on n^3 cubes, FP64; the inner system solved
+    exactly by fast diagonalisation (inner="exact") or by block-Jacobi CG to
+    c_F * tol (inner="cg").
 
     >>> s = Solver3D(n=16, dt=1e-3)
     >>> status, stats = s.solve(b, x, tol=1e-8)     # 72 n^3 cuda float64 tensors
     """
 
     def __init__(self, n, dt, nu=1.0, penalty=40.0, c_F=0.01, max_outer=50000,
-                 max_inner=DCG3D_DEFAULT_MAX_INNER):
+                 max_inner=DCG3D_DEFAULT_MAX_INNER, inner="exact"):
         _, opt = dcg_defaults()
         opt.prec, opt.outer, opt.c_A, opt.x0_given = DCG_FP64, DCG_OUTER_CG, 0.0, 0
         opt.c_F, opt.max_outer, opt.max_inner = c_F, max_outer, max_inner
         self.n, self.dt, self.nu, self.penalty, self.opt = n, dt, nu, penalty, opt
-        self.handle = dcg3d_setup(n, penalty, dt, nu, opt)
+        self.inner = inner
+        self.handle = dcg3d_setup(n, penalty, dt, nu, opt,
+                                  {"exact": DCG3D_INNER_FDM, "cg": DCG3D_INNER_PCG}[inner])
 
     def solve(self, b, x, tol=1e-8):
         return dcg3d_solve(self.handle, b, x, tol)

@@ -29,6 +29,7 @@ BATCH = 16   # vectors of the _BATCH operators and requests per serving batch
 (DCG3D_OP_ASTAR, DCG3D_OP_ZT, DCG3D_OP_Z, DCG3D_OP_DEFLATED, DCG3D_OP_REDUCED, DCG3D_OP_INNER,
  DCG3D_OP_ADIVZ) = range(7)
 DCG3D_MAX_N, DCG3D_DEFAULT_MAX_INNER, DCG3D_MAX_HOST_BLOCKS_N = 64, 20000, 16
+DCG3D_INNER_FDM, DCG3D_INNER_PCG = 0, 1
 
 
 class dcg_mesh(ctypes.Structure):
@@ -83,7 +84,7 @@ _SIGS = {
     "dcg_last_error": (ctypes.c_char_p, [_h]),
     "dcg_clear_cache": (None, []),
     "dcg3d_setup": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                   _P(dcg_options), _P(_h)]),
+                                   ctypes.c_int32, _P(dcg_options), _P(_h)]),
     "dcg3d_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.c_double, _P(dcg_stats)]),
     "dcg3d_apply": (ctypes.c_int, [_h, ctypes.c_int, _vp, _vp, ctypes.c_double]),
     "dcg3d_destroy": (ctypes.c_int, [_h]),
@@ -292,9 +293,9 @@ def _sync_torch_stream():
         cs.synchronize()
 
 
-def dcg3d_setup(n, penalty, dt, nu=1.0, opt=None):
+def dcg3d_setup(n, penalty, dt, nu=1.0, opt=None, inner=DCG3D_INNER_FDM):
     h = _h()
-    _check3(_lib.dcg3d_setup(n, penalty, dt, nu, ctypes.byref(opt) if opt is not None else None,
+    _check3(_lib.dcg3d_setup(n, penalty, dt, nu, inner, ctypes.byref(opt) if opt is not None else None,
                              ctypes.byref(h)))
     return h
 
@@ -328,7 +329,8 @@ def dcg3d_host_blocks(n, penalty, dt, which):
     """Host copy of the assembled 3D blocks (no device call): a flat float64 array."""
     import numpy as np
     ne = n ** 3
-    size = {0: 7 * ne * 576, 1: 7 * ne * 64, 2: ne * 64, 3: 64}[which]
+    N = 2 * n
+    size = {0: 7 * ne * 576, 1: 7 * ne * 64, 2: ne * 64, 3: 64, 4: 2 * (N * N + N)}[which]
     out = np.empty(size, dtype=np.float64)
     _check3(_lib.dcg3d_host_blocks(n, penalty, dt, which, out.ctypes.data_as(_P(ctypes.c_double))))
     return out

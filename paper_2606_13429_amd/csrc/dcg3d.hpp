@@ -69,6 +69,14 @@ hipError_t launch_pcg_start(int64_t ne, const double* Dinv, const double* s, dou
 hipError_t launch_pcg_step(int64_t ne, const double* Dinv, double* x, double* r, double* z,
                            double* p, const double* q, double* part, double* part2, int nblk_q,
                            PcgScalars* sc, hipStream_t st);
+// Exact inner solve out = scale V diag(1 / (lx_i + ly_j + ly_k)) V^T in by fast
+// diagonalisation (V = Vy (x) Vy (x) Vx on the tensor index (Iz, Iy, Ix);
+// the y and z axes share one factor), in six axis passes through the
+// scalar buffers t1, t2; Vd row-major [j][i] = (V_d)_{j i}, VdT its
+// transpose.  Needs 2 n <= 256.
+hipError_t launch_fdm_solve(int n, const double* Vx, const double* VxT, const double* Vy,
+                            const double* VyT, const double* lx, const double* ly, double scale,
+                            const double* in, double* out, double* t1, double* t2, hipStream_t st);
 // out[0] = sum_i x_i y_i (fixed summation order).
 hipError_t launch_dot(int64_t len, const double* x, const double* y, double* part, double* out,
                       hipStream_t st);

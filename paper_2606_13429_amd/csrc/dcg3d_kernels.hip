@@ -361,6 +361,52 @@ __global__ __launch_bounds__(kThreads) void k_fill(int64_t len, double v, double
   if (i < len) x[i] = v;
 }
 
+// Position of tensor index (Ix, Iy, Iz), I = 2 e_axis + i_axis, in the
+// element-major scalar layout 8 e + a or in the tensor layout (Iz N + Iy) N + Ix.
+template <bool ELEM>
+__device__ __forceinline__ int64_t fdm_pos(int n, int Ix, int Iy, int Iz) {
+  const int N = 2 * n;
+  if (ELEM) {
+    const int64_t e = ((int64_t)(Iz >> 1) * n + (Iy >> 1)) * n + (Ix >> 1);
+    return 8 * e + (Ix & 1) + 2 * (Iy & 1) + 4 * (Iz & 1);
+  }
+  return ((int64_t)Iz * N + Iy) * N + Ix;
+}
+
+// One pass of the fast diagonalisation: out_i = sum_j A[j N + i] in_j along
+// one axis of the (2n)^3 tensor, optionally scaled by
+// scale / (lx[Ix] + ly[Iy] + ly[Iz]).  One workgroup takes 256 / N lines of N
+// values, staged in LDS; thread (line, i) forms output i of its line.
+template <bool IN_ELEM, bool OUT_ELEM>
+__global__ __launch_bounds__(kThreads) void k_fdm_axis(int n, int axis, const double* __restrict__ A,
+                                                       const double* __restrict__ in,
+                                                       double* __restrict__ out,
+                                                       const double* __restrict__ lx,
+                                                       const double* __restrict__ ly, double scale) {
+  __shared__ double line[kThreads];
+  const int N = 2 * n;
+  const int lpw = kThreads / N;
+  const int ll = threadIdx.x / N, i = threadIdx.x % N;
+  const int64_t g = (int64_t)blockIdx.x * lpw + ll;
+  const bool live = ll < lpw && g < (int64_t)N * N;
+  int I[3] = {0, 0, 0};
+  if (live) {
+    const int o1 = int(g % N), o2 = int(g / N);
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    I[a1] = o1;
+    I[a2] = o2;
+    I[axis] = i;
+    line[threadIdx.x] = in[fdm_pos<IN_ELEM>(n, I[0], I[1], I[2])];
+  }
+  __syncthreads();
+  if (!live) return;
+  const double* lv = line + ll * N;
+  double acc = 0.0;
+  for (int j = 0; j < N; ++j) acc += A[j * N + i] * lv[j];
+  if (lx) acc *= scale / (lx[I[0]] + ly[I[1]] + ly[I[2]]);
+  out[fdm_pos<OUT_ELEM>(n, I[0], I[1], I[2])] = acc;
+}
+
 int blocks_for(int64_t len) { return int((len + kThreads - 1) / kThreads); }
 
 const double kInvSqrt3 = 1.0 / std::sqrt(3.0);
@@ -420,6 +466,22 @@ hipError_t launch_pcg_step(int64_t ne, const double* Dinv, double* x, double* r,
   k_pcg_update<<<g, kThreads, 0, st>>>(ne, Dinv, x, r, z, p, q, part2, sc);
   k_pcg_beta<<<1, kThreads, 0, st>>>(part2, g, sc);
   k_pcg_dir<<<g, kThreads, 0, st>>>(ne * kNb, z, p, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_fdm_solve(int n, const double* Vx, const double* VxT, const double* Vy,
+                            const double* VyT, const double* lx, const double* ly, double scale,
+                            const double* in, double* out, double* t1, double* t2, hipStream_t st) {
+  const int N = 2 * n;
+  if (N > kThreads) return hipErrorInvalidValue;
+  const int lpw = kThreads / N;
+  const int grid = int(((int64_t)N * N + lpw - 1) / lpw);
+  k_fdm_axis<true, false><<<grid, kThreads, 0, st>>>(n, 0, Vx, in, t1, nullptr, nullptr, 0.0);
+  k_fdm_axis<false, false><<<grid, kThreads, 0, st>>>(n, 1, Vy, t1, t2, nullptr, nullptr, 0.0);
+  k_fdm_axis<false, false><<<grid, kThreads, 0, st>>>(n, 2, Vy, t2, t1, lx, ly, scale);
+  k_fdm_axis<false, false><<<grid, kThreads, 0, st>>>(n, 2, VyT, t1, t2, nullptr, nullptr, 0.0);
+  k_fdm_axis<false, false><<<grid, kThreads, 0, st>>>(n, 1, VyT, t2, t1, nullptr, nullptr, 0.0);
+  k_fdm_axis<false, true><<<grid, kThreads, 0, st>>>(n, 0, VxT, t1, out, nullptr, nullptr, 0.0);
   return hipGetLastError();
 }
 

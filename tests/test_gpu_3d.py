@@ -43,12 +43,12 @@ def _close(got, ref, rel=1e-12):
     assert err <= rel, "max rel error %.3e" % err
 
 
-@pytest.mark.parametrize("n", [2, 3, 5])
-def test_operators_match_oracle(n):
+@pytest.mark.parametrize("n,inner", [(2, "exact"), (3, "exact"), (5, "exact"), (3, "cg"), (5, "cg")])
+def test_operators_match_oracle(n, inner):
     dt = 3e-3
-    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner=inner)
     m = 8 * n ** 3
-    print("3d operators n=%d" % n, flush=True)
+    print("3d operators n=%d inner=%s" % (n, inner), flush=True)
     rng = np.random.default_rng(n)
     x = rng.standard_normal(9 * m)                  # element-major tensor
     y = rng.standard_normal(m)                      # scalar
@@ -71,10 +71,10 @@ def test_operators_match_oracle(n):
     E = (V.T @ As @ V).tocsc()
     s.apply(lib.DCG3D_OP_REDUCED, _dev(y), out_s)
     _close(_host(out_s), E @ y)
-    # inner solve to a relative residual of 1e-12
+    # inner solve: exact (fast diagonalisation) or CG to a relative residual of 1e-12
     s.apply(lib.DCG3D_OP_INNER, _dev(y), out_s, 1e-12)
     z = _host(out_s)
-    assert np.linalg.norm(E @ z - y) <= 1.5e-12 * np.linalg.norm(y)
+    assert np.linalg.norm(E @ z - y) <= (1e-11 if inner == "exact" else 1.5e-12) * np.linalg.norm(y)
     _close(z, spla.spsolve(E, y), rel=1e-8)
     # deflated operator M_D x = A* (x - pi(A* x))
     s.apply(lib.DCG3D_OP_DEFLATED, _dev(x), out_t, 1e-13)
@@ -99,12 +99,14 @@ def _oracle(n, dt, seed, tol):
     return _ORACLE[key]
 
 
-@pytest.mark.parametrize("n,dt", [(3, 1e-1), (4, 1e-3), (4, 1e-5), (5, 1e-2)])
-def test_solve_matches_oracle(n, dt):
+@pytest.mark.parametrize("n,dt,inner", [(3, 1e-1, "exact"), (4, 1e-3, "exact"), (4, 1e-5, "exact"),
+                                        (5, 1e-2, "exact"), (3, 1e-1, "cg"), (4, 1e-3, "cg"),
+                                        (4, 1e-5, "cg"), (5, 1e-2, "cg")])
+def test_solve_matches_oracle(n, dt, inner):
     tol = 1e-10
     res, x_direct = _oracle(n, dt, 11, tol)
-    print("3d solve n=%d dt=%g" % (n, dt), flush=True)
-    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, c_F=1e-2)
+    print("3d solve n=%d dt=%g inner=%s" % (n, dt, inner), flush=True)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, c_F=1e-2, inner=inner)
     b = _dev(rhs3d(n, 11))
     x = torch.empty_like(b)
     status, st = s.solve(b, x, tol)
@@ -120,6 +122,7 @@ def test_solve_matches_oracle(n, dt):
     assert st.rel_res_recurrence <= tol
     assert st.rel_res_true <= 10 * tol
     assert st.inner_solves == st.outer_iters + 2
+    assert (st.total_wcycles == 0) == (inner == "exact")
 
 
 def test_zero_rhs_and_argument_errors():
@@ -141,6 +144,13 @@ def test_zero_rhs_and_argument_errors():
     opt.prec = lib.DCG_MIXED
     with pytest.raises(lib.DCGError):
         lib.dcg3d_setup(4, PEN, 1e-3, 1.0, opt)
+    with pytest.raises(lib.DCGError):
+        lib.dcg3d_setup(4, PEN, 1e-3, 1.0, None, inner=7)
+    s = dcg.Solver3D(2, 1e-3)
+    b = torch.full((72 * 8,), float("nan"), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.DCGError):
+        s.solve(b, torch.empty_like(b), 1e-8)
+    s.close()
 
 
 def test_full_size_identities_and_solve():
@@ -171,4 +181,5 @@ def test_full_size_identities_and_solve():
     assert status == lib.DCG_OK and st.rel_res_true <= 10 * tol
     status, st2 = s.solve(b, x2, tol)
     assert torch.equal(x1, x2) and st2.outer_iters == st.outer_iters
+    assert st.total_wcycles == 0 and st.inner_solves == st.outer_iters + 2
     s.close()
