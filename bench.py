@@ -390,6 +390,30 @@ def three_d(args):
     s.close()
 
 
+def three_d_sweep(args):
+    """The 3D analogue of Table 5 (left): deflated-CG outer iterations with the
+    exact inner solve against dt on three nested meshes (n = 8, 16, 32 cubes
+    per side), tol = 1e-8, one seeded right-hand side per mesh."""
+    import torch
+    import paper_2606_13429_amd as dcg
+    from dcg_workloads import THREE_D, rhs3d
+    torch.cuda.set_device(0)
+    rows = []
+    for n in (8, 16, 32):
+        b = torch.from_numpy(rhs3d(n, 0)).cuda()
+        x = torch.empty_like(b)
+        for dt in (1.0, 0.5, 0.1, 1e-2, 1e-3, 1e-4, 1e-5):
+            s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], max_outer=args.sweep_max_outer)
+            status, st = s.solve(b, x, THREE_D["tol"])
+            s.close()
+            rows.append({"n": n, "dt": dt, "status": status, "outer": st.outer_iters,
+                         "rel_res_true": st.rel_res_true, "ms": round(st.t_solve_ms, 1)})
+            log("3d sweep n=%d dt=%g: status=%d outer=%d res=%.2e %.1f ms"
+                % (n, dt, status, st.outer_iters, st.rel_res_true, st.t_solve_ms))
+    print(json.dumps({"metric": "3D dCG outer iterations vs dt (exact inner solve), n = 8, 16, 32",
+                      "unit": "iterations", "tol": THREE_D["tol"], "rows": rows}), flush=True)
+
+
 def variants(args):
     """The inner-tolerance rule and outer variant at the headline size: the
     fixed rule (eq. (fixed_tol), c_F = 0.01) against the adaptive rule
@@ -462,6 +486,8 @@ def main():
                     help="run the 3D solver at --n3 cubes per side")
     ap.add_argument("--n3", type=int, default=32)
     ap.add_argument("--3d-inner", dest="inner3", choices=("exact", "cg"), default="exact")
+    ap.add_argument("--3d-sweep", dest="three_d_sweep", action="store_true",
+                    help="outer iterations of the 3D solver against dt at n = 8, 16, 32")
     ap.add_argument("--variants", action="store_true",
                     help="compare the fixed and adaptive inner tolerance at --n/--dt")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -491,6 +517,9 @@ def main():
         return
     if args.three_d:
         three_d(args)
+        return
+    if args.three_d_sweep:
+        three_d_sweep(args)
         return
 
     import numpy as np

@@ -153,6 +153,23 @@ def test_zero_rhs_and_argument_errors():
     s.close()
 
 
+def test_outer_counts_fall_with_dt_and_grow_with_n():
+    # the trend of Table 5 (left) for deflated CG with an exact inner solve
+    counts = {}
+    for n in (4, 8):
+        b = _dev(rhs3d(n, 2))
+        for dt in (1e-1, 1e-3, 1e-5):
+            s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN)
+            status, st = s.solve(b, torch.empty_like(b), 1e-8)
+            s.close()
+            assert status == lib.DCG_OK and st.rel_res_true <= 1e-7
+            counts[(n, dt)] = st.outer_iters
+    for n in (4, 8):
+        assert counts[(n, 1e-5)] < counts[(n, 1e-3)] < counts[(n, 1e-1)]
+    for dt in (1e-1, 1e-3, 1e-5):
+        assert counts[(4, dt)] < counts[(8, dt)]
+
+
 def test_full_size_identities_and_solve():
     n, dt, tol = THREE_D["n"], THREE_D["dt"], THREE_D["tol"]
     print("3d full size n=%d" % n, flush=True)
