@@ -50,6 +50,33 @@ TRAFFIC = {"source_digest": "05773af7893e3209", "n": 512,
            "fetch_kib": 357599.6, "fetch_scale": 2.0, "write_kib": 16498.1, "write_scale": 1.0}
 
 
+# The same counters for the 3D A* product k_astar3 at n = 32 (exact inner solve;
+# profiles/solve3d_n32_fp64.md), valid while dcg3d_kernels.hip is unchanged.
+TRAFFIC3 = {"source_digest": "ca3ce7c62147d607", "n": 32,
+            "fetch_kib": 525986.3, "fetch_scale": 2.0, "write_kib": 18456.7, "write_scale": 1.0}
+
+
+def source_digest(*names):
+    import hashlib
+    h = hashlib.sha256()
+    for f in names:
+        with open(os.path.join(ROOT, "paper_2606_13429_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic3(n):
+    """HBM bytes per k_astar3 launch from the counters, or None when they do not
+    apply (other n, or the kernel source changed since they were taken)."""
+    try:
+        if n != TRAFFIC3["n"] or source_digest("dcg3d_kernels.hip") != TRAFFIC3["source_digest"]:
+            return None
+    except OSError:
+        return None
+    return int(1024 * (TRAFFIC3["fetch_kib"] * TRAFFIC3["fetch_scale"]
+                       + TRAFFIC3["write_kib"] * TRAFFIC3["write_scale"]))
+
+
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -383,7 +410,8 @@ def three_d(args):
                    % (n, dt, THREE_D["nu"], THREE_D["penalty"], tol)},
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic3(n) if exact else None,
                      "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n,
                      "bytes_per_launch": nbytes},
         "rows": rows}), flush=True)
