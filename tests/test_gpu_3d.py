@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
+from conftest import read_golden_matrix
 from dcg_workloads import THREE_D, rhs3d
 from layout import comp_to_elem3, elem_to_comp3
 from oracle import discretisation3d as d3
@@ -200,3 +201,63 @@ def test_full_size_identities_and_solve():
     assert torch.equal(x1, x2) and st2.outer_iters == st.outer_iters
     assert st.total_wcycles == 0 and st.inner_solves == st.outer_iters + 2
     s.close()
+
+
+def _oracle_rows(n, dt, x_elem, cubes):
+    """(A* x) on the rows of the given cubes, formed from the oracle's element
+    and face matrices one cube at a time (the full oracle assembly at the
+    benchmark size would take minutes)."""
+    h = 1.0 / n
+    gamma = PEN / h
+    me = d3.element_mass(h)
+    vol = d3.element_grad_grad(h)
+    face_in = [d3.face_matrices(ax, True, h, gamma) for ax in range(3)]
+    face_out = d3.face_matrices(0, False, h, gamma)
+    C = read_golden_matrix("dev_coefficients_3d.txt") / NU
+    X = np.asarray(x_elem).reshape(n ** 3, 9, 8)
+    out = {}
+    for (ex, ey, ez) in cubes:
+        e = d3.element_index(n, ex, ey, ez)
+        y = np.zeros((9, 8))
+        for c in range(9):                              # mass term
+            for c2 in range(9):
+                if C[c, c2]:
+                    y[c] += C[c, c2] * (me @ X[e, c2])
+        blocks = [(e, vol)]                             # (trial element, B[i][j] blocks)
+        c3 = (ex, ey, ez)
+        for ax in range(3):
+            up = list(c3); up[ax] += 1
+            dn = list(c3); dn[ax] -= 1
+            if c3[ax] + 1 < n:                          # e is the lower side of the face
+                blocks.append((e, face_in[ax][:, :, :8, :8]))
+                blocks.append((d3.element_index(n, *up), face_in[ax][:, :, :8, 8:]))
+            if c3[ax] > 0:                              # e is the upper side
+                blocks.append((e, face_in[ax][:, :, 8:, 8:]))
+                blocks.append((d3.element_index(n, *dn), face_in[ax][:, :, 8:, :8]))
+        if ex == n - 1:
+            blocks.append((e, face_out))
+        for f, B in blocks:
+            for k in range(3):
+                for j in range(3):
+                    for i in range(3):
+                        y[3 * k + j] += dt * (B[i, j] @ X[f, 3 * k + i])
+        out[(ex, ey, ez)] = y.reshape(-1)
+    return out
+
+
+def test_full_size_astar_sampled_against_oracle():
+    n, dt = THREE_D["n"], THREE_D["dt"]
+    print("3d sampled A* n=%d" % n, flush=True)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN)
+    x = np.random.default_rng(7).standard_normal(72 * n ** 3)
+    y = torch.empty(72 * n ** 3, dtype=torch.float64, device="cuda")
+    s.apply(lib.DCG3D_OP_ASTAR, _dev(x), y)
+    yg = _host(y).reshape(n ** 3, 72)
+    s.close()
+    cubes = [(0, 0, 0), (n - 1, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 5), (7, 0, n - 1), (n // 2, n // 2, n // 2),
+             (13, 21, 3), (n - 1, 17, 9), (1, 30, 30), (31, 0, 16)]
+    ref = _oracle_rows(n, dt, x, cubes)
+    scale = max(np.abs(v).max() for v in ref.values())
+    for c, v in ref.items():
+        e = d3.element_index(n, *c)
+        assert np.abs(yg[e] - v).max() <= 1e-12 * scale, c
