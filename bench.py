@@ -33,6 +33,37 @@ HBM_PEAK_GBS = 8000.0
 # iterate + pending (4 + 12) s / 4.  The four finest steps of a W-cycle are
 # one zero-start step (no L, no z), two steps with a pending update and one
 # with the prolongation; the model averages them.
+def astar_bytes(n):
+    """Algorithmic HBM bytes of one k_astar launch with the fused direction
+    update (2D): the 8 x 8 FP64 row blocks C of A_div that exist (the square and
+    its edge neighbours, 512 B each), the element mass M_1 (128 B per square),
+    r and p read, p and w written (4 x 128 B) and s = Z^T w (32 B) per square."""
+    ne = n * n
+    nblocks = ne + 4 * n * (n - 1)
+    return 512 * nblocks + (128 + 4 * 128 + 32) * ne
+
+
+def copy_gbs(nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device-to-device copy (read + write bytes / time),
+    the practical ceiling next to the vendor peak."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def sweep_bytes_per_square(s):
     base = 576 * s + 4 * s + 8 * s + s
     zero = base
@@ -585,6 +616,7 @@ def main():
     t_wall = time.time() - t_wall
     ms_total = ev0.elapsed_time(ev1)
     k_ms, k_launches = lib.dcg_kernel_timing_read(solver.handle)
+    a_ms, a_launches = lib.dcg_kernel_timing_read_astar(solver.handle)
     lib.dcg_kernel_timing(solver.handle, False)
     ms_per_step = ms_total / args.steps
     value = 1000.0 / ms_per_step
@@ -599,6 +631,17 @@ def main():
                 "bytes_per_launch": tiles_bytes}
     if roofline["traffic"]:
         roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / tiles_bytes, 3)
+    cgbs = copy_gbs()
+    roofline["copy_gbs"] = round(cgbs, 1)
+    roofline["frac_of_copy"] = round(achieved / cgbs, 4)
+    a_bytes = astar_bytes(n)
+    a_avg_ms = a_ms / max(a_launches, 1)
+    a_gbs = a_bytes / (a_avg_ms * 1e-3) / 1e9
+    roofline_astar = {"bound": "hbm", "kernel": "k_astar (A* product with the direction update)",
+                      "achieved": round(a_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(a_gbs / HBM_PEAK_GBS, 4), "frac_of_copy": round(a_gbs / cgbs, 4),
+                      "avg_launch_us": round(a_avg_ms * 1e3, 2), "launches": a_launches,
+                      "bytes_per_launch": a_bytes}
 
     outer = int(np.mean([s["outer_iters"] for s in stats]))
     result = {
@@ -617,6 +660,7 @@ def main():
                         "rel_res_true": max(s["rel_res_true"] for s in stats),
                         "setup_ms": round(stats[0]["t_setup_ms"], 1)},
         "roofline": roofline,
+        "roofline_astar": roofline_astar,
     }
 
     if not args.skip_fp64:

@@ -224,6 +224,10 @@ dcg_status dcg_bdf2_rhs(dcg_handle h, const double* s1, const double* s2, const 
  * accumulated milliseconds and launch count since the last enable. */
 dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable);
 dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launches);
+/* The same for the A* product with the fused direction update of the CG outer
+ * loop (eq. (pb_study), Section 3.1): summed duration and count of its launches since
+ * dcg_kernel_timing enabled the timing (CG and FCG(1) outer variants). */
+dcg_status dcg_kernel_timing_read_astar(dcg_handle h, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------- serving
  * A server solves many requests A*_i x_i = b_i concurrently on the current

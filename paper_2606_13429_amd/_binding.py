@@ -71,6 +71,7 @@ _SIGS = {
     "dcg_bdf2_rhs": (ctypes.c_int, [_h, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "dcg_kernel_timing": (ctypes.c_int, [_h, ctypes.c_int32]),
     "dcg_kernel_timing_read": (ctypes.c_int, [_h, _P(ctypes.c_double), _P(ctypes.c_int64)]),
+    "dcg_kernel_timing_read_astar": (ctypes.c_int, [_h, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "dcg_server_create": (ctypes.c_int, [_P(dcg_options), _P(_h)]),
     "dcg_server_prepare": (ctypes.c_int, [_h, _P(dcg_mesh)]),
     "dcg_submit": (ctypes.c_int, [_h, _P(dcg_mesh), ctypes.c_double, ctypes.c_double, _vp, _vp,
@@ -344,4 +345,11 @@ def dcg3d_kernel_timing_read(handle):
     """Returns (total ms, launches) of the timed Laplacian launches."""
     ms, k = ctypes.c_double(), ctypes.c_int64()
     _check3(_lib.dcg3d_kernel_timing_read(handle, ctypes.byref(ms), ctypes.byref(k)), handle)
+    return ms.value, k.value
+
+
+def dcg_kernel_timing_read_astar(handle):
+    """Returns (total ms, launches) of the timed A* launches of the CG outer loop."""
+    ms, k = ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.dcg_kernel_timing_read_astar(handle, ctypes.byref(ms), ctypes.byref(k)), handle)
     return ms.value, k.value

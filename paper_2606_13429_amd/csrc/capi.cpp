@@ -223,6 +223,13 @@ dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launc
   return DCG_OK;
 }
 
+dcg_status dcg_kernel_timing_read_astar(dcg_handle h, double* total_ms, int64_t* launches) {
+  if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  if (total_ms) *total_ms = h->atime_ms;
+  if (launches) *launches = h->alaunches;
+  return DCG_OK;
+}
+
 dcg_status dcg_server_create(const dcg_options* opt, dcg_server* out) {
   if (!out) return fail(nullptr, DCG_EINVAL, "out must not be NULL");
   *out = nullptr;

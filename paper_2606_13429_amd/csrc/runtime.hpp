@@ -143,6 +143,10 @@ struct dcg_ctx {
   int krec = 0;                 // event pairs recorded by the current cycle
   double ktime_ms = 0.0;
   int64_t klaunches = 0;
+  // and of the A* product with the direction update in the CG outer loop
+  hipEvent_t aev[2] = {};
+  double atime_ms = 0.0;
+  int64_t alaunches = 0;
   ~dcg_ctx();
 };
 

@@ -82,6 +82,8 @@ dcg_ctx::~dcg_ctx() {
   if (wgraph) (void)hipGraphExecDestroy(wgraph);
   for (hipEvent_t& e : kev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t& e : aev)
+    if (e) (void)hipEventDestroy(e);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   ws.release();
   (void)hipSetDevice(cur);
@@ -517,9 +519,12 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
         break;
       }
       // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
+      const bool atimed = h->ktime;
+      if (atimed) DCG_HIP(hipEventRecord(h->aev[0], stream));
       DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Cdiv, m.cols, m.M1, ne,
                            ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
                            stream));
+      if (atimed) DCG_HIP(hipEventRecord(h->aev[1], stream));
       pidx = 1 - pidx;
       const int c = inner(h, ws.s, ws.zref, tol_outer(rho), stream);
       cycles_total += c;
@@ -535,6 +540,12 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
       DCG_HIP(launch_reduce(ws.part, nbu, flex ? kRedFcgBeta : kRedBeta, ws.sc, stream));
       ++it;
       read_scalars(h, stream);
+      if (atimed) {   // both events have completed: read_scalars synchronised the stream
+        float ms = 0.0f;
+        DCG_HIP(hipEventElapsedTime(&ms, h->aev[0], h->aev[1]));
+        h->atime_ms += ms;
+        ++h->alaunches;
+      }
       if (ws.sc_host->breakdown) {
         status = DCG_EBREAKDOWN;
         break;
@@ -575,6 +586,10 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
 void kernel_timing(dcg_ctx* h, bool enable) {
   if (enable && !h->kev[0])
     for (hipEvent_t& e : h->kev) DCG_HIP(hipEventCreate(&e));
+  if (enable && !h->aev[0])
+    for (hipEvent_t& e : h->aev) DCG_HIP(hipEventCreate(&e));
+  h->atime_ms = 0.0;
+  h->alaunches = 0;
   if (h->wgraph) {
     DCG_HIP(hipGraphExecDestroy(h->wgraph));
     h->wgraph = nullptr;
