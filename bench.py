@@ -696,6 +696,23 @@ def main():
                                         "rel_res_true": sta.rel_res_true,
                                         "speedup_vs_fixed_rule": round(1.0 / (value * ta), 3)}
         sa.close()
+        # the exact inner solve (fast diagonalisation; the exact-inner deflated CG
+        # of Tables 1-2) on the same right-hand side, for reference
+        log("exact inner solve: setup + one solve")
+        t0 = time.time()
+        se = dcg.Solver(n, dt, prec="fp64", inner="exact", max_outer=args.max_outer)
+        te_setup = time.time() - t0
+        se.solve(bs[0], x, tol)                       # warm-up
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, ste = se.solve(bs[0], x, tol)
+        torch.cuda.synchronize()
+        te = time.time() - t0
+        result["exact_inner"] = {"solves_per_s": round(1.0 / te, 4), "outer_iters": ste.outer_iters,
+                                 "rel_res_true": ste.rel_res_true, "setup_s": round(te_setup, 1),
+                                 "ms_per_outer_iteration": round(1e3 * te / max(ste.outer_iters, 1), 3),
+                                 "speedup_vs_multigrid_inner": round(1.0 / (value * te), 2)}
+        se.close()
 
     if not args.skip_cpu:
         log("CPU oracle baseline (setup is not counted)")

@@ -103,7 +103,20 @@ typedef struct {
                           of outer iteration i and c_A tol for the prologue
                           and epilogue solves, instead of c_F tol [0 = off]   */
   int32_t m_max;       /* DCG_OUTER_FCG truncation, 0 = FCG(inf) [8]         */
+  int32_t inner;       /* dcg_inner: the inner solver [DCG_INNER_MG]           */
 } dcg_options;
+
+/* Inner solver of dcg_solve.  DCG_INNER_MG is the paper's method: the
+ * Multigrid iteration (Algorithm 3) of W-cycles with the RAS smoother to the
+ * inner tolerance.  DCG_INNER_EXACT solves the inner system exactly (the
+ * exact-inner deflated CG of Tables 1-2): on this uniform grid the SIPG
+ * Laplacian of Corollary 1 is L = M (x) K + K (x) M on the (y, x) grid of
+ * dofs with one-dimensional DG-P1 matrices M (mass) and K (SIPG, traction node
+ * at the left end, identical along x and y), so L^{-1} = V' diag(1/(l_i + l_k))
+ * V'^T with V' = V (x) V from the generalised eigenvectors K V = M V diag(l)
+ * (fast diagonalisation: four dense 2n x 2n FP64 products per inner solve).
+ * dcg_solve only, n <= 1024; stats count 0 W-cycles. */
+typedef enum { DCG_INNER_MG = 0, DCG_INNER_EXACT = 1 } dcg_inner;
 
 typedef struct {
   int32_t status;          /* dcg_status of the solve                         */

@@ -1,10 +1,12 @@
 // extern "C" entry points of include/dcg.h: argument checks, handle
 // management and conversion of library errors into dcg_status codes.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
 
+#include "fdm_host.hpp"
 #include "server.hpp"
 
 namespace {
@@ -53,6 +55,8 @@ dcg_status check_options(const dcg_options& o) {
     return fail(nullptr, DCG_EINVAL, "bad outer variant");
   if (!(o.c_A >= 0.0) || !std::isfinite(o.c_A)) return fail(nullptr, DCG_EINVAL, "c_A must be >= 0");
   if (o.m_max < 0) return fail(nullptr, DCG_EINVAL, "m_max must be >= 0");
+  if (o.inner != DCG_INNER_MG && o.inner != DCG_INNER_EXACT)
+    return fail(nullptr, DCG_EINVAL, "inner must be DCG_INNER_MG or DCG_INNER_EXACT");
   if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
     return fail(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
   return DCG_OK;
@@ -99,6 +103,8 @@ dcg_status dcg_setup(const dcg_mesh* mesh, double dt, double nu, const dcg_optio
   dcg_defaults(nullptr, &o);
   if (opt) o = *opt;
   if (const dcg_status cs = check_options(o); cs != DCG_OK) return cs;
+  if (o.inner == DCG_INNER_EXACT && mesh->n > 1024)
+    return fail(nullptr, DCG_EINVAL, "DCG_INNER_EXACT needs n <= 1024");
   dcg_ctx* h = nullptr;
   const dcg_status st = guarded(nullptr, [&]() {
     const auto t0 = std::chrono::steady_clock::now();
@@ -144,7 +150,21 @@ dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
   if (!mesh) return fail(nullptr, DCG_EINVAL, "mesh must not be NULL");
   std::string why;
   if (!valid_mesh(*mesh, why)) return fail(nullptr, DCG_EINVAL, why);
-  if (which < 0 || which > 5) return fail(nullptr, DCG_EINVAL, "which must be in [0, 5]");
+  if (which < 0 || which > 6) return fail(nullptr, DCG_EINVAL, "which must be in [0, 6]");
+  if (which == 6) {   // fast-diagonalisation factors of the exact inner solve: V then lambda
+    if (mesh->n > 256) return fail(nullptr, DCG_EINVAL, "which = 6 needs n <= 256");
+    return guarded(nullptr, [&]() -> dcg_status {
+      const dcg::FdmAxis f = dcg::fdm_axis_factor(mesh->n, mesh->penalty * mesh->n, true);
+      const int64_t need = int64_t(f.N) * f.N + f.N;
+      if (needed) *needed = need;
+      if (dst) {
+        if (dst_len < need) return fail(nullptr, DCG_EINVAL, "dst too small");
+        std::copy(f.V.begin(), f.V.end(), dst);
+        std::copy(f.lam.begin(), f.lam.end(), dst + int64_t(f.N) * f.N);
+      }
+      return DCG_OK;
+    });
+  }
   return guarded(nullptr, [&]() -> dcg_status {
     const int J = dcg::num_levels(mesh->n);
     if ((which == 3 || which == 4) && (level < 1 || level > J))
@@ -240,6 +260,7 @@ dcg_status dcg_server_create(const dcg_options* opt, dcg_server* out) {
   if (o.max_pending < 1) return fail(nullptr, DCG_EINVAL, "max_pending must be >= 1");
   if (o.outer == DCG_OUTER_FCG || o.outer == DCG_OUTER_GMRES)
     return fail(nullptr, DCG_EINVAL, "the server runs DCG_OUTER_CG or DCG_OUTER_FCG1");
+  if (o.inner != DCG_INNER_MG) return fail(nullptr, DCG_EINVAL, "the server runs DCG_INNER_MG");
   if (o.hbm_budget_bytes < 0) return fail(nullptr, DCG_EINVAL, "hbm_budget_bytes must be >= 0");
   return guarded(nullptr, [&]() {
     auto s = std::make_unique<dcg_srv>();

@@ -1,0 +1,25 @@
+// Host set-up of the exact inner solve by fast diagonalisation on the uniform
+// grid (the 2D path): one-dimensional DG-P1 matrices along an axis and their
+// generalised eigen-decomposition K V = M V diag(lambda), V^T M V = I.
+#pragma once
+#include <vector>
+
+namespace dcg {
+
+struct FdmAxis {
+  int N = 0;                 // 2 n dofs along the axis (dof 2 c + i, i = 0 left node)
+  std::vector<double> V;     // [N][N] row-major, column j = eigenvector j
+  std::vector<double> lam;   // [N]
+};
+
+// K: the 1D SIPG matrix on n cells of side 1/n (volume term, interior-node
+// terms with penalty gamma, and the boundary-node term at the left end x = 0
+// when left_bc); M: the 1D DG-P1 mass matrix.  Both N x N row-major.
+void sipg_axis(int n, double gamma, bool left_bc, std::vector<double>& K, std::vector<double>& M);
+
+// K V = M V Lambda, V^T M V = I, for the matrices of sipg_axis (M block
+// diagonal with 2 x 2 blocks): Cholesky of M, Householder tridiagonalisation
+// of R^{-T} K R^{-1} and the implicit QL iteration.
+FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc);
+
+}  // namespace dcg

@@ -1,0 +1,113 @@
+// Device side of the exact inner solve by fast diagonalisation (2D path):
+// z = L^{-1} s = V' diag(1 / (lam_y + lam_x)) V'^T s with V' = V (x) V on the
+// tensor index (Iy, Ix), applied as four dense N x N products (N = 2 n):
+//   T1 = S V,  T2 = (V^T T1) ./ (lam_i + lam_k),  T3 = V T2,  Z = T3 V^T,
+// with S, Z the scalar vectors rearranged from the element-major layout
+// 4 e + j (e = ey n + ex, j = ix + 2 iy) to the row-major tensor (Iy, Ix),
+// Ix = 2 ex + ix.  The products are FP64 register-blocked GEMMs staged
+// through LDS (each thread forms a 4 x 4 block of C).
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace dcg {
+namespace {
+
+constexpr int kGT = 64;        // C tile per workgroup
+constexpr int kGK = 16;        // k step
+constexpr int kGThreads = 256;
+
+// C = A B (N x N row-major); with la: C[i][k] *= 1 / (la[i] + lb[k]).
+__global__ __launch_bounds__(kGThreads) void k_gemm64(int N, const double* __restrict__ A,
+                                                      const double* __restrict__ B, double* __restrict__ C,
+                                                      const double* __restrict__ la,
+                                                      const double* __restrict__ lb) {
+  __shared__ double As[kGK][kGT + 2];   // A tile transposed: As[k][row]
+  __shared__ double Bs[kGK][kGT + 2];
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const int row0 = blockIdx.y * kGT, col0 = blockIdx.x * kGT;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < N; k0 += kGK) {
+    for (int t = tid; t < kGT * kGK; t += kGThreads) {
+      const int r = t / kGK, kk = t % kGK;          // A: row r, column k0 + kk
+      const int gr = row0 + r, gk = k0 + kk;
+      As[kk][r] = (gr < N && gk < N) ? A[(int64_t)gr * N + gk] : 0.0;
+      const int kb = t / kGT, c = t % kGT;          // B: row k0 + kb, column c
+      const int gkb = k0 + kb, gc = col0 + c;
+      Bs[kb][c] = (gkb < N && gc < N) ? B[(int64_t)gkb * N + gc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kk][ty * 4 + q];
+        b[q] = Bs[kk][tx * 4 + q];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gr = row0 + ty * 4 + i;
+    if (gr >= N) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gc = col0 + tx * 4 + j;
+      if (gc >= N) continue;
+      double v = acc[i][j];
+      if (la) v *= 1.0 / (la[gr] + lb[gc]);
+      C[(int64_t)gr * N + gc] = v;
+    }
+  }
+}
+
+// to_tensor: T[(2 ey + iy) N + 2 ex + ix] = s[4 e + j]; otherwise the inverse.
+__global__ __launch_bounds__(kGThreads) void k_fdm_permute(int n, int to_tensor,
+                                                           const double* __restrict__ in,
+                                                           double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)kGThreads + threadIdx.x;
+  const int64_t total = 4 * (int64_t)n * n;
+  if (i >= total) return;
+  const int N = 2 * n;
+  const int64_t e = i >> 2;
+  const int j = int(i & 3);
+  const int ex = int(e % n), ey = int(e / n);
+  const int64_t t = (int64_t)(2 * ey + (j >> 1)) * N + 2 * ex + (j & 1);
+  if (to_tensor) out[t] = in[i];
+  else out[i] = in[t];
+}
+
+hipError_t gemm(int N, const double* A, const double* B, double* C, const double* la,
+                const double* lb, hipStream_t st) {
+  const dim3 grid((N + kGT - 1) / kGT, (N + kGT - 1) / kGT);
+  k_gemm64<<<grid, kGThreads, 0, st>>>(N, A, B, C, la, lb);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fdm_solve2d(int n, const double* V, const double* VT, const double* lam,
+                              const double* s, double* z, double* t0, double* t1, double* t2,
+                              hipStream_t st) {
+  const int N = 2 * n;
+  const int64_t total = 4 * (int64_t)n * n;
+  const int pb = int((total + kGThreads - 1) / kGThreads);
+  k_fdm_permute<<<pb, kGThreads, 0, st>>>(n, 1, s, t0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = gemm(N, t0, V, t1, nullptr, nullptr, st)) != hipSuccess) return e;   // x: S V
+  if ((e = gemm(N, VT, t1, t2, lam, lam, st)) != hipSuccess) return e;          // y: V^T T1, scaled
+  if ((e = gemm(N, V, t2, t0, nullptr, nullptr, st)) != hipSuccess) return e;   // y: V T2
+  if ((e = gemm(N, t0, VT, t1, nullptr, nullptr, st)) != hipSuccess) return e;  // x: T3 V^T
+  k_fdm_permute<<<pb, kGThreads, 0, st>>>(n, 0, t1, z);
+  return hipGetLastError();
+}
+
+}  // namespace dcg

@@ -223,4 +223,13 @@ hipError_t launch_coarse_b(const double* inv, const T* f, T* z, hipStream_t st);
 template <typename T>
 hipError_t launch_resolve_b(int ne, bool has_z, const T* z, const T* Ye, T* out, hipStream_t st);
 
+// Exact inner solve on the uniform grid: z = L^{-1} s by fast
+// diagonalisation, L = M (x) K + K (x) M on the tensor index (Iy, Ix) of the
+// 2n x 2n grid of dofs, with K V = M V diag(lam), V^T M V = I (V, its
+// transpose VT, both 2n x 2n row-major); s, z scalar vectors 4 e + j; t0..t2
+// scratch of 4 n^2 doubles each.
+hipError_t launch_fdm_solve2d(int n, const double* V, const double* VT, const double* lam,
+                              const double* s, double* z, double* t0, double* t1, double* t2,
+                              hipStream_t st);
+
 }  // namespace dcg

@@ -147,6 +147,10 @@ struct dcg_ctx {
   hipEvent_t aev[2] = {};
   double atime_ms = 0.0;
   int64_t alaunches = 0;
+  // exact inner solve (DCG_INNER_EXACT): fast-diagonalisation factors and
+  // three scratch vectors, all in the workspace
+  bool exact = false;
+  double *fV = nullptr, *fVT = nullptr, *flam = nullptr, *ft[3] = {nullptr, nullptr, nullptr};
   ~dcg_ctx();
 };
 

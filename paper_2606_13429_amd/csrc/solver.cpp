@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "fdm_host.hpp"
 #include "wcycle.hpp"
 
 namespace dcg {
@@ -223,6 +224,10 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
 }
 
 int inner(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
+  if (h->exact) {   // z = L^{-1} s exactly (fast diagonalisation); no W-cycles
+    DCG_HIP(launch_fdm_solve2d(h->mesh->n, h->fV, h->fVT, h->flam, s, z, h->ft[0], h->ft[1], h->ft[2], st));
+    return 0;
+  }
   return h->fp32 ? inner_solve<float>(h, s, z, tol_c, st) : inner_solve<double>(h, s, z, tol_c, st);
 }
 
@@ -248,6 +253,21 @@ void handle_init(dcg_ctx* h) {
   DCG_HIP(hipMemcpy(ws.sc, ws.sc_host, sizeof(Scalars), hipMemcpyHostToDevice));
   ws.lvb.allocate(m, h->fp32, false, ws);
   DCG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+  if (h->opt.inner == DCG_INNER_EXACT) {
+    const FdmAxis f = fdm_axis_factor(m.n, h->mp.penalty * m.n, true);
+    const int64_t NN = int64_t(f.N) * f.N;
+    std::vector<double> vt(NN);
+    for (int i = 0; i < f.N; ++i)
+      for (int j = 0; j < f.N; ++j) vt[int64_t(j) * f.N + i] = f.V[int64_t(i) * f.N + j];
+    h->fV = static_cast<double*>(ws.alloc(sizeof(double) * NN));
+    h->fVT = static_cast<double*>(ws.alloc(sizeof(double) * NN));
+    h->flam = static_cast<double*>(ws.alloc(sizeof(double) * f.N));
+    for (double*& t : h->ft) t = static_cast<double*>(ws.alloc(sizeof(double) * M));
+    DCG_HIP(hipMemcpy(h->fV, f.V.data(), sizeof(double) * NN, hipMemcpyHostToDevice));
+    DCG_HIP(hipMemcpy(h->fVT, vt.data(), sizeof(double) * NN, hipMemcpyHostToDevice));
+    DCG_HIP(hipMemcpy(h->flam, f.lam.data(), sizeof(double) * f.N, hipMemcpyHostToDevice));
+    h->exact = true;
+  }
 }
 
 // ------------------------------------------------------------ stored directions

@@ -183,3 +183,44 @@ def test_outer_variants_and_adaptive_tolerance_match_oracle(outer, m_max, c_A, d
     assert err <= 1e-8
     assert abs(st.total_wcycles - ref.total_cycles) <= 0.02 * ref.total_cycles + 10
     assert st.rel_res_true <= max(1.5 * ref.rel_res_true, 2 * tol)
+
+
+# ---------------------------------------------------------------- exact inner solve
+@pytest.mark.parametrize("n,dt,prec", [(16, 1e-2, "fp64"), (32, 1e-3, "fp64"), (32, 1e-5, "mixed"),
+                                       (32, 1e-1, "fp64")])
+def test_exact_inner_solve_matches_oracle_exact_inner(n, dt, prec):
+    # DCG with the inner system solved exactly (fast diagonalisation) against the
+    # oracle's Algorithm 2 with a dense Cholesky inner solve: the same iteration
+    ref = _oracle(n, dt, 0, 1e-8, inner="exact")
+    print("exact inner n=%d dt=%g %s" % (n, dt, prec), flush=True)
+    status, st, x, s = _gpu(n, dt, 0, 1e-8, prec, inner="exact")
+    s.close()
+    assert status == lib.DCG_OK
+    assert abs(st.outer_iters - ref.iterations) <= max(2, 0.02 * ref.iterations), (st.outer_iters, ref.iterations)
+    xr = comp_to_elem(ref.x, n)
+    assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr)
+    assert st.total_wcycles == 0 and st.rel_res_true <= 2e-8
+
+
+def test_exact_inner_operator_and_rejections():
+    import scipy.sparse.linalg as spla
+    n, dt = 32, 1e-3
+    s = dcg.Solver(n, dt, prec="fp64", inner="exact")
+    E = (d.deflation_basis(n).T @ d.operator(n, dt) @ d.deflation_basis(n)).tocsc()
+    y = np.random.default_rng(4).standard_normal(4 * n * n)     # scalar dofs 4 e + j in both
+    out = torch.empty(4 * n * n, dtype=torch.float64, device="cuda")
+    s.apply(lib.DCG_OP_INNER, torch.from_numpy(y).cuda(), out)
+    torch.cuda.synchronize()
+    ref = spla.spsolve(E, y)                                     # E^{-1} = (2/dt) L^{-1}
+    got = out.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.linalg.norm(E @ got - y) <= 1e-10 * np.linalg.norm(y)
+    s.close()
+    m, opt = lib.dcg_defaults()
+    m.n, opt.inner = 2048, lib.DCG_INNER_EXACT
+    with pytest.raises(lib.DCGError):
+        lib.dcg_setup(m, 1e-3, 1.0, opt)
+    opt.inner = 7
+    m.n = 32
+    with pytest.raises(lib.DCGError):
+        lib.dcg_setup(m, 1e-3, 1.0, opt)

@@ -127,3 +127,25 @@ def test_divdiv_blocks_act_on_each_stress_row_alike():
     C = A[:, :, :8, :8]
     assert np.allclose(AZ[:, :, :8], C[..., :4] / np.sqrt(2), atol=1e-15, rtol=0)
     assert np.allclose(AZ[:, :, 8:], C[..., 4:] / np.sqrt(2), atol=1e-15, rtol=0)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_fast_diagonalisation_inverts_the_2d_laplacian(n):
+    # the exact inner solve: with the host's 1D eigenvectors V and eigenvalues l
+    # (K V = M V diag(l)), (V (x) V) diag(1 / (l_i + l_k)) (V (x) V)^T on the
+    # tensor index (Iy, Ix) must invert the oracle's SIPG Laplacian, which also
+    # checks the separable reading L = M (x) K + K (x) M
+    N = 2 * n
+    vals, _ = lib.dcg_host_assemble(_mesh(n), 6)
+    V, lam = vals[:N * N].reshape(N, N), vals[N * N:]
+    W = np.kron(V, V)
+    Linv_t = W @ np.diag(1.0 / (lam[:, None] + lam[None, :]).reshape(-1)) @ W.T
+    perm = np.zeros(4 * n * n, dtype=int)        # element-major 4 e + j -> (Iy, Ix)
+    for e in range(n * n):
+        ex, ey = e % n, e // n
+        for j in range(4):
+            perm[4 * e + j] = (2 * ey + (j >> 1)) * N + 2 * ex + (j & 1)
+    Linv = Linv_t[np.ix_(perm, perm)]
+    L = d.sipg_laplacian(n).toarray()
+    assert np.abs(L @ Linv - np.eye(4 * n * n)).max() < 1e-9
+    assert lam.min() > 0
