@@ -5,7 +5,7 @@
 // with S, Z the scalar vectors rearranged from the element-major layout
 // 4 e + j (e = ey n + ex, j = ix + 2 iy) to the row-major tensor (Iy, Ix),
 // Ix = 2 ex + ix.  The products are FP64 register-blocked GEMMs staged
-// through LDS (each thread forms a 4 x 4 block of C).
+// through LDS (each thread forms a 2 x 2 or 4 x 4 block of C).
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -13,53 +13,60 @@
 namespace dcg {
 namespace {
 
-constexpr int kGT = 64;        // C tile per workgroup
-constexpr int kGK = 16;        // k step
+template <int TILE>
+struct GemmCfg {
+  static constexpr int kT = TILE;                   // C tile per workgroup
+  static constexpr int kK = 16;                     // k step
+  static constexpr int kR = TILE / 16;              // outputs per thread along each axis
+};
 constexpr int kGThreads = 256;
 
-// C = A B (N x N row-major); with la: C[i][k] *= 1 / (la[i] + lb[k]).
-__global__ __launch_bounds__(kGThreads) void k_gemm64(int N, const double* __restrict__ A,
-                                                      const double* __restrict__ B, double* __restrict__ C,
-                                                      const double* __restrict__ la,
-                                                      const double* __restrict__ lb) {
-  __shared__ double As[kGK][kGT + 2];   // A tile transposed: As[k][row]
-  __shared__ double Bs[kGK][kGT + 2];
+// C = A B (N x N row-major); with la: C[i][k] *= 1 / (la[i] + lb[k]).  A
+// 16 x 16 grid of threads, each forming a kR x kR block of the TILE x TILE tile.
+template <int TILE>
+__global__ __launch_bounds__(kGThreads) void k_gemm(int N, const double* __restrict__ A,
+                                                    const double* __restrict__ B, double* __restrict__ C,
+                                                    const double* __restrict__ la,
+                                                    const double* __restrict__ lb) {
+  using G = GemmCfg<TILE>;
+  __shared__ double As[G::kK][G::kT + 2];   // A tile transposed: As[k][row]
+  __shared__ double Bs[G::kK][G::kT + 2];
   const int tid = threadIdx.x;
   const int tx = tid % 16, ty = tid / 16;
-  const int row0 = blockIdx.y * kGT, col0 = blockIdx.x * kGT;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < N; k0 += kGK) {
-    for (int t = tid; t < kGT * kGK; t += kGThreads) {
-      const int r = t / kGK, kk = t % kGK;          // A: row r, column k0 + kk
+  const int row0 = blockIdx.y * G::kT, col0 = blockIdx.x * G::kT;
+  double acc[G::kR][G::kR] = {};
+  for (int k0 = 0; k0 < N; k0 += G::kK) {
+    for (int t = tid; t < G::kT * G::kK; t += kGThreads) {
+      const int r = t / G::kK, kk = t % G::kK;      // A: row r, column k0 + kk
       const int gr = row0 + r, gk = k0 + kk;
       As[kk][r] = (gr < N && gk < N) ? A[(int64_t)gr * N + gk] : 0.0;
-      const int kb = t / kGT, c = t % kGT;          // B: row k0 + kb, column c
+      const int kb = t / G::kT, c = t % G::kT;      // B: row k0 + kb, column c
       const int gkb = k0 + kb, gc = col0 + c;
       Bs[kb][c] = (gkb < N && gc < N) ? B[(int64_t)gkb * N + gc] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kGK; ++kk) {
-      double a[4], b[4];
+    for (int kk = 0; kk < G::kK; ++kk) {
+      double a[G::kR], b[G::kR];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty * 4 + q];
-        b[q] = Bs[kk][tx * 4 + q];
+      for (int q = 0; q < G::kR; ++q) {
+        a[q] = As[kk][ty * G::kR + q];
+        b[q] = Bs[kk][tx * G::kR + q];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < G::kR; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int j = 0; j < G::kR; ++j) acc[i][j] += a[i] * b[j];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gr = row0 + ty * 4 + i;
+  for (int i = 0; i < G::kR; ++i) {
+    const int gr = row0 + ty * G::kR + i;
     if (gr >= N) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gc = col0 + tx * 4 + j;
+    for (int j = 0; j < G::kR; ++j) {
+      const int gc = col0 + tx * G::kR + j;
       if (gc >= N) continue;
       double v = acc[i][j];
       if (la) v *= 1.0 / (la[gr] + lb[gc]);
@@ -86,8 +93,15 @@ __global__ __launch_bounds__(kGThreads) void k_fdm_permute(int n, int to_tensor,
 
 hipError_t gemm(int N, const double* A, const double* B, double* C, const double* la,
                 const double* lb, hipStream_t st) {
-  const dim3 grid((N + kGT - 1) / kGT, (N + kGT - 1) / kGT);
-  k_gemm64<<<grid, kGThreads, 0, st>>>(N, A, B, C, la, lb);
+  // 32 x 32 tiles (2 x 2 per thread) keep at least about 4 workgroups per CU up
+  // to N = 1024; 64 x 64 (4 x 4 per thread) above
+  if (N <= 1024) {
+    const dim3 grid((N + 31) / 32, (N + 31) / 32);
+    k_gemm<32><<<grid, kGThreads, 0, st>>>(N, A, B, C, la, lb);
+  } else {
+    const dim3 grid((N + 63) / 64, (N + 63) / 64);
+    k_gemm<64><<<grid, kGThreads, 0, st>>>(N, A, B, C, la, lb);
+  }
   return hipGetLastError();
 }
 
