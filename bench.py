@@ -329,6 +329,20 @@ def dt_sweep(args):
             log("dt=%g %s: status %d outer %d Tot %d Inn %.2f %.2f s, finest RAS %.1f us"
                 % (dt, prec, status, st.outer_iters, st.total_wcycles, st.inner_per_outer, t,
                    rows[-1]["finest_ras_us"]))
+        # the comparison of Tables 1-2: plain CG (no deflation) and deflated CG with an
+        # exact inner solve on the same system
+        for inner in ("none", "exact"):
+            solver = dcg.Solver(n, dt, prec="fp64", inner=inner, max_outer=args.sweep_max_outer)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status, st = solver.solve(b, x, tol)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            solver.close()
+            rows.append({"dt": dt, "form": "fp64", "inner": inner, "status": status,
+                         "outer": st.outer_iters, "solve_s": round(t, 3), "rel_res_true": st.rel_res_true})
+            log("dt=%g %s: status %d outer %d %.2f s" % (dt, "plain CG" if inner == "none" else "DCG exact inner",
+                                                          status, st.outer_iters, t))
     print(json.dumps({"metric": "dCG outer iterations / Tot / Inn against dt", "n": n, "tol": tol,
                       "max_outer": args.sweep_max_outer, "rows": rows}), flush=True)
 

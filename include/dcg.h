@@ -116,7 +116,13 @@ typedef struct {
  * V'^T with V' = V (x) V from the generalised eigenvectors K V = M V diag(l)
  * (fast diagonalisation: four dense 2n x 2n FP64 products per inner solve).
  * dcg_solve only, n <= 1024; stats count 0 W-cycles. */
-typedef enum { DCG_INNER_MG = 0, DCG_INNER_EXACT = 1 } dcg_inner;
+typedef enum {
+  DCG_INNER_MG = 0,
+  DCG_INNER_EXACT = 1,
+  DCG_INNER_NONE = 2   /* no deflation: every inner solve returns 0, so pi = 0,
+                          f_D = f, M_D = A* and the reconstruction returns
+                          x_hat -- plain CG on A* (the CG columns of Tables 1-2) */
+} dcg_inner;
 
 typedef struct {
   int32_t status;          /* dcg_status of the solve                         */

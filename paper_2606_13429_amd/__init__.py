@@ -9,7 +9,8 @@ if the library has not been built.
 from ._binding import *          # noqa: F401,F403  (the C entry points)
 from ._binding import (DCGError, dcg_defaults, dcg_destroy, dcg_setup, dcg_solve,
                        DCG_FP64, DCG_MIXED, DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_OUTER_FCG,
-                       DCG_OUTER_GMRES, DCG_PENDING, LIB_PATH, DCG_INNER_MG, DCG_INNER_EXACT)
+                       DCG_OUTER_GMRES, DCG_PENDING, LIB_PATH, DCG_INNER_MG, DCG_INNER_EXACT,
+                       DCG_INNER_NONE)
 
 _OUTER = {"cg": DCG_OUTER_CG, "fcg1": DCG_OUTER_FCG1, "fcg": DCG_OUTER_FCG, "gmres": DCG_OUTER_GMRES}
 
@@ -67,14 +68,15 @@ class Solver:
         """outer: "cg", "fcg1", "fcg" (truncated FCG with m_max, FCG(inf) for
         m_max = 0) or "gmres"; c_A > 0 selects the adaptive inner tolerance of
         eq. (tol); inner="exact" solves the inner system exactly by fast
-        diagonalisation instead of the W-cycle multigrid (uniform grid)."""
+        diagonalisation instead of the W-cycle multigrid (uniform grid);
+        inner="none" switches the deflation off (plain CG on A*)."""
         mesh, opt = dcg_defaults()
         mesh.n, mesh.penalty, mesh.pre, mesh.post = n, penalty, pre, post
         opt.prec = {"mixed": DCG_MIXED, "fp64": DCG_FP64}[prec]
         opt.outer = _OUTER[outer]
         opt.c_F, opt.max_outer, opt.max_inner = c_F, max_outer, max_inner
         opt.c_A, opt.m_max = c_A, m_max
-        opt.inner = {"mg": DCG_INNER_MG, "exact": DCG_INNER_EXACT}[inner]
+        opt.inner = {"mg": DCG_INNER_MG, "exact": DCG_INNER_EXACT, "none": DCG_INNER_NONE}[inner]
         opt.x0_given, opt.use_graph = int(x0_given), int(use_graph)
         self.n, self.dt, self.nu, self.mesh, self.opt = n, dt, nu, mesh, opt
         self.handle = dcg_setup(mesh, dt, nu, opt)

@@ -22,7 +22,7 @@ DCG_OK, DCG_NOT_CONVERGED, DCG_PENDING = 0, 1, 2
 DCG_EINVAL, DCG_ENOMEM, DCG_EDEVICE, DCG_EAGAIN, DCG_ENOTFOUND, DCG_EBREAKDOWN = -1, -2, -3, -4, -5, -6
 DCG_FP64, DCG_MIXED = 0, 1
 DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_OUTER_FCG, DCG_OUTER_GMRES = 0, 1, 2, 3
-DCG_INNER_MG, DCG_INNER_EXACT = 0, 1
+DCG_INNER_MG, DCG_INNER_EXACT, DCG_INNER_NONE = 0, 1, 2
 (DCG_OP_ASTAR, DCG_OP_ZT, DCG_OP_Z, DCG_OP_ADIVZ, DCG_OP_DEFLATED, DCG_OP_INNER, DCG_OP_LAPLACE,
  DCG_OP_RAS, DCG_OP_RESTRICT, DCG_OP_PROLONG, DCG_OP_COARSE, DCG_OP_WCYCLE, DCG_OP_RAS_BATCH,
  DCG_OP_WCYCLE_BATCH) = range(14)

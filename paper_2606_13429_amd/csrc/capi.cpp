@@ -55,8 +55,8 @@ dcg_status check_options(const dcg_options& o) {
     return fail(nullptr, DCG_EINVAL, "bad outer variant");
   if (!(o.c_A >= 0.0) || !std::isfinite(o.c_A)) return fail(nullptr, DCG_EINVAL, "c_A must be >= 0");
   if (o.m_max < 0) return fail(nullptr, DCG_EINVAL, "m_max must be >= 0");
-  if (o.inner != DCG_INNER_MG && o.inner != DCG_INNER_EXACT)
-    return fail(nullptr, DCG_EINVAL, "inner must be DCG_INNER_MG or DCG_INNER_EXACT");
+  if (o.inner != DCG_INNER_MG && o.inner != DCG_INNER_EXACT && o.inner != DCG_INNER_NONE)
+    return fail(nullptr, DCG_EINVAL, "inner must be DCG_INNER_MG, DCG_INNER_EXACT or DCG_INNER_NONE");
   if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
     return fail(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
   return DCG_OK;

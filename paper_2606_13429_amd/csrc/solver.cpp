@@ -224,6 +224,10 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
 }
 
 int inner(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
+  if (h->opt.inner == DCG_INNER_NONE) {   // no deflation: pi = 0 turns Algorithm 2 into CG on A*
+    DCG_HIP(launch_fill<double>(4 * int64_t(h->mesh->ne), 0.0, z, st));
+    return 0;
+  }
   if (h->exact) {   // z = L^{-1} s exactly (fast diagonalisation); no W-cycles
     DCG_HIP(launch_fdm_solve2d(h->mesh->n, h->fV, h->fVT, h->flam, s, z, h->ft[0], h->ft[1], h->ft[2], st));
     return 0;

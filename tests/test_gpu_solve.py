@@ -224,3 +224,22 @@ def test_exact_inner_operator_and_rejections():
     m.n = 32
     with pytest.raises(lib.DCGError):
         lib.dcg_setup(m, 1e-3, 1.0, opt)
+
+
+@pytest.mark.parametrize("n,dt", [(16, 1e-2), (32, 1e-4)])
+def test_no_deflation_is_plain_cg(n, dt):
+    # DCG_INNER_NONE: pi = 0, so Algorithm 2 reduces to CG on A*; compare with the
+    # oracle's plain CG (the CG columns of Tables 1-2)
+    As = d.operator(n, dt)
+    f = elem_to_comp(rhs(n, 0), n)
+    x_ref, it_ref, _ = kr.cg(As, f, tol=1e-8)
+    status, st, x, s = _gpu(n, dt, 0, 1e-8, "fp64", inner="none")
+    s.close()
+    assert status == lib.DCG_OK
+    assert abs(st.outer_iters - it_ref) <= max(2, 0.02 * it_ref), (st.outer_iters, it_ref)
+    xr = comp_to_elem(x_ref, n)
+    assert np.linalg.norm(x - xr) <= 1e-6 * np.linalg.norm(xr)
+    assert st.total_wcycles == 0 and st.rel_res_true <= 2e-8
+    # deflation pays: the deflated solve of the same system takes fewer iterations
+    ref_d = _oracle(n, dt, 0, 1e-8, inner="exact")
+    assert ref_d.iterations < st.outer_iters
