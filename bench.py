@@ -476,14 +476,17 @@ def three_d_sweep(args):
         b = torch.from_numpy(rhs3d(n, 0)).cuda()
         x = torch.empty_like(b)
         for dt in (1.0, 0.5, 0.1, 1e-2, 1e-3, 1e-4, 1e-5):
-            s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], max_outer=args.sweep_max_outer)
-            status, st = s.solve(b, x, THREE_D["tol"])
-            s.close()
-            rows.append({"n": n, "dt": dt, "status": status, "outer": st.outer_iters,
-                         "rel_res_true": st.rel_res_true, "ms": round(st.t_solve_ms, 1)})
-            log("3d sweep n=%d dt=%g: status=%d outer=%d res=%.2e %.1f ms"
-                % (n, dt, status, st.outer_iters, st.rel_res_true, st.t_solve_ms))
-    print(json.dumps({"metric": "3D dCG outer iterations vs dt (exact inner solve), n = 8, 16, 32",
+            for inner in ("exact", "none"):      # deflated CG, and plain CG beside it
+                s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"],
+                                 max_outer=args.sweep_max_outer, inner=inner)
+                status, st = s.solve(b, x, THREE_D["tol"])
+                s.close()
+                rows.append({"n": n, "dt": dt, "method": "DCG" if inner == "exact" else "CG",
+                             "status": status, "outer": st.outer_iters,
+                             "rel_res_true": st.rel_res_true, "ms": round(st.t_solve_ms, 1)})
+                log("3d sweep n=%d dt=%g %s: status=%d outer=%d res=%.2e %.1f ms"
+                    % (n, dt, rows[-1]["method"], status, st.outer_iters, st.rel_res_true, st.t_solve_ms))
+    print(json.dumps({"metric": "3D outer iterations vs dt: DCG (exact inner solve) and plain CG, n = 8, 16, 32",
                       "unit": "iterations", "tol": THREE_D["tol"], "rows": rows}), flush=True)
 
 

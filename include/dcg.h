@@ -349,7 +349,8 @@ typedef struct dcg3d_ctx* dcg3d_handle;
 
 typedef enum {
   DCG3D_INNER_FDM = 0,    /* exact inner solve by fast diagonalisation (default)  */
-  DCG3D_INNER_PCG = 1     /* block-Jacobi CG to c_F * tol                           */
+  DCG3D_INNER_PCG = 1,    /* block-Jacobi CG to c_F * tol                           */
+  DCG3D_INNER_NONE = 2    /* no deflation: plain CG on A* (the CG column of Table 5)  */
 } dcg3d_inner;
 
 typedef enum {

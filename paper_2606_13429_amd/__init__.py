@@ -21,7 +21,8 @@ class Solver3D:
     """The three-dimensional solver (dcg3d_setup / dcg3d_solve): deflated CG
     for the d = 3 block structure on n^3 cubes, FP64; the inner system solved
     exactly by fast diagonalisation (inner="exact") or by block-Jacobi CG to
-    c_F * tol (inner="cg").
+    c_F * tol (inner="cg"); inner="none" switches the deflation off (plain CG
+    on A*).
 
     >>> s = Solver3D(n=16, dt=1e-3)
     >>> status, stats = s.solve(b, x, tol=1e-8)     # 72 n^3 cuda float64 tensors
@@ -35,7 +36,8 @@ class Solver3D:
         self.n, self.dt, self.nu, self.penalty, self.opt = n, dt, nu, penalty, opt
         self.inner = inner
         self.handle = dcg3d_setup(n, penalty, dt, nu, opt,
-                                  {"exact": DCG3D_INNER_FDM, "cg": DCG3D_INNER_PCG}[inner])
+                                  {"exact": DCG3D_INNER_FDM, "cg": DCG3D_INNER_PCG,
+                                   "none": DCG3D_INNER_NONE}[inner])
 
     def solve(self, b, x, tol=1e-8):
         return dcg3d_solve(self.handle, b, x, tol)

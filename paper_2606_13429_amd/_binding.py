@@ -30,7 +30,7 @@ BATCH = 16   # vectors of the _BATCH operators and requests per serving batch
 (DCG3D_OP_ASTAR, DCG3D_OP_ZT, DCG3D_OP_Z, DCG3D_OP_DEFLATED, DCG3D_OP_REDUCED, DCG3D_OP_INNER,
  DCG3D_OP_ADIVZ) = range(7)
 DCG3D_MAX_N, DCG3D_DEFAULT_MAX_INNER, DCG3D_MAX_HOST_BLOCKS_N = 64, 20000, 16
-DCG3D_INNER_FDM, DCG3D_INNER_PCG = 0, 1
+DCG3D_INNER_FDM, DCG3D_INNER_PCG, DCG3D_INNER_NONE = 0, 1, 2
 
 
 class dcg_mesh(ctypes.Structure):

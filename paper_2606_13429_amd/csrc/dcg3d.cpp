@@ -469,7 +469,7 @@ struct dcg3d_ctx {
     H3(hipMemcpyAsync(y, x, len * sizeof(double), hipMemcpyDeviceToDevice, nullptr));
   }
   void astar(const double* x, double* y) {
-    const bool timed = timing && inner_kind == DCG3D_INNER_FDM;   // the dominant kernel then
+    const bool timed = timing && inner_kind != DCG3D_INNER_PCG;   // the dominant kernel then
     if (timed) time_mark();
     H3(dcg3::launch_astar3(n, Cd, Me, 1.0 / nu, dt, x, y, nullptr));
     if (timed) time_mark();
@@ -478,6 +478,11 @@ struct dcg3d_ctx {
   // yh = E^{-1} s to ||s - E yh|| <= rel ||s|| by block-Jacobi CG; returns the
   // number of steps.
   int inner(const double* rhs, double* out, double rel) {
+    if (inner_kind == DCG3D_INNER_NONE) {    // no deflation: pi = 0, Algorithm 2 is CG on A*
+      H3(dcg3::launch_fill(ns, 0.0, out, nullptr));
+      inner_solves += 1;
+      return 0;
+    }
     if (inner_kind == DCG3D_INNER_FDM) {     // exact: E^{-1} = (3/dt) L^{-1}
       H3(dcg3::launch_fdm_solve(n, fVx, fVxT, fVy, fVyT, flx, fly, 3.0 / dt, rhs, out, ir, iz, nullptr));
       inner_solves += 1;
@@ -643,8 +648,8 @@ dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, int32_t 
   if (!out) return fail3(nullptr, DCG_EINVAL, "out is NULL");
   *out = nullptr;
   if (n < 2 || n > DCG3D_MAX_N) return fail3(nullptr, DCG_EINVAL, "n must be in [2, 64]");
-  if (inner != DCG3D_INNER_FDM && inner != DCG3D_INNER_PCG)
-    return fail3(nullptr, DCG_EINVAL, "inner must be DCG3D_INNER_FDM or DCG3D_INNER_PCG");
+  if (inner != DCG3D_INNER_FDM && inner != DCG3D_INNER_PCG && inner != DCG3D_INNER_NONE)
+    return fail3(nullptr, DCG_EINVAL, "inner must be DCG3D_INNER_FDM, DCG3D_INNER_PCG or DCG3D_INNER_NONE");
   if (!(penalty > 0.0) || !std::isfinite(penalty)) return fail3(nullptr, DCG_EINVAL, "penalty must be positive");
   if (!(dt > 0.0) || !std::isfinite(dt) || !(nu > 0.0) || !std::isfinite(nu))
     return fail3(nullptr, DCG_EINVAL, "dt and nu must be positive");

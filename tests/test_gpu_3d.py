@@ -171,6 +171,23 @@ def test_outer_counts_fall_with_dt_and_grow_with_n():
         assert counts[(4, dt)] < counts[(8, dt)]
 
 
+@pytest.mark.parametrize("n,dt", [(3, 1e-2), (4, 1e-4)])
+def test_no_deflation_is_plain_cg(n, dt):
+    As = d3.operator(n, dt, nu=NU, penalty=PEN)
+    f = elem_to_comp3(rhs3d(n, 1), n)
+    x_ref, it_ref, _ = kr.cg(As, f, tol=1e-10)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="none")
+    b = _dev(rhs3d(n, 1))
+    x = torch.empty_like(b)
+    status, st = s.solve(b, x, 1e-10)
+    s.close()
+    assert status == lib.DCG_OK
+    assert abs(st.outer_iters - it_ref) <= max(2, 0.02 * it_ref), (st.outer_iters, it_ref)
+    assert np.linalg.norm(elem_to_comp3(_host(x), n) - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
+    res, _ = _oracle(n, dt, 1, 1e-10)
+    assert res.iterations < st.outer_iters               # deflation pays
+
+
 def test_full_size_identities_and_solve():
     n, dt, tol = THREE_D["n"], THREE_D["dt"], THREE_D["tol"]
     print("3d full size n=%d" % n, flush=True)
