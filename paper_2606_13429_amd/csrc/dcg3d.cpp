@@ -25,6 +25,7 @@
 
 #include "../../include/dcg.h"
 #include "dcg3d.hpp"
+#include "fdm_host.hpp"
 
 namespace {
 
@@ -226,135 +227,14 @@ void assemble3d(int n, double penalty, double dt, std::vector<double>& cd, std::
 // ---------------------------------------------------------------------------
 // On the uniform grid the SIPG Laplacian is the Kronecker sum
 //   L = M (x) M (x) K_x + M (x) K_y (x) M + K_z (x) M (x) M
-// (tensor index (Iz, Iy, Ix), I = 2 e_axis + i_axis), with M the 1D DG-P1 mass
-// matrix and K the 1D SIPG matrix along one axis: the volume term, the
-// interior-node terms and, for x only, the outflow node x = 1.  The face
-// integrals of the 3D forms factor into 1D face terms times the 2D mass of the
-// face, so the sum is exact.  With K_d V_d = M V_d Lambda_d, V_d^T M V_d = I,
+// (tensor index (Iz, Iy, Ix), I = 2 e_axis + i_axis) of the 1D DG-P1 mass M and
+// the 1D SIPG matrices K (volume term, interior-node terms and, for x only,
+// the outflow node x = 1), because the face integrals of the 3D forms factor
+// into 1D node terms times the 2D mass of the face.  With K_d V_d = M V_d
+// Lambda_d, V_d^T M V_d = I (dcg::fdm_axis_factor),
 //   L^{-1} = V diag(1 / (lx_i + ly_j + lz_k)) V^T,  V = V_z (x) V_y (x) V_x.
-struct Fdm1d {
-  std::vector<double> V;     // [N][N] row-major: V[j * N + i] = (V_d)_{j i}
-  std::vector<double> lam;   // [N]
-};
-
-// 1D matrices on n cells of side h, dofs 2 c + i (i = 0 left node, 1 right).
-void sipg_1d(int n, double gamma, bool outflow, std::vector<double>& K, std::vector<double>& M) {
-  const int N = 2 * n;
-  const double h = 1.0 / n;
-  K.assign((size_t)N * N, 0.0);
-  M.assign((size_t)N * N, 0.0);
-  auto at = [N](std::vector<double>& A, int i, int j) -> double& { return A[(size_t)i * N + j]; };
-  const double d[2] = {-1.0 / h, 1.0 / h};       // derivatives of the two P1 functions of a cell
-  for (int c = 0; c < n; ++c)
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) {
-        at(M, 2 * c + i, 2 * c + j) += h / 6.0 * (i == j ? 2.0 : 1.0);
-        at(K, 2 * c + i, 2 * c + j) += h * d[i] * d[j];
-      }
-  // a node term  - {u'} [v] - {v'} [u] + gamma [u] [v]  with the jump [w] and the
-  // mean derivative {w'} given as coefficient lists over the dofs
-  auto node = [&](const std::vector<std::pair<int, double>>& jump,
-                  const std::vector<std::pair<int, double>>& mean) {
-    for (auto [a, ja] : jump)
-      for (auto [b, mb] : mean) {
-        at(K, a, b) -= ja * mb;     // test in the jump, trial in the mean derivative
-        at(K, b, a) -= ja * mb;     // the transposed term
-      }
-    for (auto [a, ja] : jump)
-      for (auto [b, jb] : jump) at(K, a, b) += gamma * ja * jb;
-  };
-  for (int c = 0; c + 1 < n; ++c)
-    node({{2 * c + 1, 1.0}, {2 * c + 2, -1.0}},
-         {{2 * c, 0.5 * d[0]}, {2 * c + 1, 0.5 * d[1]}, {2 * c + 2, 0.5 * d[0]}, {2 * c + 3, 0.5 * d[1]}});
-  if (outflow) node({{N - 1, 1.0}}, {{N - 2, d[0]}, {N - 1, d[1]}});
-}
-
-// Eigen-decomposition of a symmetric matrix by cyclic Jacobi rotations:
-// A = Q diag(w) Q^T, Q column j = eigenvector j.
-void jacobi_eigen(std::vector<double> A, int N, std::vector<double>& Q, std::vector<double>& w) {
-  Q.assign((size_t)N * N, 0.0);
-  for (int i = 0; i < N; ++i) Q[(size_t)i * N + i] = 1.0;
-  auto a = [&](int i, int j) -> double& { return A[(size_t)i * N + j]; };
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) (i == j ? tot : off) += a(i, j) * a(i, j);
-    if (off <= 1e-30 * (tot + off)) break;
-    for (int p = 0; p < N - 1; ++p)
-      for (int q = p + 1; q < N; ++q) {
-        const double apq = a(p, q);
-        if (apq == 0.0) continue;
-        const double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-        for (int k = 0; k < N; ++k) {         // A <- A J (columns p, q)
-          const double akp = a(k, p), akq = a(k, q);
-          a(k, p) = c * akp - sn * akq;
-          a(k, q) = sn * akp + c * akq;
-        }
-        for (int k = 0; k < N; ++k) {         // A <- J^T A (rows p, q)
-          const double apk = a(p, k), aqk = a(q, k);
-          a(p, k) = c * apk - sn * aqk;
-          a(q, k) = sn * apk + c * aqk;
-        }
-        for (int k = 0; k < N; ++k) {         // Q <- Q J
-          double* qk = &Q[(size_t)k * N];
-          const double qkp = qk[p], qkq = qk[q];
-          qk[p] = c * qkp - sn * qkq;
-          qk[q] = sn * qkp + c * qkq;
-        }
-      }
-  }
-  w.resize(N);
-  for (int i = 0; i < N; ++i) w[i] = a(i, i);
-}
-
-// K V = M V Lambda with V^T M V = I: M = R^T R (R upper triangular, here 2 x 2
-// blocks), C = R^{-T} K R^{-1} = Q Lambda Q^T, V = R^{-1} Q.
-Fdm1d fdm_axis(int n, double gamma, bool outflow) {
-  const int N = 2 * n;
-  std::vector<double> K, M;
-  sipg_1d(n, gamma, outflow, K, M);
-  // R^{-1} of the 2 x 2 blocks [[2,1],[1,2]] h/6: R = [[r00, r01], [0, r11]]
-  std::vector<double> Ri((size_t)N * N, 0.0);
-  for (int c = 0; c < n; ++c) {
-    const double m00 = M[(size_t)(2 * c) * N + 2 * c], m01 = M[(size_t)(2 * c) * N + 2 * c + 1],
-                 m11 = M[(size_t)(2 * c + 1) * N + 2 * c + 1];
-    const double r00 = std::sqrt(m00), r01 = m01 / r00, r11 = std::sqrt(m11 - r01 * r01);
-    Ri[(size_t)(2 * c) * N + 2 * c] = 1.0 / r00;
-    Ri[(size_t)(2 * c) * N + 2 * c + 1] = -r01 / (r00 * r11);
-    Ri[(size_t)(2 * c + 1) * N + 2 * c + 1] = 1.0 / r11;
-  }
-  std::vector<double> T((size_t)N * N, 0.0), C((size_t)N * N, 0.0);
-  for (int i = 0; i < N; ++i)          // T = K R^{-1}
-    for (int k = 0; k < N; ++k) {
-      const double kik = K[(size_t)i * N + k];
-      if (kik == 0.0) continue;
-      for (int j = 0; j < N; ++j) T[(size_t)i * N + j] += kik * Ri[(size_t)k * N + j];
-    }
-  for (int i = 0; i < N; ++i)          // C = R^{-T} T
-    for (int k = 0; k < N; ++k) {
-      const double rki = Ri[(size_t)k * N + i];
-      if (rki == 0.0) continue;
-      for (int j = 0; j < N; ++j) C[(size_t)i * N + j] += rki * T[(size_t)k * N + j];
-    }
-  for (int i = 0; i < N; ++i)          // symmetrise the rounding
-    for (int j = i + 1; j < N; ++j) {
-      const double v = 0.5 * (C[(size_t)i * N + j] + C[(size_t)j * N + i]);
-      C[(size_t)i * N + j] = C[(size_t)j * N + i] = v;
-    }
-  std::vector<double> Q, w;
-  jacobi_eigen(C, N, Q, w);
-  Fdm1d out;
-  out.lam = w;
-  out.V.assign((size_t)N * N, 0.0);
-  for (int i = 0; i < N; ++i)          // V = R^{-1} Q
-    for (int k = 0; k < N; ++k) {
-      const double rik = Ri[(size_t)i * N + k];
-      if (rik == 0.0) continue;
-      for (int j = 0; j < N; ++j) out.V[(size_t)i * N + j] += rik * Q[(size_t)k * N + j];
-    }
-  return out;
+dcg::FdmAxis fdm3_axis(int n, double penalty, bool outflow) {
+  return dcg::fdm_axis_factor(n, penalty * n, false, outflow);
 }
 
 template <typename T>
@@ -430,7 +310,7 @@ struct dcg3d_ctx {
     H3(hipMemcpy(Me, me.data(), 64 * sizeof(double), hipMemcpyHostToDevice));
     if (inner_kind == DCG3D_INNER_FDM) {
       const int N = 2 * n;
-      const Fdm1d fx = fdm_axis(n, penalty * n, true), fy = fdm_axis(n, penalty * n, false);
+      const dcg::FdmAxis fx = fdm3_axis(n, penalty, true), fy = fdm3_axis(n, penalty, false);
       std::vector<double> vxt((size_t)N * N), vyt((size_t)N * N);
       for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) {
@@ -720,9 +600,9 @@ dcg_status dcg3d_host_blocks(int32_t n, double penalty, double dt, int32_t which
   return guarded3(nullptr, [&] {
     if (which == 4) {   // fast-diagonalisation factors: V_x, lambda_x, V_y, lambda_y
       const size_t N = 2 * (size_t)n;
-      const Fdm1d fx = fdm_axis(n, penalty * n, true), fy = fdm_axis(n, penalty * n, false);
+      const dcg::FdmAxis fx = fdm3_axis(n, penalty, true), fy = fdm3_axis(n, penalty, false);
       double* o = out;
-      for (const Fdm1d* f : {&fx, &fy}) {
+      for (const dcg::FdmAxis* f : {&fx, &fy}) {
         std::memcpy(o, f->V.data(), N * N * sizeof(double));
         std::memcpy(o + N * N, f->lam.data(), N * sizeof(double));
         o += N * N + N;

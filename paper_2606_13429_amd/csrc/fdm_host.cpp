@@ -16,7 +16,8 @@
 
 namespace dcg {
 
-void sipg_axis(int n, double gamma, bool left_bc, std::vector<double>& K, std::vector<double>& M) {
+void sipg_axis(int n, double gamma, bool left_bc, std::vector<double>& K, std::vector<double>& M,
+               bool right_bc) {
   const int N = 2 * n;
   const double h = 1.0 / n;
   K.assign((size_t)N * N, 0.0);
@@ -46,6 +47,8 @@ void sipg_axis(int n, double gamma, bool left_bc, std::vector<double>& K, std::v
          {{2 * c, 0.5 * d[0]}, {2 * c + 1, 0.5 * d[1]}, {2 * c + 2, 0.5 * d[0]}, {2 * c + 3, 0.5 * d[1]}});
   if (left_bc)                      // x = 0, outward normal -1: jump -u, single trace
     node({{0, -1.0}}, {{0, d[0]}, {1, d[1]}});
+  if (right_bc)                     // x = 1, outward normal +1: jump u, single trace
+    node({{N - 1, 1.0}}, {{N - 2, d[0]}, {N - 1, d[1]}});
 }
 
 namespace {
@@ -152,10 +155,10 @@ void tridiag_ql(std::vector<double>& d, std::vector<double>& e, int N, std::vect
 
 }  // namespace
 
-FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc) {
+FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc, bool right_bc) {
   const int N = 2 * n;
   std::vector<double> K, M;
-  sipg_axis(n, gamma, left_bc, K, M);
+  sipg_axis(n, gamma, left_bc, K, M, right_bc);
   // M = R^T R with R upper triangular 2 x 2 blocks; C = R^{-T} K R^{-1}
   std::vector<double> Ri((size_t)N * N, 0.0);
   for (int c = 0; c < n; ++c) {

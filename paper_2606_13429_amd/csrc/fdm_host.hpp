@@ -14,12 +14,14 @@ struct FdmAxis {
 
 // K: the 1D SIPG matrix on n cells of side 1/n (volume term, interior-node
 // terms with penalty gamma, and the boundary-node term at the left end x = 0
-// when left_bc); M: the 1D DG-P1 mass matrix.  Both N x N row-major.
-void sipg_axis(int n, double gamma, bool left_bc, std::vector<double>& K, std::vector<double>& M);
+// when left_bc, at the right end x = 1 when right_bc); M: the 1D DG-P1 mass
+// matrix.  Both N x N row-major.
+void sipg_axis(int n, double gamma, bool left_bc, std::vector<double>& K, std::vector<double>& M,
+               bool right_bc = false);
 
 // K V = M V Lambda, V^T M V = I, for the matrices of sipg_axis (M block
 // diagonal with 2 x 2 blocks): Cholesky of M, Householder tridiagonalisation
 // of R^{-T} K R^{-1} and the implicit QL iteration.
-FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc);
+FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc, bool right_bc = false);
 
 }  // namespace dcg
