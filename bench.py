@@ -160,7 +160,8 @@ def cpu_baseline(n, dt, tol, gpu_outer, gpu_wcycles, c_F=0.01):
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": ("n=%d dt=%g: one inner multigrid solve (%d W-cycles, %.1f s) and one A* product "
+            "sample": ("n=%d dt=%g: one inner multigrid solve on the oracle's full hierarchy "
+                       "(coarsest 16x16, dense Cholesky; %d W-cycles, %.1f s) and one A* product "
                        "(%.2f s), extrapolated to the GPU solve's %d W-cycles and %d outer iterations "
                        "(estimate %.0f s per solve); oracle setup %.0f s not counted"
                        % (n, dt, cycles, t_inner, t_spmv, gpu_wcycles, gpu_outer, t_solve, t_setup)),
@@ -542,6 +543,9 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--dt", type=float, default=1e-4)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--levels", type=int, default=4,
+                    help="multigrid levels of the inner W-cycle (Section 5 uses four; capped at "
+                         "the mesh's log2(n/16)+1; 0 = every level down to 16x16 squares)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--max-outer", type=int, default=50000,
@@ -606,9 +610,13 @@ def main():
 
     n, dt, tol = args.n, args.dt, args.tol
     torch.cuda.set_device(0)
-    log("setup n=%d dt=%g (mixed form)" % (n, dt))
+    J_full = lib.dcg_num_levels(n)
+    if args.levels >= J_full:
+        args.levels = 0                # every level: the stored hierarchy as it is
+    levels_in_use = args.levels or J_full
+    log("setup n=%d dt=%g (mixed form, %d multigrid levels)" % (n, dt, levels_in_use))
     t0 = time.time()
-    solver = dcg.Solver(n, dt, prec="mixed", max_outer=args.max_outer)
+    solver = dcg.Solver(n, dt, prec="mixed", max_outer=args.max_outer, levels=args.levels)
     log("setup done in %.1f s" % (time.time() - t0))
     bs = [torch.from_numpy(rhs(n, s)).cuda() for s in range(max(args.steps, 1))]
     x = torch.empty_like(bs[0])
@@ -661,6 +669,9 @@ def main():
                       "bytes_per_launch": a_bytes}
 
     outer = int(np.mean([s["outer_iters"] for s in stats]))
+    nc = n >> (levels_in_use - 1)
+    coarse = ("coarsest %dx%d by fast diagonalisation" % (nc, nc) if args.levels
+              else "coarsest %dx%d by dense Cholesky" % (nc, nc))
     result = {
         "metric": "dCG solves/s & HBM GB/s, n=512 dt=1e-4, FP32-MG vs FP64; serve p50/p99",
         "value": round(value, 5), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -668,9 +679,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 outer / f32 multigrid",
         "data": "synthetic: b ~ N(0,1) seeds 0..%d, element-major" % (args.steps - 1),
         "config": {"workload": "deflated CG, unit square %dx%d DG-Q1 (%d dofs), dt=%g, tol=%g, "
-                               "W-cycle J=%d with RAS 4x4+1, c_F=0.01, mixed form"
-                               % (n, n, 16 * n * n, dt, tol, lib.dcg_num_levels(n)),
-                   "n": n, "dt": dt, "tol": tol, "form": "mixed"},
+                               "W-cycle J=%d (%s) with RAS 4x4+1, c_F=0.01, mixed form"
+                               % (n, n, 16 * n * n, dt, tol, levels_in_use, coarse),
+                   "n": n, "dt": dt, "tol": tol, "form": "mixed",
+                   "levels": levels_in_use},
         "solve_stats": {"outer_iters": outer,
                         "total_wcycles": int(np.mean([s["total_wcycles"] for s in stats])),
                         "inner_per_outer": round(float(np.mean([s["inner_per_outer"] for s in stats])), 2),
@@ -682,7 +694,7 @@ def main():
 
     if not args.skip_fp64:
         log("FP64 form: setup + one solve")
-        s64 = dcg.Solver(n, dt, prec="fp64", max_outer=args.max_outer)
+        s64 = dcg.Solver(n, dt, prec="fp64", max_outer=args.max_outer, levels=args.levels)
         x64 = torch.empty_like(x)
         torch.cuda.synchronize()
         t0 = time.time()
@@ -697,11 +709,27 @@ def main():
             result["fp64"]["mixed_vs_fp64_rel_diff"] = rel
         s64.close()
 
+    if not args.skip_fp64 and args.levels:
+        # the same solve on every level down to 16 x 16 squares (dense Cholesky
+        # coarsest), for reference
+        log("full hierarchy (J=%d): one solve" % J_full)
+        sf = dcg.Solver(n, dt, prec="mixed", max_outer=args.max_outer, levels=0)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, stf = sf.solve(bs[0], x, tol)
+        torch.cuda.synchronize()
+        tf = time.time() - t0
+        result["full_hierarchy"] = {"levels": J_full, "solves_per_s": round(1.0 / tf, 5),
+                                    "outer_iters": stf.outer_iters, "total_wcycles": stf.total_wcycles,
+                                    "rel_res_true": stf.rel_res_true,
+                                    "speedup_of_levels_%d" % levels_in_use: round(value * tf, 3)}
+        sf.close()
+
     if not args.skip_fp64:
         # the paper's adaptive inner tolerance (eq. (tol), c_A = 0.01) on the same
         # solve, for reference; the headline keeps the fixed rule of the workload
         log("adaptive inner tolerance: one solve")
-        sa = dcg.Solver(n, dt, prec="mixed", c_A=0.01, max_outer=args.max_outer)
+        sa = dcg.Solver(n, dt, prec="mixed", c_A=0.01, max_outer=args.max_outer, levels=args.levels)
         torch.cuda.synchronize()
         t0 = time.time()
         _, sta = sa.solve(bs[0], x, tol)

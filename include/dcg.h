@@ -104,6 +104,17 @@ typedef struct {
                           and epilogue solves, instead of c_F tol [0 = off]   */
   int32_t m_max;       /* DCG_OUTER_FCG truncation, 0 = FCG(inf) [8]         */
   int32_t inner;       /* dcg_inner: the inner solver [DCG_INNER_MG]           */
+  int32_t levels;      /* multigrid levels J of the inner W-cycle (Algorithm 4,
+                          levels k = 1..J, Section 5 uses four).  0 = every
+                          level down to 16 x 16 squares, J = log2(n/16) + 1;
+                          1 <= levels < log2(n/16) + 1: the finest `levels`
+                          levels of that hierarchy, whose coarsest level of
+                          n / 2^(levels-1) squares per side (at most 1024) is
+                          solved exactly by fast diagonalisation of its
+                          Galerkin operator L_1 = M_1 (x) K_1 + K_1 (x) M_1
+                          (the dense Cholesky solve up to rounding, without
+                          forming the inverse).  dcg_solve / dcg_apply only;
+                          the server and the _BATCH operators need 0.  [0]   */
 } dcg_options;
 
 /* Inner solver of dcg_solve.  DCG_INNER_MG is the paper's method: the
@@ -163,7 +174,8 @@ dcg_status dcg_solve(dcg_handle h, const double* b, double* x, double tol,
 
 /* Operator-level entry points (for verification and composition).  All on
  * the handle's mesh context; vectors are device pointers.  "level" counts
- * multigrid levels 1 (coarsest, 16 x 16) .. J (finest); level vectors are
+ * the handle's multigrid levels 1 (coarsest: 16 x 16, or the coarsest level
+ * of opt.levels) .. J (finest); level vectors are
  * FP32 in the DCG_MIXED form and FP64 in the DCG_FP64 form ("real" below).
  *
  *  op                 in           in2         out          computes
@@ -177,7 +189,8 @@ dcg_status dcg_solve(dcg_handle h, const double* b, double* x, double tol,
  *  DCG_OP_RAS         f  (real,m_k) z (real)   z' (real,m_k) z + S_k (f - L_k z)
  *  DCG_OP_RESTRICT    r  (real,m_k) -          rc (real,m_{k-1}) P_k^T r
  *  DCG_OP_PROLONG     e  (real,m_{k-1}) -      v  (real,m_k) P_k e
- *  DCG_OP_COARSE      f  (real,m_1) -          z  (real,m_1) L_1^{-1} f (FP64 inverse)
+ *  DCG_OP_COARSE      f  (real,m_1) -          z  (real,m_1) L_1^{-1} f (FP64 inverse, or
+ *                                                            FP64 fast diagonalisation)
  *  DCG_OP_WCYCLE      f  (real,m_k) z0 (real or NULL = 0)  z (real,m_k)  Wcycle_k(f, z0)
  *  DCG_OP_RAS_BATCH   f  (real,16 m_k) z (real)  z' (real,16 m_k)  DCG_OP_RAS of 16 vectors
  *  DCG_OP_WCYCLE_BATCH f (real,16 m_k) z0 (or NULL) z (real,16 m_k) DCG_OP_WCYCLE of 16 vectors
@@ -213,6 +226,11 @@ int32_t dcg_num_levels(int32_t n);
  *   which = 4: RAS tile inverses of level, D_i-weighted, dst [T_k][128][128]
  *              (F[j][i] = (L_k)_i^{-1}[j][i] d_i), cols [T_k][32] = squares
  *   which = 5: coarsest inverse L_1^{-1}, dst [1024][1024]
+ *   which = 6: exact inner solve factors (n <= 256): the axis eigenvectors
+ *              V [2n][2n] row-major, then the eigenvalues lam [2n]
+ *   which = 7: the same factors of the coarsest level of the hierarchy with
+ *              ``level`` levels (opt.levels; 1 <= level <= J), whose axis
+ *              has N = 2 n / 2^(level-1) dofs (N <= 512): V [N][N], lam [N]
  * Slots are (self, x-1, x+1, y-1, y+1); a missing neighbour has a zero
  * block and column index -1.  ``dst_len`` is the buffer length in doubles;
  * *needed (may be NULL) receives the required length.  Returns DCG_EINVAL

@@ -43,7 +43,8 @@ class dcg_options(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int32),
-                ("c_A", ctypes.c_double), ("m_max", ctypes.c_int32), ("inner", ctypes.c_int32)]
+                ("c_A", ctypes.c_double), ("m_max", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("levels", ctypes.c_int32)]
 
 
 class dcg_stats(ctypes.Structure):

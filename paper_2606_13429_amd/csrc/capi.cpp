@@ -59,6 +59,7 @@ dcg_status check_options(const dcg_options& o) {
     return fail(nullptr, DCG_EINVAL, "inner must be DCG_INNER_MG, DCG_INNER_EXACT or DCG_INNER_NONE");
   if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
     return fail(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
+  if (o.levels < 0) return fail(nullptr, DCG_EINVAL, "levels must be >= 0");
   return DCG_OK;
 }
 
@@ -105,6 +106,10 @@ dcg_status dcg_setup(const dcg_mesh* mesh, double dt, double nu, const dcg_optio
   if (const dcg_status cs = check_options(o); cs != DCG_OK) return cs;
   if (o.inner == DCG_INNER_EXACT && mesh->n > 1024)
     return fail(nullptr, DCG_EINVAL, "DCG_INNER_EXACT needs n <= 1024");
+  if (o.levels > dcg::num_levels(mesh->n))
+    return fail(nullptr, DCG_EINVAL, "levels exceeds log2(n/16) + 1");
+  if (o.levels > 0 && (mesh->n >> (o.levels - 1)) > 1024)
+    return fail(nullptr, DCG_EINVAL, "levels leaves a coarsest level above 1024 x 1024 squares");
   dcg_ctx* h = nullptr;
   const dcg_status st = guarded(nullptr, [&]() {
     const auto t0 = std::chrono::steady_clock::now();
@@ -150,7 +155,23 @@ dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
   if (!mesh) return fail(nullptr, DCG_EINVAL, "mesh must not be NULL");
   std::string why;
   if (!valid_mesh(*mesh, why)) return fail(nullptr, DCG_EINVAL, why);
-  if (which < 0 || which > 6) return fail(nullptr, DCG_EINVAL, "which must be in [0, 6]");
+  if (which < 0 || which > 7) return fail(nullptr, DCG_EINVAL, "which must be in [0, 7]");
+  if (which == 7) {   // fast-diagonalisation factors of the coarsest level of `level` levels
+    if (level < 1 || level > dcg::num_levels(mesh->n))
+      return fail(nullptr, DCG_EINVAL, "level out of range");
+    if ((mesh->n >> (level - 1)) > 256) return fail(nullptr, DCG_EINVAL, "which = 7 needs a coarsest n <= 256");
+    return guarded(nullptr, [&]() -> dcg_status {
+      const dcg::FdmAxis f = dcg::fdm_coarse_axis(mesh->n, mesh->penalty * mesh->n, level - 1);
+      const int64_t need = int64_t(f.N) * f.N + f.N;
+      if (needed) *needed = need;
+      if (dst) {
+        if (dst_len < need) return fail(nullptr, DCG_EINVAL, "dst too small");
+        std::copy(f.V.begin(), f.V.end(), dst);
+        std::copy(f.lam.begin(), f.lam.end(), dst + int64_t(f.N) * f.N);
+      }
+      return DCG_OK;
+    });
+  }
   if (which == 6) {   // fast-diagonalisation factors of the exact inner solve: V then lambda
     if (mesh->n > 256) return fail(nullptr, DCG_EINVAL, "which = 6 needs n <= 256");
     return guarded(nullptr, [&]() -> dcg_status {
@@ -261,6 +282,7 @@ dcg_status dcg_server_create(const dcg_options* opt, dcg_server* out) {
   if (o.outer == DCG_OUTER_FCG || o.outer == DCG_OUTER_GMRES)
     return fail(nullptr, DCG_EINVAL, "the server runs DCG_OUTER_CG or DCG_OUTER_FCG1");
   if (o.inner != DCG_INNER_MG) return fail(nullptr, DCG_EINVAL, "the server runs DCG_INNER_MG");
+  if (o.levels != 0) return fail(nullptr, DCG_EINVAL, "the server runs the full hierarchy (levels = 0)");
   if (o.hbm_budget_bytes < 0) return fail(nullptr, DCG_EINVAL, "hbm_budget_bytes must be >= 0");
   return guarded(nullptr, [&]() {
     auto s = std::make_unique<dcg_srv>();

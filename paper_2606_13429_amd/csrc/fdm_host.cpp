@@ -155,10 +155,10 @@ void tridiag_ql(std::vector<double>& d, std::vector<double>& e, int N, std::vect
 
 }  // namespace
 
-FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc, bool right_bc) {
-  const int N = 2 * n;
-  std::vector<double> K, M;
-  sipg_axis(n, gamma, left_bc, K, M, right_bc);
+FdmAxis fdm_factor(const std::vector<double>& K, const std::vector<double>& M, int N) {
+  if (N % 2 || K.size() != size_t(N) * N || M.size() != size_t(N) * N)
+    throw std::invalid_argument("fdm_factor: K and M must be N x N with N even");
+  const int n = N / 2;
   // M = R^T R with R upper triangular 2 x 2 blocks; C = R^{-T} K R^{-1}
   std::vector<double> Ri((size_t)N * N, 0.0);
   for (int c = 0; c < n; ++c) {
@@ -198,6 +198,54 @@ FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc, bool right_bc) {
       for (int j = 0; j < N; ++j) out.V[(size_t)i * N + j] += ria * Q[(size_t)a * N + j];
     }
   return out;
+}
+
+FdmAxis fdm_axis_factor(int n, double gamma, bool left_bc, bool right_bc) {
+  std::vector<double> K, M;
+  sipg_axis(n, gamma, left_bc, K, M, right_bc);
+  return fdm_factor(K, M, 2 * n);
+}
+
+void galerkin_coarsen_axis(int n, std::vector<double>& K, std::vector<double>& M) {
+  // P: coarse DG-P1 on n / 2 cells -> fine DG-P1 on n cells.  Fine cell
+  // 2 c + s, node i sits at the local coordinate t = (s + i) / 2 of coarse
+  // cell c, where the coarse left / right functions take 1 - t / t.
+  if (n % 2) throw std::invalid_argument("galerkin_coarsen_axis: n must be even");
+  const int N = 2 * n, Nc = n;
+  std::vector<double> P((size_t)N * Nc, 0.0);
+  for (int c = 0; c < n / 2; ++c)
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < 2; ++i) {
+        const double t = 0.5 * (s + i);
+        const int row = 2 * (2 * c + s) + i;
+        P[(size_t)row * Nc + 2 * c] = 1.0 - t;
+        P[(size_t)row * Nc + 2 * c + 1] = t;
+      }
+  auto ptap = [&](const std::vector<double>& A) {
+    std::vector<double> AP((size_t)N * Nc, 0.0), C((size_t)Nc * Nc, 0.0);
+    for (int i = 0; i < N; ++i)
+      for (int k = 0; k < N; ++k) {
+        const double a = A[(size_t)i * N + k];
+        if (a == 0.0) continue;
+        for (int j = 0; j < Nc; ++j) AP[(size_t)i * Nc + j] += a * P[(size_t)k * Nc + j];
+      }
+    for (int k = 0; k < N; ++k)
+      for (int i = 0; i < Nc; ++i) {
+        const double p = P[(size_t)k * Nc + i];
+        if (p == 0.0) continue;
+        for (int j = 0; j < Nc; ++j) C[(size_t)i * Nc + j] += p * AP[(size_t)k * Nc + j];
+      }
+    return C;
+  };
+  K = ptap(K);
+  M = ptap(M);
+}
+
+FdmAxis fdm_coarse_axis(int n, double gamma, int coarsenings) {
+  std::vector<double> K, M;
+  sipg_axis(n, gamma, true, K, M);
+  for (int l = 0; l < coarsenings; ++l) galerkin_coarsen_axis(n >> l, K, M);
+  return fdm_factor(K, M, 2 * (n >> coarsenings));
 }
 
 }  // namespace dcg

@@ -231,5 +231,11 @@ hipError_t launch_resolve_b(int ne, bool has_z, const T* z, const T* Ye, T* out,
 hipError_t launch_fdm_solve2d(int n, const double* V, const double* VT, const double* lam,
                               const double* s, double* z, double* t0, double* t1, double* t2,
                               hipStream_t st);
+// The same solve as the exact coarsest-level solve of a multigrid level of n
+// squares per side with level vectors of type T (FP32 in the mixed form): f
+// is widened to FP64, solved in FP64 and z rounded back to T.
+template <typename T>
+hipError_t launch_fdm_coarse(int n, const double* V, const double* VT, const double* lam,
+                             const T* f, T* z, double* t0, double* t1, double* t2, hipStream_t st);
 
 }  // namespace dcg

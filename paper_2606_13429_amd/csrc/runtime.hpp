@@ -63,6 +63,18 @@ struct MeshContext {
   std::vector<void*> allocations;
 };
 
+// Exact coarsest-level solve of a shortened hierarchy (coarsest level larger
+// than the stored 16 x 16 one) by fast diagonalisation: the axis factors of
+// that level's Galerkin operator (V, its transpose VT, both 2n x 2n
+// row-major, eigenvalues lam) and three FP64 scratch vectors of 4 n^2.
+struct CoarseFdm {
+  int n = 0;                      // squares per side of the coarsest level
+  const double* V = nullptr;
+  const double* VT = nullptr;
+  const double* lam = nullptr;
+  double* t[3] = {nullptr, nullptr, nullptr};
+};
+
 // Returns the cached context of (current device, n, penalty), building and
 // uploading it on first use.
 std::shared_ptr<MeshContext> get_context(int n, double penalty, bool fp32);
@@ -151,6 +163,11 @@ struct dcg_ctx {
   // three scratch vectors, all in the workspace
   bool exact = false;
   double *fV = nullptr, *fVT = nullptr, *flam = nullptr, *ft[3] = {nullptr, nullptr, nullptr};
+  // multigrid levels in use (opt.levels): the hierarchy of the inner solve
+  // is stored levels lbase + 1 .. J, and with lbase > 0 its coarsest level is
+  // solved by fast diagonalisation (cfdm, factors in the workspace)
+  int lbase = 0;
+  dcg::CoarseFdm cfdm;
   ~dcg_ctx();
 };
 

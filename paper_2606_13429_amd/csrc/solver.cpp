@@ -99,6 +99,8 @@ constexpr double kApplyTol = 1e-8;   // outer tolerance assumed by DCG_OP_INNER 
 template <typename T>
 Cycle<T> make_cycle(dcg_ctx* h) {
   Cycle<T> c(*h->mesh, h->ws.lvb, h->mp.pre, h->mp.post);
+  c.base = h->lbase;
+  if (h->lbase > 0) c.cfdm = &h->cfdm;
   if (h->ktime) {
     c.timer.ev = h->kev;
     c.timer.max = dcg_ctx::kMaxTimed;
@@ -127,7 +129,7 @@ void collect_kernel_times(dcg_ctx* h) {
 template <typename T>
 LvState run_wcycle_finest(dcg_ctx* h, hipStream_t st) {
   MeshContext& m = *h->mesh;
-  const int J = m.J;
+  const int J = m.J - h->lbase;   // levels of the cycle's own hierarchy
   const Cycle<T> cyc = make_cycle<T>(h);
   h->krec = 0;
   LvState s;
@@ -271,6 +273,26 @@ void handle_init(dcg_ctx* h) {
     DCG_HIP(hipMemcpy(h->fVT, vt.data(), sizeof(double) * NN, hipMemcpyHostToDevice));
     DCG_HIP(hipMemcpy(h->flam, f.lam.data(), sizeof(double) * f.N, hipMemcpyHostToDevice));
     h->exact = true;
+  }
+  if (h->opt.inner == DCG_INNER_MG && h->opt.levels > 0 && h->opt.levels < m.J) {
+    // shortened hierarchy: the coarsest level in use is stored level lbase + 1
+    h->lbase = m.J - h->opt.levels;
+    const FdmAxis f = fdm_coarse_axis(m.n, h->mp.penalty * m.n, h->opt.levels - 1);
+    const int64_t NN = int64_t(f.N) * f.N;
+    std::vector<double> vt(NN);
+    for (int i = 0; i < f.N; ++i)
+      for (int j = 0; j < f.N; ++j) vt[int64_t(j) * f.N + i] = f.V[int64_t(i) * f.N + j];
+    double* V = static_cast<double*>(ws.alloc(sizeof(double) * NN));
+    double* VT = static_cast<double*>(ws.alloc(sizeof(double) * NN));
+    double* lam = static_cast<double*>(ws.alloc(sizeof(double) * f.N));
+    for (double*& t : h->cfdm.t) t = static_cast<double*>(ws.alloc(sizeof(double) * NN));
+    DCG_HIP(hipMemcpy(V, f.V.data(), sizeof(double) * NN, hipMemcpyHostToDevice));
+    DCG_HIP(hipMemcpy(VT, vt.data(), sizeof(double) * NN, hipMemcpyHostToDevice));
+    DCG_HIP(hipMemcpy(lam, f.lam.data(), sizeof(double) * f.N, hipMemcpyHostToDevice));
+    h->cfdm.n = f.N / 2;
+    h->cfdm.V = V;
+    h->cfdm.VT = VT;
+    h->cfdm.lam = lam;
   }
 }
 
@@ -631,12 +653,14 @@ template <typename T>
 void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, void* out,
                  hipStream_t st) {
   MeshContext& m = *h->mesh;
-  if (k < 1 || k > m.J) throw Error(DCG_EINVAL, "level out of range");
-  const DeviceLevel& d = m.lv[k - 1];
+  if (k < 1 || k > m.J - h->lbase) throw Error(DCG_EINVAL, "level out of range");
+  const DeviceLevel& d = m.lv[k - 1 + h->lbase];
   const int64_t mk = 4 * int64_t(d.ne);
   const T* x = static_cast<const T*>(in);
   T* y = static_cast<T*>(out);
-  const Cycle<T> cyc(m, h->ws.lvb, h->mp.pre, h->mp.post);
+  Cycle<T> cyc(m, h->ws.lvb, h->mp.pre, h->mp.post);
+  cyc.base = h->lbase;
+  if (h->lbase > 0) cyc.cfdm = &h->cfdm;
   switch (op) {
     case DCG_OP_LAPLACE:
       DCG_HIP(launch_lap<T>(false, level_L<T>(d), d.cols, d.ne, nullptr, x, y, st));
@@ -663,7 +687,11 @@ void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, 
       break;
     case DCG_OP_COARSE:
       if (k != 1) throw Error(DCG_EINVAL, "coarse solve is on level 1");
-      DCG_HIP(launch_coarse<T>(m.coarse_inv, x, y, st));
+      if (h->lbase > 0)
+        DCG_HIP(launch_fdm_coarse<T>(h->cfdm.n, h->cfdm.V, h->cfdm.VT, h->cfdm.lam, x, y,
+                                     h->cfdm.t[0], h->cfdm.t[1], h->cfdm.t[2], st));
+      else
+        DCG_HIP(launch_coarse<T>(m.coarse_inv, x, y, st));
       break;
     case DCG_OP_WCYCLE: {
       DCG_HIP(launch_copy<T>(mk, x, cyc.f(k), st));
@@ -681,6 +709,7 @@ void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, 
     }
     case DCG_OP_RAS_BATCH:
     case DCG_OP_WCYCLE_BATCH: {
+      if (h->lbase > 0) throw Error(DCG_EINVAL, "the batched operators run the full hierarchy (levels = 0)");
       LevelBuffers& lb = h->ws.lvb_batch;
       if (lb.f.empty()) lb.allocate(m, h->fp32, true, h->ws);
       const Cycle<T> bc(m, lb, h->mp.pre, h->mp.post);

@@ -44,25 +44,32 @@ inline const float* level_F<float>(const DeviceLevel& d) { return d.F32; }
 template <>
 inline const double* level_F<double>(const DeviceLevel& d) { return d.F64; }
 
+// Levels are numbered 1 (coarsest) .. J of the cycle's own hierarchy, which
+// is the stored one shifted by ``base``: cycle level k is stored level
+// k + base.  With base > 0 the coarsest level is solved by fast
+// diagonalisation (``cfdm``); with base = 0 by the stored dense inverse.
 template <typename T>
 struct Cycle {
   const MeshContext& m;
   const LevelBuffers& b;
   int pre = 2, post = 2;
   SweepTimer timer;
+  int base = 0;
+  const CoarseFdm* cfdm = nullptr;
 
   Cycle(const MeshContext& mesh, const LevelBuffers& bufs, int m1, int m2)
       : m(mesh), b(bufs), pre(m1), post(m2) {}
 
-  T* f(int k) const { return static_cast<T*>(b.f[k - 1]); }
-  T* rr(int k) const { return static_cast<T*>(b.rr[k - 1]); }
-  T* z(int k, int i) const { return static_cast<T*>(b.z[i][k - 1]); }
-  T* Y(int k, int i) const { return static_cast<T*>(b.Y[i][k - 1]); }
+  const DeviceLevel& lev(int k) const { return m.lv[k - 1 + base]; }
+  T* f(int k) const { return static_cast<T*>(b.f[k - 1 + base]); }
+  T* rr(int k) const { return static_cast<T*>(b.rr[k - 1 + base]); }
+  T* z(int k, int i) const { return static_cast<T*>(b.z[i][k - 1 + base]); }
+  T* Y(int k, int i) const { return static_cast<T*>(b.Y[i][k - 1 + base]); }
 
   // One RAS step z <- z + S_k (f - L_k z) of level k; ``coarse`` (optional)
   // is the state of level k-1 whose prolongation P e is added first.
   void sweep_step(int k, LvState& s, const LvState* coarse, hipStream_t st) const {
-    const DeviceLevel& d = m.lv[k - 1];
+    const DeviceLevel& d = lev(k);
     SweepArgs<T> a;
     a.F = level_F<T>(d);
     a.dw = level_dw<T>(d);
@@ -90,7 +97,7 @@ struct Cycle {
     a.write_z = changes;
     a.z_new = z(k, zb_new);
     a.Y_new = Y(k, 1 - s.yb);
-    const bool timed = timer.ev && k == m.J && *timer.rec < timer.max;
+    const bool timed = timer.ev && k + base == m.J && *timer.rec < timer.max;
     if (timed) DCG_HIP(hipEventRecord(timer.ev[2 * *timer.rec], st));
     if (b.batched)
       DCG_HIP(launch_sweep_b<T>(a, st));
@@ -106,7 +113,7 @@ struct Cycle {
   // Resolves the pending update and restricts the residual:
   // f_{k-1} = P_k^T (f_k - L_k z).
   void restrict_step(int k, LvState& s, hipStream_t st) const {
-    const DeviceLevel& d = m.lv[k - 1];
+    const DeviceLevel& d = lev(k);
     RestrictArgs<T> a;
     a.n = d.n;
     a.ne = d.ne;
@@ -141,11 +148,11 @@ struct Cycle {
       return;
     }
     if (b.batched) throw Error(DCG_EINVAL, "the batched cycle needs post-smoothing (m2 >= 1)");
-    const DeviceLevel& d = m.lv[k - 1];
-    const int64_t mc = 4 * int64_t(m.lv[k - 2].ne);
+    const DeviceLevel& d = lev(k);
+    const int64_t mc = 4 * int64_t(lev(k - 1).ne);
     T* e = rr(k - 1);
     if (c.has_y)
-      DCG_HIP(launch_resolve<T>(m.lv[k - 2].ne, c.has_z, z(k - 1, c.zb), Y(k - 1, c.yb), e, st));
+      DCG_HIP(launch_resolve<T>(lev(k - 1).ne, c.has_z, z(k - 1, c.zb), Y(k - 1, c.yb), e, st));
     else
       DCG_HIP(launch_copy<T>(mc, z(k - 1, c.zb), e, st));
     if (!s.has_z) DCG_HIP(launch_fill<T>(4 * int64_t(d.ne), T(0), z(k, s.zb), st));
@@ -156,7 +163,11 @@ struct Cycle {
   // Level k W-cycle (Algorithm 4) on f_k from the iterate described by ``s``.
   void wcycle(int k, LvState& s, hipStream_t st) const {
     if (k == 1) {   // exact coarsest solve; the initial guess is irrelevant
-      if (b.batched)
+      if (cfdm) {
+        if (b.batched) throw Error(DCG_EINVAL, "the batched cycle runs the full hierarchy");
+        DCG_HIP(launch_fdm_coarse<T>(cfdm->n, cfdm->V, cfdm->VT, cfdm->lam, f(1), z(1, 0),
+                                     cfdm->t[0], cfdm->t[1], cfdm->t[2], st));
+      } else if (b.batched)
         DCG_HIP(launch_coarse_b<T>(m.coarse_inv, f(1), z(1, 0), st));
       else
         DCG_HIP(launch_coarse<T>(m.coarse_inv, f(1), z(1, 0), st));

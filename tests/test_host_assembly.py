@@ -149,3 +149,41 @@ def test_fast_diagonalisation_inverts_the_2d_laplacian(n):
     L = d.sipg_laplacian(n).toarray()
     assert np.abs(L @ Linv - np.eye(4 * n * n)).max() < 1e-9
     assert lam.min() > 0
+
+
+@pytest.mark.parametrize("n,levels", [(64, 2), (64, 3), (32, 1)])
+def test_coarse_level_fast_diagonalisation_inverts_galerkin_operator(n, levels):
+    # the exact coarsest solve of a shortened hierarchy: the host's axis factors
+    # of the coarsest level of ``levels`` levels must invert the oracle's own
+    # Galerkin coarsest operator P^T ... L ... P (dense products of its sparse
+    # hierarchy), which checks that the Galerkin product keeps the form
+    # M_c (x) K_c + K_c (x) M_c with the one-dimensional injection
+    nc = n >> (levels - 1)
+    N = 2 * nc
+    vals, _ = lib.dcg_host_assemble(_mesh(n), 7, levels)
+    assert vals.size == N * N + N
+    V, lam = vals[:N * N].reshape(N, N), vals[N * N:]
+    W = np.kron(V, V)
+    Linv_t = W @ np.diag(1.0 / (lam[:, None] + lam[None, :]).reshape(-1)) @ W.T
+    perm = np.zeros(4 * nc * nc, dtype=int)
+    for e in range(nc * nc):
+        ex, ey = e % nc, e // nc
+        for j in range(4):
+            perm[4 * e + j] = (2 * ey + (j >> 1)) * N + 2 * ex + (j & 1)
+    Linv = Linv_t[np.ix_(perm, perm)]
+    As = d.operator(n, 2.0)                       # dt = 2: Z_J = V^T A* V = L_J
+    Vd = d.deflation_basis(n)
+    H = mg.Hierarchy((Vd.T @ As @ Vd).tocsr(), n, coarsest=nc)
+    assert H.J == levels and H.n[1] == nc
+    Lc = H.A[1].toarray()
+    assert np.abs(Lc @ Linv - np.eye(4 * nc * nc)).max() < 1e-9
+    assert lam.min() > 0
+
+
+def test_coarse_level_factors_reject_bad_levels():
+    with pytest.raises(lib.DCGError):
+        lib.dcg_host_assemble(_mesh(64), 7, 0)
+    with pytest.raises(lib.DCGError):
+        lib.dcg_host_assemble(_mesh(64), 7, 4)       # J = 3 at n = 64
+    with pytest.raises(lib.DCGError):
+        lib.dcg_host_assemble(_mesh(1024), 7, 2)     # coarsest 512 > 256
