@@ -113,10 +113,93 @@ hipError_t gemm(int N, const double* A, const double* B, double* C, const double
   return hipGetLastError();
 }
 
+// Small grids (N = 2 n in {32, 64, 128, 256}: coarse levels) in two passes
+// with the layout change folded into the loads and stores, one workgroup per
+// row:
+//   pass 1: T2[i][k] = (sum_a sum_c V[a][i] S[a][c] V[c][k]) / (lam_i + lam_k),
+//           row i of U = V^T S, then of U V;
+//   pass 2: Z[a][c] = sum_i sum_k V[a][i] T2[i][k] V[c][k],
+//           row a of W = V T2, then of W V^T.
+// Thread t forms a partial sum for column t % N over the contraction range
+// [p N / P, (p + 1) N / P), p = t / N, P = 256 / N; the P partials of a
+// column are added in LDS in ascending p (fixed order).
+constexpr int kFThreads = 256;
+
+__device__ __forceinline__ int64_t tensor_to_elem(int n, int a, int c) {
+  return 4 * ((int64_t)(a >> 1) * n + (c >> 1)) + (c & 1) + 2 * (a & 1);
+}
+
+// sum over p of part[p N + c] for the threads t < N (column c = t)
+__device__ __forceinline__ double column_total(const double* part, int N, int P, int c) {
+  double t = 0.0;
+  for (int p = 0; p < P; ++p) t += part[p * N + c];
+  return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFThreads) void k_fdm_pass1(int n, const double* __restrict__ V,
+                                                         const double* __restrict__ VT,
+                                                         const double* __restrict__ lam,
+                                                         const T* __restrict__ s, double* __restrict__ T2) {
+  __shared__ double lhs[kFThreads];
+  __shared__ double mid[kFThreads];
+  __shared__ double part[kFThreads];
+  const int N = 2 * n, P = kFThreads / N, len = N / P;
+  const int tid = threadIdx.x, c = tid % N, q0 = (tid / N) * len;
+  const int i = blockIdx.x;
+  if (tid < N) lhs[tid] = VT[(int64_t)i * N + tid];     // row i of V^T
+  __syncthreads();
+  double u = 0.0;
+#pragma unroll 16
+  for (int a = q0; a < q0 + len; ++a) u += lhs[a] * double(s[tensor_to_elem(n, a, c)]);
+  part[tid] = u;
+  __syncthreads();
+  if (tid < N) mid[tid] = column_total(part, N, P, tid);   // U[i][c]
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll 16
+  for (int q = q0; q < q0 + len; ++q) t += mid[q] * V[(int64_t)q * N + c];
+  part[tid] = t;
+  __syncthreads();
+  if (tid < N) T2[(int64_t)i * N + tid] = column_total(part, N, P, tid) * (1.0 / (lam[i] + lam[tid]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFThreads) void k_fdm_pass2(int n, const double* __restrict__ V,
+                                                         const double* __restrict__ VT,
+                                                         const double* __restrict__ T2, T* __restrict__ z) {
+  __shared__ double lhs[kFThreads];
+  __shared__ double mid[kFThreads];
+  __shared__ double part[kFThreads];
+  const int N = 2 * n, P = kFThreads / N, len = N / P;
+  const int tid = threadIdx.x, c = tid % N, q0 = (tid / N) * len;
+  const int a = blockIdx.x;
+  if (tid < N) lhs[tid] = V[(int64_t)a * N + tid];      // row a of V
+  __syncthreads();
+  double w = 0.0;
+#pragma unroll 16
+  for (int i = q0; i < q0 + len; ++i) w += lhs[i] * T2[(int64_t)i * N + c];
+  part[tid] = w;
+  __syncthreads();
+  if (tid < N) mid[tid] = column_total(part, N, P, tid);   // W[a][c]
+  __syncthreads();
+  double v = 0.0;
+#pragma unroll 16
+  for (int k = q0; k < q0 + len; ++k) v += mid[k] * VT[(int64_t)k * N + c];
+  part[tid] = v;
+  __syncthreads();
+  if (tid < N) z[tensor_to_elem(n, a, tid)] = T(column_total(part, N, P, tid));
+}
+
 template <typename T>
 hipError_t fdm_solve(int n, const double* V, const double* VT, const double* lam, const T* s, T* z,
                      double* t0, double* t1, double* t2, hipStream_t st) {
   const int N = 2 * n;
+  if (N >= 32 && N <= kFThreads && kFThreads % N == 0) {
+    k_fdm_pass1<T><<<N, kFThreads, 0, st>>>(n, V, VT, lam, s, t0);
+    k_fdm_pass2<T><<<N, kFThreads, 0, st>>>(n, V, VT, t0, z);
+    return hipGetLastError();
+  }
   const int64_t total = 4 * (int64_t)n * n;
   const int pb = int((total + kGThreads - 1) / kGThreads);
   k_fdm_permute<T, double><<<pb, kGThreads, 0, st>>>(n, 1, s, t0);
