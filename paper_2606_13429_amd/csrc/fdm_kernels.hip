@@ -5,7 +5,7 @@
 // with S, Z the scalar vectors rearranged from the element-major layout
 // 4 e + j (e = ey n + ex, j = ix + 2 iy) to the row-major tensor (Iy, Ix),
 // Ix = 2 ex + ix.  The products are FP64 register-blocked GEMMs staged
-// through LDS (each thread forms a 1 x 1, 2 x 2 or 4 x 4 block of C).  The
+// through LDS (each thread forms a 2 x 2 or 4 x 4 block of C).  The
 // same solve serves as the exact coarsest-level solve of a shortened
 // multigrid hierarchy, whose level vectors may be FP32.
 #include <cstdint>
@@ -97,13 +97,8 @@ __global__ __launch_bounds__(kGThreads) void k_fdm_permute(int n, int to_tensor,
 hipError_t gemm(int N, const double* A, const double* B, double* C, const double* la,
                 const double* lb, hipStream_t st) {
   // 32 x 32 tiles (2 x 2 per thread) keep at least about 4 workgroups per CU up
-  // to N = 1024; 64 x 64 (4 x 4 per thread) above.  Small products (coarse
-  // levels, N <= 256) are latency-bound: 16 x 16 tiles with 64-deep k steps
-  // give more workgroups and fewer LDS round trips.
-  if (N <= 256) {
-    const dim3 grid((N + 15) / 16, (N + 15) / 16);
-    k_gemm<16, 64><<<grid, kGThreads, 0, st>>>(N, A, B, C, la, lb);
-  } else if (N <= 1024) {
+  // to N = 1024; 64 x 64 (4 x 4 per thread) above
+  if (N <= 1024) {
     const dim3 grid((N + 31) / 32, (N + 31) / 32);
     k_gemm<32, 16><<<grid, kGThreads, 0, st>>>(N, A, B, C, la, lb);
   } else {
