@@ -65,11 +65,28 @@ def copy_gbs(nbytes=1 << 30, reps=10):
 
 
 def sweep_bytes_per_square(s):
-    base = 576 * s + 4 * s + 8 * s + s
+    """Algorithmic HBM bytes per square of one RAS step, element size s, as
+    the mean over the four steps of a level visit (zero start, two with the
+    pending update, one with the prolongation).  Every step reads f and the
+    weight and writes the tile outputs (128 per 16-square core); all but the
+    first read the 80 operator entries of the square and its iterate and
+    write the resolved iterate; the pending outputs (12 per square) or the
+    coarse iterate and its pending outputs (a quarter square's worth) come on
+    top.  The tile inverses are not charged per square: the uniform grid has
+    9 distinct local problems per level, read once (sweep_launch_bytes)."""
+    base = 4 * s + 8 * s + s
     zero = base
     pending = base + 80 * s + 4 * s + 12 * s + 4 * s
     prolong = base + 80 * s + 4 * s + 4 * s + (4 * s + 12 * s) / 4
     return (zero + 2 * pending + prolong) / 4
+
+
+SWEEP_CLASSES = 9    # distinct RAS local problems per level (3 x 3 tile positions)
+
+
+def sweep_launch_bytes(n, s):
+    """Algorithmic bytes of one RAS step on a level of n x n squares."""
+    return int(sweep_bytes_per_square(s) * n * n + SWEEP_CLASSES * 36 * 256 * s)
 
 
 # HBM traffic of one finest-level RAS launch at n = 512 (mixed form), from two
@@ -308,7 +325,7 @@ def dt_sweep(args):
     b = torch.from_numpy(rhs(n, 0)).cuda()
     x = torch.empty_like(b)
     rows = []
-    s_bytes = {"fp64": sweep_bytes_per_square(8), "mixed": sweep_bytes_per_square(4)}
+    s_bytes = {"fp64": 8, "mixed": 4}
     for dt in (1e-5, 1e-4, 1e-3, 1e-2, 1e-1):
         for prec in ("fp64", "mixed"):
             solver = dcg.Solver(n, dt, prec=prec, max_outer=args.sweep_max_outer)
@@ -321,7 +338,7 @@ def dt_sweep(args):
             t = time.perf_counter() - t0
             k_ms, k_n = lib.dcg_kernel_timing_read(solver.handle)
             solver.close()
-            gbs = s_bytes[prec] * n * n / (k_ms / max(k_n, 1) * 1e-3) / 1e9
+            gbs = sweep_launch_bytes(n, s_bytes[prec]) / (k_ms / max(k_n, 1) * 1e-3) / 1e9
             rows.append({"dt": dt, "form": prec, "status": status, "outer": st.outer_iters,
                          "tot": st.total_wcycles, "inn": round(st.inner_per_outer, 2),
                          "solve_s": round(t, 3), "rel_res_true": st.rel_res_true,
@@ -378,7 +395,7 @@ def timestep(args):
     t_all = time.perf_counter() - t_all
     k_ms, k_n = lib.dcg_kernel_timing_read(stepper.solver.handle)
     k_avg = k_ms / max(k_n, 1)
-    gbs = sweep_bytes_per_square(4) * n * n / (k_avg * 1e-3) / 1e9
+    gbs = sweep_launch_bytes(n, 4) / (k_avg * 1e-3) / 1e9
     print(json.dumps({"metric": "BDF2 steps/s, n=1024 dt=1e-5, mixed form, warm start",
                       "value": round(len(rows) / t_all, 5), "unit": "steps/s", "steps": len(rows),
                       "of_steps": TIMESTEP["steps"],
@@ -462,6 +479,43 @@ def three_d(args):
                      "bytes_per_launch": nbytes},
         "rows": rows}), flush=True)
     s.close()
+
+
+def levels_sweep(args):
+    """Multigrid depth at the headline size: one warm solve per depth (levels
+    2 .. J, coarsest exact by fast diagonalisation, J = dense Cholesky of 16 x
+    16 squares), mixed form, capped at --sweep-max-outer outer iterations, so
+    that the time per W-cycle and the W-cycle counts can be compared."""
+    import torch
+    import paper_2606_13429_amd as dcg
+    from paper_2606_13429_amd import _binding as lib
+    from dcg_workloads import rhs
+    n, dt, tol = args.n, args.dt, args.tol
+    torch.cuda.set_device(0)
+    b = torch.from_numpy(rhs(n, 0)).cuda()
+    x = torch.empty_like(b)
+    J = lib.dcg_num_levels(n)
+    rows = []
+    for levels in range(2, J + 1):
+        solver = dcg.Solver(n, dt, prec="mixed", max_outer=args.sweep_max_outer,
+                            levels=0 if levels == J else levels)
+        solver.solve(b, x, tol)                          # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, st = solver.solve(b, x, tol)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        solver.close()
+        nc = n >> (levels - 1)
+        rows.append({"levels": levels, "coarsest": "%dx%d" % (nc, nc), "status": status,
+                     "outer": st.outer_iters, "tot": st.total_wcycles,
+                     "inn": round(st.inner_per_outer, 2), "solve_ms": round(1e3 * t, 1),
+                     "ms_per_wcycle": round(1e3 * t / max(st.total_wcycles, 1), 4)})
+        log("levels=%d (coarsest %s): outer %d Tot %d Inn %.2f  %.1f ms, %.3f ms per W-cycle"
+            % (levels, rows[-1]["coarsest"], st.outer_iters, st.total_wcycles, st.inner_per_outer,
+               1e3 * t, rows[-1]["ms_per_wcycle"]))
+    print(json.dumps({"levels_sweep": rows, "n": n, "dt": dt, "tol": tol,
+                      "max_outer": args.sweep_max_outer}), flush=True)
 
 
 def three_d_sweep(args):
@@ -558,6 +612,8 @@ def main():
     ap.add_argument("--serve-c-A", type=float, default=0.0,
                     help="serving: adaptive inner tolerance constant (0 = the fixed rule)")
     ap.add_argument("--dt-sweep", action="store_true", help="run the dt sweep at --sweep-n")
+    ap.add_argument("--levels-sweep", action="store_true",
+                    help="time per W-cycle against the multigrid depth at --n (capped solves)")
     ap.add_argument("--sweep-n", type=int, default=128)
     ap.add_argument("--sweep-max-outer", type=int, default=20000)
     ap.add_argument("--timestep", action="store_true", help="run BDF2 time stepping at n=1024")
@@ -588,6 +644,9 @@ def main():
         return
     if args.variants:
         variants(args)
+        return
+    if args.levels_sweep:
+        levels_sweep(args)
         return
     if args.dt_sweep:
         dt_sweep(args)
@@ -646,7 +705,7 @@ def main():
     ms_per_step = ms_total / args.steps
     value = 1000.0 / ms_per_step
 
-    tiles_bytes = int(sweep_bytes_per_square(4) * n * n)
+    tiles_bytes = sweep_launch_bytes(n, 4)
     k_avg_ms = k_ms / max(k_launches, 1)
     achieved = tiles_bytes / (k_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_sweep<float,1> (finest-level RAS step)",

@@ -111,17 +111,19 @@ void upload_level_L(const HostLevel& hl, T* dev) {
   DCG_HIP(hipMemcpy(dev, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
-// Tile inverses in the packed symmetric layout of the sweep kernel: per tile
-// the 36 upper 16 x 16 blocks (P <= Q, row by row), each row-major.
+// Inverses of the distinct local problems in the packed symmetric layout of
+// the sweep kernel: per class the 36 upper 16 x 16 blocks (P <= Q, row by
+// row), each row-major.  Tiles address them through their class.
 template <typename T>
 void upload_factors(const HostLevel& hl, T* dev) {
   const int64_t per = 36 * 256;
   const int chunk = 512;
+  const int classes = int(hl.unique_inv.size());
   std::vector<T> stage(size_t(chunk) * per);
-  for (int t0 = 0; t0 < hl.tiles; t0 += chunk) {
-    const int cnt = std::min(chunk, hl.tiles - t0);
+  for (int t0 = 0; t0 < classes; t0 += chunk) {
+    const int cnt = std::min(chunk, classes - t0);
     threaded(cnt, [&](int64_t dt) {
-      const std::vector<double>& src = hl.unique_inv[hl.tile_class[t0 + dt]];
+      const std::vector<double>& src = hl.unique_inv[t0 + dt];
       T* d = &stage[size_t(dt) * per];
       int b = 0;
       for (int P = 0; P < 8; ++P)
@@ -200,6 +202,12 @@ std::shared_ptr<MeshContext> build_context(int device, int n, double penalty) {
       dl.tile_dst = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_dst.size()));
       DCG_HIP(hipMemcpy(dl.tile_dst, hl.tile_dst.data(), sizeof(int32_t) * hl.tile_dst.size(),
                         hipMemcpyHostToDevice));
+      dl.classes = int(hl.unique_inv.size());
+      for (int32_t c : hl.tile_class)
+        if (c < 0 || c >= dl.classes) throw Error(DCG_EINVAL, "tile class out of range");
+      dl.fcls = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_class.size()));
+      DCG_HIP(hipMemcpy(dl.fcls, hl.tile_class.data(), sizeof(int32_t) * hl.tile_class.size(),
+                        hipMemcpyHostToDevice));
     }
   }
   ctx->coarse_inv = static_cast<double*>(ctx->alloc(sizeof(double) * kCoarseDofs * kCoarseDofs));
@@ -227,7 +235,7 @@ void MeshContext::ensure_factors(bool fp32) {
       upload_level_L<float>(hl, dl.L32);
     }
     if (k >= 2) {
-      const size_t cnt = size_t(hl.tiles) * 36 * 256;
+      const size_t cnt = size_t(dl.classes) * 36 * 256;
       if (fp32) {
         dl.F32 = static_cast<float*>(alloc(sizeof(float) * cnt));
         upload_factors<float>(hl, dl.F32);

@@ -11,8 +11,11 @@
 //   M_1              double  [Ne][16]
 //   L_k              T       [slot][Ne][row=4][4]
 //   cols             int32   [slot][Ne]               -1 = none
-//   RAS factors      T       [tile][36 blocks P <= Q][16][16]  packed upper blocks of the
-//                                                     symmetric (L_k)_t^{-1}, row-major
+//   RAS factors      T       [class][36 blocks P <= Q][16][16]  packed upper blocks of the
+//                                                     symmetric (L_k)_t^{-1}, row-major, one per
+//                                                     distinct local problem (interior tiles of
+//                                                     the uniform grid share one)
+//   factor classes   int32   [tile]                   class of the tile's inverse
 //   RAS weights      T       [Ne]                     1 / #blocks containing the square
 //   pending slots    int32   [tile][32]               3 e + k for block square e
 //   coarsest inverse double  [1024][1024]
@@ -165,7 +168,8 @@ hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st);
 // every tile) and its own tile outputs Y_new.
 template <typename T>
 struct SweepArgs {
-  const T* F = nullptr;             // [tiles][36][16][16] packed symmetric inverses
+  const T* F = nullptr;             // [classes][36][16][16] packed symmetric inverses
+  const int32_t* fcls = nullptr;    // [tiles] class of the tile's inverse in F
   const T* dw = nullptr;            // [ne] partition-of-unity weight 1 / #blocks
   const int32_t* ext = nullptr;     // [tiles][52] block squares + outside neighbours
   int tiles = 0, n = 0, ne = 0;

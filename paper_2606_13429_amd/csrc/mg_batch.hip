@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_b(SweepArgs<T> a) {
   // MFMA A operands: lane (r, k) of k-step kk holds row 16 P + r, column
   // 16 Q + 4 k + kk of the tile inverse; column blocks are loaded two ahead
   // of their use (the first two before the gather and residual phases)
-  const T* Ft = a.F + (int64_t)t * (36 * 256);
+  const T* Ft = a.F + (int64_t)a.fcls[t] * (36 * 256);   // grid = tiles
   auto load_q = [&](int Q, T (&dst)[2][4]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs<T> a) {
   // Every global load of the step is issued up front (one memory round
   // trip): the first factor blocks, the operator rows of this thread's
   // residual rows, and the iterate of the squares this thread resolves.
-  const T* Ft = a.F + (int64_t)t * (36 * 256);
+  const T* Ft = a.F + (int64_t)(live ? a.fcls[t] : 0) * (36 * 256);
   T pf[NP][4];
   if (live) {
 #pragma unroll

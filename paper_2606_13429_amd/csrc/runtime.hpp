@@ -33,8 +33,13 @@ struct DeviceLevel {
   int tiles = 0;                  // levels >= 2
   int32_t* tile_ext = nullptr;    // [tiles][52]
   int32_t* tile_dst = nullptr;    // [tiles][32]
-  float* F32 = nullptr;           // [tiles][36][16][16] packed symmetric inverses
+  // packed symmetric inverses of the distinct local problems (bit-identical
+  // local matrices and weights share one), [classes][36][16][16], and the
+  // class of every tile
+  float* F32 = nullptr;
   double* F64 = nullptr;
+  int32_t* fcls = nullptr;        // [tiles]
+  int classes = 0;
   float* dw32 = nullptr;          // [ne] 1 / #blocks containing the square
   double* dw64 = nullptr;
 };

@@ -157,8 +157,10 @@ size_t context_bytes(int n, bool fp32) {
     b += nek * kSlots * (sizeof(int32_t) + 16 * sizeof(double) + (fp32 ? 16 * sizeof(float) : 0));
     if (nk > kCoarsestN) {
       const size_t tiles = nek / 16;
-      b += tiles * (52 + 32) * sizeof(int32_t);
-      b += (tiles * 36 * 256 + nek) * (fp32 ? sizeof(float) : sizeof(double));
+      // distinct local problems: 9 on the uniform grid (3 x 3 tile positions)
+      const size_t classes = std::min<size_t>(tiles, 16);
+      b += tiles * (52 + 32 + 1) * sizeof(int32_t);
+      b += (classes * 36 * 256 + nek) * (fp32 ? sizeof(float) : sizeof(double));
     }
   }
   return b + size_t(kCoarseDofs) * kCoarseDofs * sizeof(double);

@@ -72,6 +72,7 @@ struct Cycle {
     const DeviceLevel& d = lev(k);
     SweepArgs<T> a;
     a.F = level_F<T>(d);
+    a.fcls = d.fcls;
     a.dw = level_dw<T>(d);
     a.ext = d.tile_ext;
     a.tiles = d.tiles;
