@@ -94,8 +94,8 @@ def sweep_launch_bytes(n, s):
 # each scaled by the reading of a plain 1 GiB copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE
 # 1 GiB).  Valid only for the kernel source it was taken on: the digest of the RAS kernel
 # sources must match, else the bench reports traffic as null.
-TRAFFIC = {"source_digest": "05773af7893e3209", "n": 512,
-           "fetch_kib": 357599.6, "fetch_scale": 2.0, "write_kib": 16498.1, "write_scale": 1.0}
+TRAFFIC = {"source_digest": "9b5580a635920db9", "n": 512,
+           "fetch_kib": 53428.2, "fetch_scale": 2.0, "write_kib": 15125.5, "write_scale": 1.0}
 
 
 # The same counters for the 3D A* product k_astar3 at n = 32 (exact inner solve;

@@ -144,9 +144,14 @@ __global__ __launch_bounds__(kFThreads) void k_fdm_pass1(int n, const double* __
   const int i = blockIdx.x;
   if (tid < N) lhs[tid] = VT[(int64_t)i * N + tid];     // row i of V^T
   __syncthreads();
+  // rows a, a + 1 (a even) of column c sit at sc[0] and sc[2] of the square
+  // row a / 2; consecutive square rows are 4 n apart
+  const T* sc = s + tensor_to_elem(n, q0, c);
+  const int64_t step = 4 * (int64_t)n;
   double u = 0.0;
-#pragma unroll 16
-  for (int a = q0; a < q0 + len; ++a) u += lhs[a] * double(s[tensor_to_elem(n, a, c)]);
+#pragma unroll 8
+  for (int a = q0; a < q0 + len; a += 2, sc += step)
+    u += lhs[a] * double(sc[0]) + lhs[a + 1] * double(sc[2]);
   part[tid] = u;
   __syncthreads();
   if (tid < N) mid[tid] = column_total(part, N, P, tid);   // U[i][c]
