@@ -81,6 +81,11 @@ def sweep_bytes_per_square(s):
     return (zero + 2 * pending + prolong) / 4
 
 
+# The finest-level RAS launches of every TIMING_STRIDE-th W-cycle are bracketed
+# by HIP events during the timed solve: an event pair costs a few microseconds of
+# stream time, which timing all 80,900 launches of a solve would add to it.
+TIMING_STRIDE = 8
+
 SWEEP_CLASSES = 9    # distinct RAS local problems per level (3 x 3 tile positions)
 
 
@@ -144,6 +149,13 @@ def measured_traffic(n):
         return None
     return int(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
                        + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
+
+
+def levels_option(n, levels):
+    """dcg_options.levels for a requested depth: 0 (the whole stored hierarchy)
+    when the mesh has no more than ``levels`` levels."""
+    from paper_2606_13429_amd import _binding as lib
+    return 0 if levels <= 0 or levels >= lib.dcg_num_levels(n) else levels
 
 
 def log(msg):
@@ -377,9 +389,9 @@ def timestep(args):
     torch.cuda.set_device(0)
     t0 = time.time()
     F = torch.from_numpy(forcing_load(n, fourier_modes(TIMESTEP["seed"], TIMESTEP["modes"]))).cuda()
-    stepper = BDF2(n, dt, prec="mixed", tol=args.tol)
+    stepper = BDF2(n, dt, prec="mixed", tol=args.tol, levels=levels_option(n, args.levels))
     log("n=%d setup + forcing %.1f s" % (n, time.time() - t0))
-    lib.dcg_kernel_timing(stepper.solver.handle, True)
+    lib.dcg_kernel_timing(stepper.solver.handle, TIMING_STRIDE)
     rows = []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -558,7 +570,8 @@ def variants(args):
     x = torch.empty_like(b)
     rows = []
     for outer, c_A in (("cg", 0.0), ("cg", 0.01), ("fcg1", 0.01), ("fcg", 0.01), ("gmres", 0.01)):
-        solver = dcg.Solver(n, dt, prec="mixed", outer=outer, c_A=c_A, m_max=8)
+        solver = dcg.Solver(n, dt, prec="mixed", outer=outer, c_A=c_A, m_max=8,
+                            levels=levels_option(n, args.levels))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         status, st = solver.solve(b, x, tol)
@@ -670,8 +683,7 @@ def main():
     n, dt, tol = args.n, args.dt, args.tol
     torch.cuda.set_device(0)
     J_full = lib.dcg_num_levels(n)
-    if args.levels >= J_full:
-        args.levels = 0                # every level: the stored hierarchy as it is
+    args.levels = levels_option(n, args.levels)
     levels_in_use = args.levels or J_full
     log("setup n=%d dt=%g (mixed form, %d multigrid levels)" % (n, dt, levels_in_use))
     t0 = time.time()
@@ -683,7 +695,7 @@ def main():
         st = solver.solve(bs[0], x, tol)[1]
         log("warmup %d: outer=%d Tot=%d %.1f ms" % (i, st.outer_iters, st.total_wcycles, st.t_solve_ms))
 
-    lib.dcg_kernel_timing(solver.handle, True)
+    lib.dcg_kernel_timing(solver.handle, TIMING_STRIDE)
     stats = []
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -712,7 +724,7 @@ def main():
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(n),
                 "avg_launch_us": round(k_avg_ms * 1e3, 2), "launches": k_launches,
-                "bytes_per_launch": tiles_bytes}
+                "timed_every_nth_wcycle": TIMING_STRIDE, "bytes_per_launch": tiles_bytes}
     if roofline["traffic"]:
         roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / tiles_bytes, 3)
     cgbs = copy_gbs()

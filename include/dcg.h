@@ -253,12 +253,15 @@ dcg_status dcg_bdf2_rhs(dcg_handle h, const double* s1, const double* s2, const 
 
 /* Live timing of the dominant kernel of the solve, the RAS tile solves of
  * the finest level (Section 4.2, (A_J)_i^{-1} applied to every block).
- * While enabled, every launch of that kernel made by dcg_solve on this
- * handle is bracketed by a pair of HIP events recorded on the solve's
- * stream (inside the captured W-cycle graph as event-record nodes); the
- * elapsed times are accumulated at the solver's convergence syncs.
- * Enabling or disabling discards the captured graph.  _read returns the
- * accumulated milliseconds and launch count since the last enable. */
+ * enable = k > 0: the finest-level launches of every k-th W-cycle made by
+ * dcg_solve on this handle (k = 1: every launch) are bracketed by a pair of
+ * HIP events recorded on the solve's stream (those launches are issued
+ * outside the captured graph); the elapsed times are accumulated at the
+ * solver's convergence syncs.  enable = 0 switches the timing off.  A
+ * recorded event costs a few microseconds of stream time, hence the
+ * sampling.  Enabling or disabling discards the captured graph.  _read
+ * returns the accumulated milliseconds and launch count since the last
+ * enable. */
 dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable);
 dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launches);
 /* The same for the A* product with the fused direction update of the CG outer

@@ -251,8 +251,9 @@ dcg_status dcg_bdf2_rhs(dcg_handle h, const double* s1, const double* s2, const 
 
 dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable) {
   if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  if (enable < 0) return fail(h, DCG_EINVAL, "enable must be >= 0");
   return guarded(h, [&]() {
-    dcg::kernel_timing(h, enable != 0);
+    dcg::kernel_timing(h, enable);
     return DCG_OK;
   });
 }

@@ -158,6 +158,8 @@ struct dcg_ctx {
   bool ktime = false;
   hipEvent_t kev[2 * kMaxTimed] = {};
   int krec = 0;                 // event pairs recorded by the current cycle
+  int kstride = 1;              // time the finest steps of every kstride-th W-cycle
+  int64_t kcycle = 0;           // W-cycles since timing was enabled
   double ktime_ms = 0.0;
   int64_t klaunches = 0;
   // and of the A* product with the direction update in the CG outer loop
@@ -180,7 +182,7 @@ namespace dcg {
 void handle_init(dcg_ctx* h);             // allocates the workspace
 dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* st,
                  hipStream_t stream);
-void kernel_timing(dcg_ctx* h, bool enable);
+void kernel_timing(dcg_ctx* h, int stride);   // 0 = off
 dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* in2, void* out,
                  hipStream_t stream);
 }  // namespace dcg

@@ -101,7 +101,7 @@ Cycle<T> make_cycle(dcg_ctx* h) {
   Cycle<T> c(*h->mesh, h->ws.lvb, h->mp.pre, h->mp.post);
   c.base = h->lbase;
   if (h->lbase > 0) c.cfdm = &h->cfdm;
-  if (h->ktime) {
+  if (h->ktime && h->kcycle++ % h->kstride == 0) {   // a sampled W-cycle
     c.timer.ev = h->kev;
     c.timer.max = dcg_ctx::kMaxTimed;
     c.timer.rec = &h->krec;
@@ -629,7 +629,8 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
   return status;
 }
 
-void kernel_timing(dcg_ctx* h, bool enable) {
+void kernel_timing(dcg_ctx* h, int stride) {
+  const bool enable = stride > 0;
   if (enable && !h->kev[0])
     for (hipEvent_t& e : h->kev) DCG_HIP(hipEventCreate(&e));
   if (enable && !h->aev[0])
@@ -641,6 +642,8 @@ void kernel_timing(dcg_ctx* h, bool enable) {
     h->wgraph = nullptr;
   }
   h->ktime = enable;
+  h->kstride = enable ? stride : 1;
+  h->kcycle = 0;
   h->krec = 0;
   h->ktime_ms = 0.0;
   h->klaunches = 0;

@@ -178,3 +178,20 @@ def test_full_size_four_levels_coarsest_solve_and_contraction():
     s.close()
     rho = np.linalg.norm(fh - L @ wh) / np.linalg.norm(fh)
     assert rho < 0.2, rho
+
+
+def test_coarsest_solve_on_a_128_grid_by_residual():
+    # n = 128 with one level: the fused passes with 2n = 256 (one thread group
+    # per column, no partial sums), checked by the residual against the
+    # oracle's SIPG Laplacian (the oracle's dense solve of 65,536 unknowns
+    # does not finish in seconds)
+    n = 128
+    L = d.sipg_laplacian(n).tocsr()
+    s = dcg.Solver(n, DT, prec="fp64", levels=1)
+    f = np.random.default_rng(12).standard_normal(4 * n * n)
+    out = torch.empty(4 * n * n, dtype=torch.float64, device="cuda")
+    s.apply(lib.DCG_OP_COARSE, _dev(f), out, level=1)
+    z = _host(out)
+    s.close()
+    assert np.isfinite(z).all()
+    assert np.linalg.norm(f - L @ z) <= 1e-9 * np.linalg.norm(f)

@@ -243,3 +243,26 @@ def test_no_deflation_is_plain_cg(n, dt):
     # deflation pays: the deflated solve of the same system takes fewer iterations
     ref_d = _oracle(n, dt, 0, 1e-8, inner="exact")
     assert ref_d.iterations < st.outer_iters
+
+
+def test_kernel_timing_samples_every_kth_wcycle():
+    # m1 + m2 = 4 finest-level RAS steps per W-cycle; with stride k the steps
+    # of W-cycles 0, k, 2k, ... since the enable are timed
+    s = dcg.Solver(64, 1e-3, prec="mixed")
+    b = torch.from_numpy(rhs(64, 2)).cuda()
+    x = torch.empty_like(b)
+    lib.dcg_kernel_timing(s.handle, 1)
+    _, st = s.solve(b, x, 1e-8)
+    ms1, n1 = lib.dcg_kernel_timing_read(s.handle)
+    assert n1 == 4 * st.total_wcycles and ms1 > 0
+    lib.dcg_kernel_timing(s.handle, 4)
+    _, st = s.solve(b, x, 1e-8)
+    ms4, n4 = lib.dcg_kernel_timing_read(s.handle)
+    assert n4 == 4 * ((st.total_wcycles + 3) // 4) and ms4 > 0
+    assert 0.5 < (ms4 / n4) / (ms1 / n1) < 2.0
+    lib.dcg_kernel_timing(s.handle, 0)
+    _, st = s.solve(b, x, 1e-8)
+    assert lib.dcg_kernel_timing_read(s.handle)[1] == 0
+    with pytest.raises(lib.DCGError):
+        lib.dcg_kernel_timing(s.handle, -1)
+    s.close()
