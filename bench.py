@@ -69,15 +69,16 @@ def sweep_bytes_per_square(s):
     the mean over the four steps of a level visit (zero start, two with the
     pending update, one with the prolongation).  Every step reads f and the
     weight and writes the tile outputs (128 per 16-square core); all but the
-    first read the 80 operator entries of the square and its iterate and
-    write the resolved iterate; the pending outputs (12 per square) or the
-    coarse iterate and its pending outputs (a quarter square's worth) come on
-    top.  The tile inverses are not charged per square: the uniform grid has
-    9 distinct local problems per level, read once (sweep_launch_bytes)."""
+    first read the square's iterate and write the resolved iterate; the
+    pending outputs (12 per square) or the coarse iterate and its pending
+    outputs (a quarter square's worth) come on top.  The tile inverses and
+    the level operator are not charged per square: on the uniform grid they
+    fall into 9 classes each (3 x 3 tile and square positions), read once per
+    launch (sweep_launch_bytes)."""
     base = 4 * s + 8 * s + s
     zero = base
-    pending = base + 80 * s + 4 * s + 12 * s + 4 * s
-    prolong = base + 80 * s + 4 * s + 4 * s + (4 * s + 12 * s) / 4
+    pending = base + 4 * s + 12 * s + 4 * s
+    prolong = base + 4 * s + 4 * s + (4 * s + 12 * s) / 4
     return (zero + 2 * pending + prolong) / 4
 
 
@@ -86,12 +87,14 @@ def sweep_bytes_per_square(s):
 # stream time, which timing all 80,900 launches of a solve would add to it.
 TIMING_STRIDE = 8
 
-SWEEP_CLASSES = 9    # distinct RAS local problems per level (3 x 3 tile positions)
+SWEEP_CLASSES = 9    # distinct RAS local problems and operator rows per level
 
 
 def sweep_launch_bytes(n, s):
-    """Algorithmic bytes of one RAS step on a level of n x n squares."""
-    return int(sweep_bytes_per_square(s) * n * n + SWEEP_CLASSES * 36 * 256 * s)
+    """Algorithmic bytes of one RAS step on a level of n x n squares: the
+    per-square vectors and, once, the 9 class inverses and the 9 class rows
+    of the level operator."""
+    return int(sweep_bytes_per_square(s) * n * n + SWEEP_CLASSES * (36 * 256 + 80) * s)
 
 
 # HBM traffic of one finest-level RAS launch at n = 512 (mixed form), from two
@@ -99,8 +102,8 @@ def sweep_launch_bytes(n, s):
 # each scaled by the reading of a plain 1 GiB copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE
 # 1 GiB).  Valid only for the kernel source it was taken on: the digest of the RAS kernel
 # sources must match, else the bench reports traffic as null.
-TRAFFIC = {"source_digest": "9b5580a635920db9", "n": 512,
-           "fetch_kib": 53428.2, "fetch_scale": 2.0, "write_kib": 15125.5, "write_scale": 1.0}
+TRAFFIC = {"source_digest": "069bc87c046ef773", "n": 512,
+           "fetch_kib": 15044.5, "fetch_scale": 2.0, "write_kib": 15062.6, "write_scale": 1.0}
 
 
 # The same counters for the 3D A* product k_astar3 at n = 32 (exact inner solve;

@@ -137,6 +137,37 @@ void upload_factors(const HostLevel& hl, T* dev) {
   }
 }
 
+// The level operator's blocks per square class ([9][5][4][4], see
+// square_class), when every square of a class carries bit-identical blocks
+// (the uniform grid); empty otherwise.
+std::vector<double> square_class_table(const HostLevel& hl) {
+  const int n = hl.n;
+  if (n < 3) return {};
+  std::vector<double> Lc(9 * kSlots * 16, 0.0);
+  std::vector<char> seen(9, 0);
+  for (int64_t e = 0; e < int64_t(n) * n; ++e) {
+    const int c = square_class(int(e % n), int(e / n), n);
+    const double* src = &hl.L[e * kSlots * 16];
+    double* dst = &Lc[size_t(c) * kSlots * 16];
+    if (!seen[c]) {
+      std::memcpy(dst, src, sizeof(double) * kSlots * 16);
+      seen[c] = 1;
+    } else if (std::memcmp(dst, src, sizeof(double) * kSlots * 16) != 0) {
+      return {};
+    }
+  }
+  return Lc;
+}
+
+template <typename T>
+T* upload_class_table(MeshContext* ctx, const std::vector<double>& Lc) {
+  if (Lc.empty()) return nullptr;
+  std::vector<T> t(Lc.begin(), Lc.end());
+  T* dev = static_cast<T*>(ctx->alloc(sizeof(T) * t.size()));
+  DCG_HIP(hipMemcpy(dev, t.data(), sizeof(T) * t.size(), hipMemcpyHostToDevice));
+  return dev;
+}
+
 template <typename T>
 void upload_weights(const HostLevel& hl, T* dev) {
   std::vector<T> t(hl.dw.size());
@@ -194,6 +225,7 @@ std::shared_ptr<MeshContext> build_context(int device, int n, double penalty) {
     // level and the FP64 form at every level
     dl.L64 = static_cast<double*>(ctx->alloc(sizeof(double) * dl.ne * kSlots * 16));
     upload_level_L<double>(hl, dl.L64);
+    dl.Lc64 = upload_class_table<double>(ctx.get(), square_class_table(hl));
     if (k >= 2) {
       dl.tiles = hl.tiles;
       dl.tile_ext = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_ext.size()));
@@ -233,6 +265,7 @@ void MeshContext::ensure_factors(bool fp32) {
     if (fp32) {
       dl.L32 = static_cast<float*>(alloc(sizeof(float) * dl.ne * kSlots * 16));
       upload_level_L<float>(hl, dl.L32);
+      dl.Lc32 = upload_class_table<float>(this, square_class_table(hl));
     }
     if (k >= 2) {
       const size_t cnt = size_t(dl.classes) * 36 * 256;

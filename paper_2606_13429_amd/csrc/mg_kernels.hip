@@ -47,6 +47,14 @@ __device__ inline void add_pending(const T* Ye, int e, T z[4]) {
   for (int j = 0; j < 4; ++j) z[j] = ((z[j] + y0[j]) + y1[j]) + y2[j];
 }
 
+// Row j of block s of the level operator at square e: from the class table
+// when there is one, else from the per-square array.
+template <typename T, typename Args>
+__device__ __forceinline__ const T* op_row(const Args& a, int s, int e, int j) {
+  if (a.Lc) return a.Lc + (square_class(e % a.n, e / a.n, a.n) * 5 + s) * 16 + 4 * j;
+  return a.L + (((int64_t)s * a.ne + e) * 4 + j) * 4;
+}
+
 template <typename T>
 __device__ inline void current_z(const SweepArgs<T>& a, int e, T z[4]) {
   if (a.has_z) {
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs<T> a) {
             const bool in = ex + dx >= 0 && ex + dx < a.n && ey + dy >= 0 && ey + dy < a.n;
             if (in && need_z) {
               nb[u][s] = nbr_slot(p, s);
-              if constexpr (HOIST) ld4(a.L + (((int64_t)s * a.ne + e) * 4 + j) * 4, lrow[u][s]);
+              if constexpr (HOIST) ld4(op_row<T>(a, s, e, j), lrow[u][s]);
             }
           }
         }
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs<T> a) {
         if constexpr (HOIST) {
           l[0] = lrow[u][s][0]; l[1] = lrow[u][s][1]; l[2] = lrow[u][s][2]; l[3] = lrow[u][s][3];
         } else {
-          ld4(a.L + (((int64_t)s * a.ne + esq[u]) * 4 + (i & 3)) * 4, l);
+          ld4(op_row<T>(a, s, esq[u], i & 3), l);
         }
         acc += l[0] * zn[tl][q][0] + l[1] * zn[tl][q][1] + l[2] * zn[tl][q][2] + l[3] * zn[tl][q][3];
       }
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict_res(RestrictArgs<T> a) {
       if (a.has_y) add_pending(a.Y_old, c, z);
       if (s == 0 && a.write_z) a.z_new[4 * (int64_t)e + j] = z[j];
       T l[4];
-      ld4(a.L + (((int64_t)s * a.ne + e) * 4 + j) * 4, l);
+      ld4(op_row<T>(a, s, e, j), l);
       acc += l[0] * z[0] + l[1] * z[1] + l[2] * z[2] + l[3] * z[3];
     }
     rv = a.f[4 * (int64_t)e + j] - acc;

@@ -32,6 +32,12 @@ inline const float* level_L<float>(const DeviceLevel& d) { return d.L32; }
 template <>
 inline const double* level_L<double>(const DeviceLevel& d) { return d.L64; }
 template <typename T>
+const T* level_Lc(const DeviceLevel& d);
+template <>
+inline const float* level_Lc<float>(const DeviceLevel& d) { return d.Lc32; }
+template <>
+inline const double* level_Lc<double>(const DeviceLevel& d) { return d.Lc64; }
+template <typename T>
 const T* level_dw(const DeviceLevel& d);
 template <>
 inline const float* level_dw<float>(const DeviceLevel& d) { return d.dw32; }
@@ -79,6 +85,7 @@ struct Cycle {
     a.n = d.n;
     a.ne = d.ne;
     a.L = level_L<T>(d);
+    a.Lc = level_Lc<T>(d);
     a.cols = d.cols;
     a.dst = d.tile_dst;
     a.f = f(k);
@@ -119,6 +126,7 @@ struct Cycle {
     a.n = d.n;
     a.ne = d.ne;
     a.L = level_L<T>(d);
+    a.Lc = level_Lc<T>(d);
     a.cols = d.cols;
     a.f = f(k);
     a.has_z = s.has_z;
