@@ -138,11 +138,11 @@ void upload_factors(const HostLevel& hl, T* dev) {
 }
 
 // The level operator's blocks per square class ([9][5][4][4], see
-// square_class), when every square of a class carries bit-identical blocks
-// (the uniform grid); empty otherwise.
+// square_class); every square of a class must carry bit-identical blocks,
+// which the uniform grid guarantees and this checks.
 std::vector<double> square_class_table(const HostLevel& hl) {
   const int n = hl.n;
-  if (n < 3) return {};
+  if (n < 3) throw Error(DCG_EINVAL, "level grid below 3 x 3 squares");
   std::vector<double> Lc(9 * kSlots * 16, 0.0);
   std::vector<char> seen(9, 0);
   for (int64_t e = 0; e < int64_t(n) * n; ++e) {
@@ -153,7 +153,7 @@ std::vector<double> square_class_table(const HostLevel& hl) {
       std::memcpy(dst, src, sizeof(double) * kSlots * 16);
       seen[c] = 1;
     } else if (std::memcmp(dst, src, sizeof(double) * kSlots * 16) != 0) {
-      return {};
+      throw Error(DCG_EINVAL, "level operator blocks differ within a square class");
     }
   }
   return Lc;
@@ -161,7 +161,6 @@ std::vector<double> square_class_table(const HostLevel& hl) {
 
 template <typename T>
 T* upload_class_table(MeshContext* ctx, const std::vector<double>& Lc) {
-  if (Lc.empty()) return nullptr;
   std::vector<T> t(Lc.begin(), Lc.end());
   T* dev = static_cast<T*>(ctx->alloc(sizeof(T) * t.size()));
   DCG_HIP(hipMemcpy(dev, t.data(), sizeof(T) * t.size(), hipMemcpyHostToDevice));

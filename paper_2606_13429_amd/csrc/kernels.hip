@@ -491,9 +491,8 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, double c,
 // Thread (square e, row a): one workgroup = 64 squares.
 template <typename T, bool FIRST>
 __global__ __launch_bounds__(kThreads) void k_refine_residual(
-    const double* __restrict__ L, const double* __restrict__ Lc, const int32_t* __restrict__ cols,
-    int n, int ne, const double* __restrict__ s, const double* __restrict__ z, T* __restrict__ fJ,
-    double* __restrict__ part, Slots sl) {
+    const double* __restrict__ Lc, int n, int ne, const double* __restrict__ s,
+    const double* __restrict__ z, T* __restrict__ fJ, double* __restrict__ part, Slots sl) {
   __shared__ double lds[4];
   const int slot = slot_id(sl);
   s += slot * sl.sstride;
@@ -507,7 +506,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_residual(
     const int e = (g << 6) + (threadIdx.x >> 2);
     if (e >= ne) continue;
     double acc = 0.0;
-    if (!FIRST && Lc) {          // blocks of the square's class, neighbours from (ex, ey)
+    if (!FIRST) {                // blocks of the square's class, neighbours from (ex, ey)
       const int ex = e % n, ey = e / n;
       const double* Le = Lc + square_class(ex, ey, n) * 80 + 4 * a;
 #pragma unroll
@@ -517,16 +516,6 @@ __global__ __launch_bounds__(kThreads) void k_refine_residual(
         double l[4], zc[4];
         ld4(Le + 16 * sn, l);
         ld4(z + 4 * ((int64_t)e + dx + (int64_t)dy * n), zc);
-        acc += l[0] * zc[0] + l[1] * zc[1] + l[2] * zc[2] + l[3] * zc[3];
-      }
-    } else if (!FIRST) {
-#pragma unroll
-      for (int sn = 0; sn < 5; ++sn) {
-        const int col = cols[sn * ne + e];
-        if (col < 0) continue;
-        double l[4], zc[4];
-        ld4(L + (((int64_t)sn * ne + e) * 4 + a) * 4, l);
-        ld4(z + 4 * (int64_t)col, zc);
         acc += l[0] * zc[0] + l[1] * zc[1] + l[2] * zc[2] + l[3] * zc[3];
       }
     }
@@ -779,16 +768,15 @@ hipError_t launch_scale(int64_t n, double c, const double* in, double* out, hipS
 int refine_blocks(int ne) { return grid_for(ne, 64, kPartStride); }
 
 template <typename T>
-hipError_t launch_refine_residual(bool first, const double* L64, const double* Lc64,
-                                  const int32_t* cols, int n, int ne, const double* s,
+hipError_t launch_refine_residual(bool first, const double* Lc64, int n, int ne, const double* s,
                                   const double* z, T* fJ, double* part, hipStream_t st,
                                   const Slots& sl, int count) {
-  if (Lc64 && int64_t(n) * n != ne) return hipErrorInvalidValue;
+  if (!Lc64 || n < 3 || int64_t(n) * n != ne) return hipErrorInvalidValue;
   const dim3 grid(refine_blocks(ne), count);
   if (first)
-    k_refine_residual<T, true><<<grid, kThreads, 0, st>>>(L64, Lc64, cols, n, ne, s, z, fJ, part, sl);
+    k_refine_residual<T, true><<<grid, kThreads, 0, st>>>(Lc64, n, ne, s, z, fJ, part, sl);
   else
-    k_refine_residual<T, false><<<grid, kThreads, 0, st>>>(L64, Lc64, cols, n, ne, s, z, fJ, part, sl);
+    k_refine_residual<T, false><<<grid, kThreads, 0, st>>>(Lc64, n, ne, s, z, fJ, part, sl);
   return hipGetLastError();
 }
 
@@ -837,8 +825,7 @@ hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st) {
 }
 
 #define DCG_INSTANTIATE(T)                                                                      \
-  template hipError_t launch_refine_residual<T>(bool, const double*, const double*,            \
-                                                const int32_t*, int, int, const double*,       \
+  template hipError_t launch_refine_residual<T>(bool, const double*, int, int, const double*,  \
                                                 const double*, T*, double*, hipStream_t,       \
                                                 const Slots&, int);                            \
   template hipError_t launch_lap<T>(bool, const T*, const int32_t*, int, const T*, const T*, T*, \

@@ -88,8 +88,8 @@ enum AstarMode : int {
 // L_k at square (ex, ey) depend only on whether the square touches the left
 // or right (bottom or top) side of the domain, so 3 x 3 classes, 3 cy + cx
 // with cx = 0 at ex = 0, 2 at ex = n - 1, 1 otherwise.  A class table
-// Lc [class 9][slot 5][row 4][4] holds one copy per class; the host builds it
-// only when every square of a class carries bit-identical blocks.
+// Lc [class 9][slot 5][row 4][4] holds one copy per class; the host checks
+// that every square of a class carries bit-identical blocks.
 __host__ __device__ inline int square_class(int ex, int ey, int n) {
   const int cx = ex == 0 ? 0 : (ex == n - 1 ? 2 : 1);
   const int cy = ey == 0 ? 0 : (ey == n - 1 ? 2 : 1);
@@ -152,12 +152,10 @@ hipError_t launch_fcg_direction(int64_t n, const double* r, const double* const*
                                 int m, int R, const double* coef, double* d, double* part,
                                 int* nblocks, hipStream_t st);
 
-// inner refinement (FP64 residual of the level-J Laplacian); Lc64 (may be
-// nullptr): the class table of L64 on the n x n grid, read instead of L64 and
-// cols
+// inner refinement (FP64 residual of the level-J Laplacian): Lc64 is the
+// class table of L_J on the n x n grid (ne = n^2 squares)
 template <typename T>
-hipError_t launch_refine_residual(bool first, const double* L64, const double* Lc64,
-                                  const int32_t* cols, int n, int ne, const double* s,
+hipError_t launch_refine_residual(bool first, const double* Lc64, int n, int ne, const double* s,
                                   const double* z, T* fJ, double* part, hipStream_t st,
                                   const Slots& sl = Slots(), int count = 1);
 
@@ -188,8 +186,8 @@ struct SweepArgs {
   const T* dw = nullptr;            // [ne] partition-of-unity weight 1 / #blocks
   const int32_t* ext = nullptr;     // [tiles][52] block squares + outside neighbours
   int tiles = 0, n = 0, ne = 0;
-  const T* L = nullptr;             // level operator [5][ne][4][4]
-  const T* Lc = nullptr;            // its class table [9][5][4][4], or nullptr
+  const T* L = nullptr;             // level operator [5][ne][4][4] (batched kernels)
+  const T* Lc = nullptr;            // its class table [9][5][4][4]
   const int32_t* cols = nullptr;    // [5][ne]
   const int32_t* dst = nullptr;     // [tiles][32] pending slot 3 e + k of each block square
   const T* f = nullptr;
@@ -207,7 +205,7 @@ template <typename T>
 struct RestrictArgs {
   int n = 0, ne = 0;                // fine level
   const T* L = nullptr;
-  const T* Lc = nullptr;            // class table of L, or nullptr
+  const T* Lc = nullptr;            // class table of L
   const int32_t* cols = nullptr;
   const T* f = nullptr;
   const T* z_old = nullptr;

@@ -47,12 +47,10 @@ __device__ inline void add_pending(const T* Ye, int e, T z[4]) {
   for (int j = 0; j < 4; ++j) z[j] = ((z[j] + y0[j]) + y1[j]) + y2[j];
 }
 
-// Row j of block s of the level operator at square e: from the class table
-// when there is one, else from the per-square array.
+// Row j of block s of the level operator at square e, from its class table.
 template <typename T, typename Args>
 __device__ __forceinline__ const T* op_row(const Args& a, int s, int e, int j) {
-  if (a.Lc) return a.Lc + (square_class(e % a.n, e / a.n, a.n) * 5 + s) * 16 + 4 * j;
-  return a.L + (((int64_t)s * a.ne + e) * 4 + j) * 4;
+  return a.Lc + (square_class(e % a.n, e / a.n, a.n) * 5 + s) * 16 + 4 * j;
 }
 
 template <typename T>

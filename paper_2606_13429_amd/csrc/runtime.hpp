@@ -30,8 +30,8 @@ struct DeviceLevel {
   int32_t* cols = nullptr;        // [5][ne]
   double* L64 = nullptr;          // [5][ne][4][4]
   float* L32 = nullptr;
-  double* Lc64 = nullptr;         // class tables [9][5][4][4] of L64 / L32 (nullptr when
-  float* Lc32 = nullptr;          // the squares of a class differ)
+  double* Lc64 = nullptr;         // class tables [9][5][4][4] of L64 / L32
+  float* Lc32 = nullptr;
   int tiles = 0;                  // levels >= 2
   int32_t* tile_ext = nullptr;    // [tiles][52]
   int32_t* tile_dst = nullptr;    // [tiles][32]

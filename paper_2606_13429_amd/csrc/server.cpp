@@ -478,7 +478,7 @@ void Server::Impl::enqueue_step(Group& g) {
     using T = decltype(tag);
     T* fJ = static_cast<T*>(g.ws.lvb.f[m.J - 1]);
     if (cnt(kLInnerStart)) {
-      DCG_HIP(launch_refine_residual<T>(true, fine.L64, fine.Lc64, fine.cols, fine.n, fine.ne, g.s, nullptr, fJ,
+      DCG_HIP(launch_refine_residual<T>(true, fine.Lc64, fine.n, fine.ne, g.s, nullptr, fJ,
                                         g.ws.part, st, sl(kLInnerStart), cnt(kLInnerStart)));
       DCG_HIP(launch_reduce(g.ws.part, nbR, kRedS2, g.ws.sc, st, sl(kLInnerStart),
                             cnt(kLInnerStart)));
@@ -518,7 +518,7 @@ void Server::Impl::enqueue_step(Group& g) {
     if (cnt(kLAddMore))
       DCG_HIP(launch_refine_add<T>(fine.ne, false, fs.has_z, fs.has_y, zJ, YJ, g.zref, st,
                                    sl(kLAddMore), cnt(kLAddMore)));
-    DCG_HIP(launch_refine_residual<T>(false, fine.L64, fine.Lc64, fine.cols, fine.n, fine.ne, g.s, g.zref, fJ,
+    DCG_HIP(launch_refine_residual<T>(false, fine.Lc64, fine.n, fine.ne, g.s, g.zref, fJ,
                                       g.ws.part, st, sl(kLInnerAll), cnt(kLInnerAll)));
     DCG_HIP(launch_reduce(g.ws.part, nbR, kRedR2, g.ws.sc, st, sl(kLInnerAll), cnt(kLInnerAll)));
   };

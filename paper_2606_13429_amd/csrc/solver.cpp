@@ -198,8 +198,8 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
   const int64_t mlen = 4 * int64_t(fine.ne);
   T* fJ = static_cast<T*>(h->ws.lvb.f[m.J - 1]);
   const int nb = refine_blocks(fine.ne);
-  DCG_HIP(launch_refine_residual<T>(true, fine.L64, fine.Lc64, fine.cols, fine.n, fine.ne, s, nullptr,
-                                    fJ, h->ws.part, st));
+  DCG_HIP(launch_refine_residual<T>(true, fine.Lc64, fine.n, fine.ne, s, nullptr, fJ, h->ws.part,
+                                    st));
   DCG_HIP(launch_reduce(h->ws.part, nb, kRedS2, h->ws.sc, st));
   read_scalars(h, st);
   const double s2 = h->ws.sc_host->s2;
@@ -213,8 +213,8 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
       DCG_HIP(launch_refine_add<T>(fine.ne, cycles == 0, fs.has_z, fs.has_y,
                                    static_cast<T*>(h->ws.lvb.z[fs.zb][m.J - 1]),
                                    static_cast<T*>(h->ws.lvb.Y[fs.yb][m.J - 1]), z, st));
-      DCG_HIP(launch_refine_residual<T>(false, fine.L64, fine.Lc64, fine.cols, fine.n, fine.ne, s, z,
-                                        fJ, h->ws.part, st));
+      DCG_HIP(launch_refine_residual<T>(false, fine.Lc64, fine.n, fine.ne, s, z, fJ, h->ws.part,
+                                        st));
       DCG_HIP(launch_reduce(h->ws.part, nb, kRedR2, h->ws.sc, st));
       read_scalars(h, st);
       collect_kernel_times(h);
