@@ -102,8 +102,8 @@ def sweep_launch_bytes(n, s):
 # each scaled by the reading of a plain 1 GiB copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE
 # 1 GiB).  Valid only for the kernel source it was taken on: the digest of the RAS kernel
 # sources must match, else the bench reports traffic as null.
-TRAFFIC = {"source_digest": "069bc87c046ef773", "n": 512,
-           "fetch_kib": 15044.5, "fetch_scale": 2.0, "write_kib": 15062.6, "write_scale": 1.0}
+TRAFFIC = {"source_digest": "979fa51417d1a7ed", "n": 512,
+           "fetch_kib": 15036.3, "fetch_scale": 2.0, "write_kib": 15062.7, "write_scale": 1.0}
 
 
 # The same counters for the 3D A* product k_astar3 at n = 32 (exact inner solve;
