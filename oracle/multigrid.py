@@ -7,8 +7,10 @@ Galerkin hierarchy of Algorithm 2 (Z_{k-1} = I_k^{k-1} Z_k I_{k-1}^k).
 
 Readings where the paper is silent or written for other meshes:
 * Levels: the finest grid has n x n squares, each coarser level agglomerates
-  2 x 2 squares, and the coarsest level k = 1 is always 16 x 16 squares, so
-  J = log2(n / 16) + 1.
+  2 x 2 squares, and the coarsest level k = 1 has 16 x 16 squares by default,
+  so J = log2(n / 16) + 1; a shorter hierarchy (the four levels of the
+  paper's experiments, Section 5) stops at a larger coarsest grid
+  (``coarsest``), J = log2(n / coarsest) + 1, still solved exactly.
 * Coarse spaces are DG-Q1 on the agglomerated squares.  They are nested, so
   the L2-projection prolongation of Section 4.2 is the exact injection of a
   coarse Q1 function into the four fine squares (coefficients in

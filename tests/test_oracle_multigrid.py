@@ -10,6 +10,8 @@ from oracle import multigrid as mg
 
 def test_num_levels():
     assert [mg.num_levels(n) for n in (16, 32, 128, 512, 1024)] == [1, 2, 4, 6, 7]
+    # shortened hierarchies: the four levels of Section 5 at n = 512 stop at 64 x 64
+    assert [mg.num_levels(n, c) for n, c in ((512, 64), (64, 32), (32, 32), (1024, 128))] == [4, 2, 1, 4]
     for bad in (8, 48, 100):
         with pytest.raises(ValueError):
             mg.num_levels(bad)
