@@ -648,7 +648,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only; the solve is not sharded across "
+        print("bench.py: this benchmark measures one GPU only; the solve is not sharded across "
               "GPUs (multi-GPU sharding is a design note).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
