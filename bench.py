@@ -730,6 +730,11 @@ def main():
                 "timed_every_nth_wcycle": TIMING_STRIDE, "bytes_per_launch": tiles_bytes}
     if roofline["traffic"]:
         roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / tiles_bytes, 3)
+    # the class inverses every tile reads from L2 (36 packed 16 x 16 FP32 blocks
+    # per tile): the stream that bounds the step now that its HBM bytes are vectors
+    tiles = (n // 4) * (n // 4)
+    roofline["l2_factor_bytes_per_launch"] = tiles * 36 * 256 * 4
+    roofline["l2_factor_gbs"] = round(tiles * 36 * 256 * 4 / (k_avg_ms * 1e-3) / 1e9, 1)
     cgbs = copy_gbs()
     roofline["copy_gbs"] = round(cgbs, 1)
     roofline["frac_of_copy"] = round(achieved / cgbs, 4)
