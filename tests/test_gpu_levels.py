@@ -195,3 +195,31 @@ def test_coarsest_solve_on_a_128_grid_by_residual():
     s.close()
     assert np.isfinite(z).all()
     assert np.linalg.norm(f - L @ z) <= 1e-9 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("outer,c_A", [("fcg1", 0.01), ("cg", 0.01)])
+def test_adaptive_tolerance_on_shortened_hierarchy_matches_oracle(outer, c_A):
+    # the adaptive inner tolerance of eq. (tol) with a two-level hierarchy
+    # (exact 32 x 32 coarsest level) against the oracle with the same depth;
+    # the same gate as the full-hierarchy variant tests
+    n, dt, tol, levels = 64, 1e-3, 1e-8, 2
+    As = d.operator(n, dt)
+    V = d.deflation_basis(n)
+    E = (V.T @ As @ V).tocsr()
+    f = elem_to_comp(rhs(n, 6), n)
+    kw = dict(outer="fcg", m_max=1) if outer == "fcg1" else dict(outer="cg")
+    ref = kr.dcg(As, V, f, kr.mg_inner(mg.Hierarchy(E, n, coarsest=n >> (levels - 1))), tol=tol,
+                 c_A=c_A, **kw)
+    s = dcg.Solver(n, dt, prec="mixed", outer=outer, c_A=c_A, levels=levels)
+    b = torch.from_numpy(rhs(n, 6)).cuda()
+    x = torch.empty_like(b)
+    status, st = s.solve(b, x, tol)
+    torch.cuda.synchronize()
+    s.close()
+    xr = comp_to_elem(ref.x, n)
+    assert status == lib.DCG_OK
+    assert abs(st.outer_iters - ref.iterations) <= 2, (st.outer_iters, ref.iterations)
+    assert st.rel_res_recurrence <= tol
+    assert _relerr(x.cpu().numpy(), xr) <= 1e-8
+    assert abs(st.total_wcycles - ref.total_cycles) <= 0.02 * ref.total_cycles + 10
+    assert st.rel_res_true <= max(1.5 * ref.rel_res_true, 2 * tol)
