@@ -158,8 +158,13 @@ void dcg_defaults(dcg_mesh* mesh, dcg_options* opt);
  * context -- A_div, the element mass blocks, A_div Z, the Galerkin multigrid
  * hierarchy of L (Algorithm 2: Z_{k-1} = I Z_k I), the RAS tile inverses and
  * the coarsest inverse -- on the current device, and a solver handle for the
- * scalars dt > 0, nu > 0.  opt may be NULL (defaults).  Returns DCG_EINVAL
- * for unsupported n / parameters, DCG_ENOMEM when device memory runs out. */
+ * scalars dt > 0, nu > 0.  On the uniform grid the RAS local problems and the
+ * level operators' blocks fall into 9 bit-identical classes per level
+ * (interior, edges, corners); the context stores one tile inverse and one set
+ * of operator blocks per class (setup checks the bit identity).  With
+ * opt->levels > 0 the handle also holds the fast-diagonalisation factors of
+ * its coarsest level.  opt may be NULL (defaults).  Returns DCG_EINVAL for
+ * unsupported n / parameters, DCG_ENOMEM when device memory runs out. */
 dcg_status dcg_setup(const dcg_mesh* mesh, double dt, double nu,
                      const dcg_options* opt, dcg_handle* out);
 
