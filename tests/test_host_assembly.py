@@ -187,3 +187,66 @@ def test_coarse_level_factors_reject_bad_levels():
         lib.dcg_host_assemble(_mesh(64), 7, 4)       # J = 3 at n = 64
     with pytest.raises(lib.DCGError):
         lib.dcg_host_assemble(_mesh(1024), 7, 2)     # coarsest 512 > 256
+
+
+def _square_class(ex, ey, n):
+    cx = 0 if ex == 0 else (2 if ex == n - 1 else 1)
+    cy = 0 if ey == 0 else (2 if ey == n - 1 else 1)
+    return 3 * cy + cx
+
+
+def test_level_operator_blocks_depend_only_on_the_square_class():
+    # the device keeps one set of the five 4 x 4 blocks of L_k per class of
+    # squares (left / interior / right times bottom / interior / top); the
+    # library's host blocks must be bit-identical within a class (setup refuses
+    # otherwise), and the oracle's own Galerkin hierarchy must show the same
+    # structure (translation invariance of the uniform grid and of P^T L P)
+    n = 64
+    As = d.operator(n, 2.0)
+    V = d.deflation_basis(n)
+    H = mg.Hierarchy((V.T @ As @ V).tocsr(), n)
+    steps = [(0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)]
+    for k in range(1, H.J + 1):
+        nk = H.n[k]
+        vals, cols = lib.dcg_host_assemble(_mesh(n), 3, k)
+        blocks = vals.reshape(nk * nk, 5, 4, 4)
+        A = H.A[k].tocsr()
+        rep_lib, rep_orc = {}, {}
+        for e in range(nk * nk):
+            ex, ey = e % nk, e // nk
+            c = _square_class(ex, ey, nk)
+            orc = np.zeros((5, 4, 4))
+            for s, (dx, dy) in enumerate(steps):
+                if 0 <= ex + dx < nk and 0 <= ey + dy < nk:
+                    f = e + dx + dy * nk
+                    orc[s] = A[4 * e:4 * e + 4, 4 * f:4 * f + 4].toarray()
+            if c not in rep_lib:
+                rep_lib[c], rep_orc[c] = blocks[e].copy(), orc
+                continue
+            assert np.array_equal(blocks[e], rep_lib[c]), (k, e)
+            assert np.abs(orc - rep_orc[c]).max() <= 1e-12 * np.abs(rep_orc[c]).max(), (k, e)
+        assert sorted(rep_lib) == list(range(9))
+        for c in range(9):          # and the library's class blocks are the oracle's
+            assert np.abs(rep_lib[c] - rep_orc[c]).max() <= 1e-12 * np.abs(rep_orc[c]).max()
+
+
+def test_tile_inverses_fall_into_nine_position_classes():
+    # the device stores one inverse per class of tiles; on the uniform grid the
+    # local problem (L_k)_i and its weights D_i depend only on whether the tile
+    # touches the left / right and bottom / top sides
+    n = 64
+    for k in (2, 3):
+        vals, cols = lib.dcg_host_assemble(_mesh(n), 4, k)
+        T = vals.size // (128 * 128)
+        inv = vals.reshape(T, 128, 128)
+        side = int(round(T ** 0.5))
+        rep = {}
+        for t in range(T):
+            c = _square_class(t % side, t // side, side)
+            if c in rep:
+                assert np.array_equal(inv[t], inv[rep[c]]), (k, t)
+            else:
+                rep[c] = t
+        assert len(rep) == 9
+        distinct = {inv[t].tobytes() for t in rep.values()}
+        assert len(distinct) == 9
