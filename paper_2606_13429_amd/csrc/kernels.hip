@@ -46,13 +46,6 @@ __device__ inline void ld4(const double* p, double v[4]) {
   const double2 b = reinterpret_cast<const double2*>(p)[1];
   v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
-__device__ inline void st4(float* p, const float v[4]) {
-  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-__device__ inline void st4(double* p, const double v[4]) {
-  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
-  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
-}
 
 inline int grid_for(int64_t items, int per_block, int cap) {
   int64_t g = (items + per_block - 1) / per_block;
