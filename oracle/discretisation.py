@@ -428,17 +428,3 @@ def interpolate(n, fun):
     """DG-Q1 nodal interpolant of fun(x, y) (exact for bilinear fun)."""
     xy = node_coordinates(n)
     return np.array([fun(x, y) for x, y in xy])
-
-
-def load_vector(n, values_at_points):
-    """f[4e + j] = int_K F phi_j by 2x2 Gauss, where
-    ``values_at_points[e, qy, qx]`` holds F at the Gauss point
-    (ex + g_qx) h, (ey + g_qy) h of element e."""
-    h = 1.0 / n
-    f = np.zeros(4 * n * n)
-    for e in range(n * n):
-        for qy, (gy, wy) in enumerate(zip(GAUSS_POINTS, GAUSS_WEIGHTS)):
-            for qx, (gx, wx) in enumerate(zip(GAUSS_POINTS, GAUSS_WEIGHTS)):
-                for j in range(4):
-                    f[4 * e + j] += wx * wy * h * h * values_at_points[e, qy, qx] * q1_value(j, gx, gy)
-    return f

@@ -3,7 +3,11 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Follows Section 4.2 and Algorithms 3 (Multigrid) and 4 (Wcycle), with the
-Galerkin hierarchy of Algorithm 2 (Z_{k-1} = I_k^{k-1} Z_k I_{k-1}^k).
+Galerkin hierarchy of Algorithm 2 (each coarse operator is the fine one
+multiplied by the prolongation on the right and its transpose on the left).
+The W-cycle is written from its definition: smoothing by the Schwarz
+operator, a coarse-grid correction made of gamma = 2 cycles of the next
+coarser level, smoothing again; the exact solve on level 1.
 
 Readings where the paper is silent or written for other meshes:
 * Levels: the finest grid has n x n squares, each coarser level agglomerates
@@ -28,8 +32,9 @@ Readings where the paper is silent or written for other meshes:
 Parity status: pinned.  Prolongation exactness on Q1 functions, the Galerkin
 identity against direct coarse assembly, the partition of unity, the RAS
 special cases (one block = exact solve; 1x1 non-overlapping blocks = block
-Jacobi), the coarsest Cholesky and one two-grid W-cycle against its dense
-error-propagation matrix are checked in tests/test_oracle_multigrid.py.
+Jacobi), the coarsest Cholesky and the two- and three-level W-cycles
+against their dense error-propagation matrices are checked in
+tests/test_oracle_multigrid.py.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -147,21 +152,39 @@ class Hierarchy:
         self.chol = sla.cho_factor(self.A[1].toarray(), lower=True)
 
 
+def smooth(H, k, f, z, steps):
+    """``steps`` RAS smoothing steps z <- z + S_k (f - A_k z) on level k
+    (Section 4.2: the smoother is the Schwarz operator S_k applied to the
+    current residual)."""
+    for _ in range(steps):
+        z = z + H.S[k].apply(f - H.A[k] @ z)
+    return z
+
+
+def coarse_correction(H, k, residual, m1, m2, gamma=2):
+    """Correction from level k - 1 for the level-k residual (Section 4.2).
+
+    The residual is restricted with P_k^T, the coarse problem
+    A_{k-1} c = P_k^T residual is approximated by ``gamma`` successive
+    level-(k-1) cycles started from c = 0 (gamma = 2: the W-cycle), and the
+    result is prolongated with P_k.  On level 1 a cycle is the exact solve,
+    so every repetition returns the same vector."""
+    rhs = H.P[k].T @ residual
+    c = np.zeros_like(rhs)
+    for _ in range(gamma):
+        c = wcycle(H, rhs, c, k - 1, m1, m2)
+    return H.P[k] @ c
+
+
 def wcycle(H, f, z0, k, m1=2, m2=2):
-    """One W-cycle on level k (Algorithm 4)."""
+    """One W-cycle for A_k z = f from the guess z0 (Algorithm 4): the exact
+    solve on level 1, otherwise m1 smoothing steps, the coarse-grid
+    correction with two coarse cycles, and m2 smoothing steps."""
     if k == 1:
         return sla.cho_solve(H.chol, f)
-    A, S = H.A[k], H.S[k]
-    z = z0.copy()
-    for _ in range(m1):                                   # pre-smoothing
-        z = z + S.apply(f - A @ z)
-    r_c = H.P[k].T @ (f - A @ z)                          # restriction
-    e_bar = wcycle(H, r_c, np.zeros_like(r_c), k - 1, m1, m2)
-    e = wcycle(H, r_c, e_bar, k - 1, m1, m2)
-    z = z + H.P[k] @ e                                    # prolongation
-    for _ in range(m2):                                   # post-smoothing
-        z = z + S.apply(f - A @ z)
-    return z
+    z = smooth(H, k, f, z0.copy(), m1)
+    z = z + coarse_correction(H, k, f - H.A[k] @ z, m1, m2)
+    return smooth(H, k, f, z, m2)
 
 
 def multigrid(H, f, z0=None, m1=2, m2=2, tol=1e-10, n_max=100):

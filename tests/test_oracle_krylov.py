@@ -248,3 +248,117 @@ def test_gmres_with_adaptive_inexact_inner_solves_converges():
     # and, as for the CG family (Table 3), the relaxed inner solves cost fewer cycles
     fixed = kr.dcg(As, V, f, kr.mg_inner(H), tol=tol, outer='gmres', c_F=0.01, max_iter=1000)
     assert r.total_cycles < 0.8 * fixed.total_cycles, (r.total_cycles, fixed.total_cycles)
+
+
+# ---------------------------------------------------------------------------
+# The truncation window of FCG(m_max) (Algorithm 1 with Remark 5's
+# m_0 = 0, m_i = max{1, mod(i, m_max + 1)}), pinned with an inexact
+# multigrid inner solve: with a varying (non-symmetric) effective operator
+# the kept directions matter, which an exact inner solve (where every
+# truncation reduces to CG) cannot show.
+# ---------------------------------------------------------------------------
+def _inexact_fcg_problem():
+    # two-grid inner solve (16 x 16 -> 8 x 8) stopped at a relative residual
+    # of 1e-2 (c_F tol = 1e6 * 1e-8): one or two W-cycles per inner solve
+    n, dt = 16, 1e-2
+    As, V, E, f = _problem(n, dt)
+    H = mg.Hierarchy(E, n, coarsest=8)
+    return As, V, f, kr.mg_inner(H)
+
+
+# The windows {i - m_i, ..., i - 1} of Remark 5 for m_max = 3, written out by
+# hand: m_i = 0, 1, 2, 3, 1, 1, 2, 3, 1, 1, 2, 3 for i = 0 .. 11.
+_WINDOWS_M3 = [[], [0], [0, 1], [0, 1, 2], [3], [4], [4, 5], [4, 5, 6], [7], [8], [8, 9],
+               [8, 9, 10]]
+
+
+def _lstsq_residual(cols, g):
+    D = np.stack(cols, axis=1)
+    c, *_ = np.linalg.lstsq(D, g, rcond=None)
+    return np.linalg.norm(g - D @ c) / np.linalg.norm(g)
+
+
+def _cos(a, b):
+    return abs(a @ b) / (np.linalg.norm(a) * np.linalg.norm(b))
+
+
+def test_fcg_directions_use_exactly_the_kept_window():
+    As, V, f, inner = _inexact_fcg_problem()
+    tr = []
+    kr.dcg(As, V, f, inner, tol=1e-8, max_iter=len(_WINDOWS_M3), outer='fcg', m_max=3,
+           c_F=1e6, trace=tr)
+    assert len(tr) == len(_WINDOWS_M3)
+    for i, (t, w) in enumerate(zip(tr, _WINDOWS_M3)):
+        g = t['d'] - t['r']
+        if not w:                        # d_0 = r_0
+            assert np.array_equal(t['d'], t['r'])
+            continue
+        # d_i - r_i lies in the span of the kept directions ...
+        assert _lstsq_residual([tr[k]['d'] for k in w], g) <= 1e-12, i
+        # ... and needs every one of them
+        for k in w:
+            rest = [tr[kk]['d'] for kk in w if kk != k]
+            miss = 1.0 if not rest else _lstsq_residual(rest, g)
+            assert miss >= 1e-7, (i, k, miss)
+
+
+def test_fcg_direction_is_conjugate_to_the_oldest_kept_direction():
+    # Within a window the later kept directions were themselves made
+    # conjugate to the oldest one, so (d_i, q_s) = 0 for s = i - m_i holds
+    # exactly, whatever the symmetry of the varying operator; the direction
+    # just before the window is no longer orthogonalised against and keeps a
+    # component of the operator's variation.
+    As, V, f, inner = _inexact_fcg_problem()
+    tr = []
+    kr.dcg(As, V, f, inner, tol=1e-8, max_iter=len(_WINDOWS_M3), outer='fcg', m_max=3,
+           c_F=1e6, trace=tr)
+    for i, w in enumerate(_WINDOWS_M3):
+        if not w:
+            continue
+        s = w[0]
+        assert _cos(tr[i]['d'], tr[s]['q']) <= 1e-13, i
+        if s > 0:
+            assert _cos(tr[i]['d'], tr[s - 1]['q']) >= 1e-6, i
+        if len(w) >= 2:
+            # Algorithm 1 forms every coefficient from r_i (classical
+            # Gram-Schmidt): against the newest kept direction the conjugacy
+            # is only as good as the operator's variation allows (a modified
+            # Gram-Schmidt loop would make it exact)
+            assert _cos(tr[i]['d'], tr[i - 1]['q']) >= 1e-13, i
+
+
+@pytest.mark.parametrize("m_max", [3, 6])
+def test_fcg_truncated_equals_untruncated_until_the_first_wrap(m_max):
+    # m_i = i for i <= m_max: FCG(m_max) and FCG(inf) agree iterate for
+    # iterate over m_max + 1 iterations; iteration m_max + 1 keeps one
+    # direction (m_i = 1) and the iterates part
+    As, V, f, inner = _inexact_fcg_problem()
+    K = m_max + 1
+    a = kr.dcg(As, V, f, inner, tol=1e-8, max_iter=K, outer='fcg', m_max=None, c_F=1e6)
+    b = kr.dcg(As, V, f, inner, tol=1e-8, max_iter=K, outer='fcg', m_max=m_max, c_F=1e6)
+    assert a.iterations == b.iterations == K
+    assert np.array_equal(a.x_hat, b.x_hat)
+    a = kr.dcg(As, V, f, inner, tol=1e-8, max_iter=K + 1, outer='fcg', m_max=None, c_F=1e6)
+    b = kr.dcg(As, V, f, inner, tol=1e-8, max_iter=K + 1, outer='fcg', m_max=m_max, c_F=1e6)
+    assert np.linalg.norm(a.x_hat - b.x_hat) >= 1e-7 * np.linalg.norm(a.x_hat)
+
+
+def test_restart_brings_the_true_residual_to_tol():
+    # An inexact inner solve (two-grid, c_F tol = 1e-8) leaves the
+    # reconstructed x of this solve with a true residual above tol although
+    # the recurrence residual met it; one warm restart of Algorithm 2 from
+    # that x closes the gap.  With exact inner solves the two residuals
+    # coincide and no restart is taken.
+    n, dt, tol = 16, 1e-3, 1e-8
+    As, V, E, f = _problem(n, dt)
+    inner = kr.mg_inner(mg.Hierarchy(E, n, coarsest=8))
+    plain = kr.dcg(As, V, f, inner, tol=tol, c_F=1.0)
+    assert plain.restarts == 0
+    assert plain.rel_res_recurrence <= tol < plain.rel_res_true
+    again = kr.dcg(As, V, f, inner, tol=tol, c_F=1.0, restarts=2)
+    assert again.restarts >= 1 and again.rel_res_true <= tol
+    assert again.iterations >= plain.iterations
+    # the first pass is the plain solve; the restart starts from its x
+    assert again.total_cycles > plain.total_cycles
+    exact = kr.dcg(As, V, f, kr.exact_inner(E), tol=tol, restarts=2)
+    assert exact.restarts == 0 and exact.rel_res_true <= tol
