@@ -115,6 +115,22 @@ typedef struct {
                           (the dense Cholesky solve up to rounding, without
                           forming the inverse).  dcg_solve / dcg_apply only;
                           the server and the _BATCH operators need 0.  [0]   */
+  int32_t restarts;    /* dcg_solve: when the reconstructed x misses tol on its
+                          true residual ||b - A* x|| / ||b|| (the recurrence
+                          residual of inexact inner solves drifts from it),
+                          run Algorithm 2 again from x_0 = x, at most this many
+                          times (pi(b) and f_D are reused; counts and max_outer
+                          cover every pass).  With restarts > 0 the status is
+                          DCG_OK only if the true residual meets tol, else
+                          DCG_NOT_CONVERGED; 0 keeps the paper's test on the
+                          recurrence residual alone.  Ignored by the server. [0] */
+  int32_t ras_group;   /* RAS step kernel of levels >= 2 (Section 4.2):
+                          0 = automatic by level size; 1, 2 or 4 = one
+                          workgroup per ras_group x ras_group tiles with the
+                          tile solves as MFMA products of each class inverse
+                          with the group's residuals; -1 = one tile per
+                          wavefront group, scalar FMAs.  Same step either way
+                          (up to rounding).  Not used by the server. [0]     */
 } dcg_options;
 
 /* Inner solver of dcg_solve.  DCG_INNER_MG is the paper's method: the
@@ -146,6 +162,7 @@ typedef struct {
   double t_setup_ms;       /* handle setup time (mesh context build/upload)   */
   double t_solve_ms;       /* wall time of dcg_solve; server: admission to done */
   double t_queue_ms;       /* server: submission to admission (0 for dcg_solve) */
+  int32_t restarts;        /* warm restarts taken (dcg_options.restarts)       */
 } dcg_stats;
 
 typedef struct dcg_ctx* dcg_handle;

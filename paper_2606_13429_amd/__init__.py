@@ -66,14 +66,18 @@ class Solver:
 
     def __init__(self, n, dt, nu=1.0, prec="mixed", outer="cg", penalty=10.0, pre=2, post=2,
                  c_F=0.01, max_outer=50000, max_inner=100, x0_given=False, use_graph=True,
-                 c_A=0.0, m_max=8, inner="mg", levels=0):
+                 c_A=0.0, m_max=8, inner="mg", levels=0, restarts=0, ras_group=0):
         """outer: "cg", "fcg1", "fcg" (truncated FCG with m_max, FCG(inf) for
         m_max = 0) or "gmres"; c_A > 0 selects the adaptive inner tolerance of
         eq. (tol); inner="exact" solves the inner system exactly by fast
         diagonalisation instead of the W-cycle multigrid (uniform grid);
         inner="none" switches the deflation off (plain CG on A*); levels > 0
         keeps the finest ``levels`` levels of the multigrid hierarchy and
-        solves its coarsest level exactly by fast diagonalisation."""
+        solves its coarsest level exactly by fast diagonalisation; restarts > 0
+        reruns Algorithm 2 from the returned x while its true residual misses
+        tol (at most that many times); ras_group selects the RAS step kernel
+        (0 automatic, 1 / 2 / 4 grouped MFMA tiles, -1 one tile per wavefront
+        group)."""
         mesh, opt = dcg_defaults()
         mesh.n, mesh.penalty, mesh.pre, mesh.post = n, penalty, pre, post
         opt.prec = {"mixed": DCG_MIXED, "fp64": DCG_FP64}[prec]
@@ -82,7 +86,7 @@ class Solver:
         opt.c_A, opt.m_max = c_A, m_max
         opt.inner = {"mg": DCG_INNER_MG, "exact": DCG_INNER_EXACT, "none": DCG_INNER_NONE}[inner]
         opt.x0_given, opt.use_graph = int(x0_given), int(use_graph)
-        opt.levels = levels
+        opt.levels, opt.restarts, opt.ras_group = levels, restarts, ras_group
         self.n, self.dt, self.nu, self.mesh, self.opt = n, dt, nu, mesh, opt
         self.handle = dcg_setup(mesh, dt, nu, opt)
 

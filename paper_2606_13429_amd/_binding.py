@@ -44,7 +44,8 @@ class dcg_options(ctypes.Structure):
                 ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int32),
                 ("c_A", ctypes.c_double), ("m_max", ctypes.c_int32), ("inner", ctypes.c_int32),
-                ("levels", ctypes.c_int32)]
+                ("levels", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("ras_group", ctypes.c_int32)]
 
 
 class dcg_stats(ctypes.Structure):
@@ -52,7 +53,8 @@ class dcg_stats(ctypes.Structure):
                 ("total_wcycles", ctypes.c_int32), ("inner_solves", ctypes.c_int32),
                 ("inner_per_outer", ctypes.c_double), ("rel_res_recurrence", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double), ("t_queue_ms", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("t_queue_ms", ctypes.c_double),
+                ("restarts", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -60,6 +60,10 @@ dcg_status check_options(const dcg_options& o) {
   if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
     return fail(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
   if (o.levels < 0) return fail(nullptr, DCG_EINVAL, "levels must be >= 0");
+  if (o.restarts < 0) return fail(nullptr, DCG_EINVAL, "restarts must be >= 0");
+  if (o.ras_group != 0 && o.ras_group != -1 && o.ras_group != 1 && o.ras_group != 2 &&
+      o.ras_group != 4)
+    return fail(nullptr, DCG_EINVAL, "ras_group must be 0, -1, 1, 2 or 4");
   return DCG_OK;
 }
 

@@ -1,5 +1,6 @@
 // Mesh contexts: host assembly (host_setup.cpp) converted to the device
 // layouts of kernels.hpp and uploaded once per (device, n, penalty).
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -137,6 +138,80 @@ void upload_factors(const HostLevel& hl, T* dev) {
   }
 }
 
+// The same inverses in the operand order of the grouped RAS step's MFMA
+// products: per class [P 8][Q 8][lane 64][4], lane l of fragment (P, Q)
+// holding row 16 P + l % 16, columns 16 Q + 4 (l / 16) .. + 3, so that each
+// lane's operand of one 16 x 16 x 4 step is one contiguous vector and a
+// fragment is one contiguous 1 KiB (FP32) run.
+template <typename T>
+void upload_fragments(const HostLevel& hl, T* dev) {
+  const int64_t per = 64 * 64 * 4;
+  const int classes = int(hl.unique_inv.size());
+  std::vector<T> stage(size_t(classes) * per);
+  threaded(classes, [&](int64_t c) {
+    const std::vector<double>& src = hl.unique_inv[c];
+    T* d = &stage[size_t(c) * per];
+    for (int P = 0; P < 8; ++P)
+      for (int Q = 0; Q < 8; ++Q)
+        for (int l = 0; l < 64; ++l)
+          for (int kk = 0; kk < 4; ++kk)
+            d[((P * 8 + Q) * 64 + l) * 4 + kk] =
+                T(src[size_t(16 * P + l % 16) * kTileDofs + 16 * Q + 4 * (l / 16) + kk]);
+  });
+  DCG_HIP(hipMemcpy(dev, stage.data(), sizeof(T) * stage.size(), hipMemcpyHostToDevice));
+}
+
+// The grouped RAS step derives the pending slot and the weight of a block
+// square from the tile geometry instead of reading the tables: the blocks
+// containing a square are its own tile and the neighbour tile on each side
+// where the square lies on the core's edge (inside the domain), the pending
+// slot is the writer's rank among them in increasing tile order (the order
+// of the cover lists), and the weight is one over their number.  Checked
+// here against the tables the host built, for every tile and block square.
+void check_tile_geometry(const HostLevel& hl) {
+  const int n = hl.n, tpr = n / 4;
+  for (int t = 0; t < hl.tiles; ++t)
+    for (int p = 0; p < kTileSlots; ++p) {
+      const int32_t e = hl.tile_elems[int64_t(t) * kTileSlots + p];
+      if (e < 0) continue;
+      const int X = int(e % n), Y = int(e / n);
+      const int TX = X >> 2, TY = Y >> 2, lx = X & 3, ly = Y & 3, T = TY * tpr + TX;
+      const bool below = ly == 0 && TY > 0, left = lx == 0 && TX > 0;
+      const bool right = lx == 3 && TX < tpr - 1, above = ly == 3 && TY < tpr - 1;
+      const int count = 1 + below + left + right + above;
+      const int rank = (below && T - tpr < t) + (left && T - 1 < t) + (T < t) +
+                       (right && T + 1 < t) + (above && T + tpr < t);
+      if (hl.tile_dst[int64_t(t) * kTileSlots + p] != 3 * e + rank || hl.dw[e] != 1.0 / count)
+        throw Error(DCG_EINVAL, "RAS tile geometry differs from the cover lists");
+    }
+}
+
+// Extra workgroups of the grouped RAS step with g x g tiles per group: for
+// every group (row-major), the classes of its tiles in order of first
+// appearance (tiles row by row within the group); the first is run by the
+// group's own workgroup, every further one by an extra workgroup listed as
+// (group, class).
+std::vector<int32_t> group_extra(const HostLevel& hl, int g) {
+  std::vector<int32_t> out;
+  const int tpr = hl.n / kTileCore;
+  if (tpr % g) return out;
+  const int gpr = tpr / g;
+  for (int G = 0; G < gpr * gpr; ++G) {
+    std::vector<int32_t> seen;
+    for (int i = 0; i < g * g; ++i) {
+      const int t = (G / gpr * g + i / g) * tpr + G % gpr * g + i % g;
+      const int32_t c = hl.tile_class[t];
+      if (std::find(seen.begin(), seen.end(), c) != seen.end()) continue;
+      if (!seen.empty()) {
+        out.push_back(G);
+        out.push_back(c);
+      }
+      seen.push_back(c);
+    }
+  }
+  return out;
+}
+
 // The level operator's blocks per square class ([9][5][4][4], see
 // square_class); every square of a class must carry bit-identical blocks,
 // which the uniform grid guarantees and this checks.
@@ -236,6 +311,15 @@ std::shared_ptr<MeshContext> build_context(int device, int n, double penalty) {
       dl.classes = int(hl.unique_inv.size());
       for (int32_t c : hl.tile_class)
         if (c < 0 || c >= dl.classes) throw Error(DCG_EINVAL, "tile class out of range");
+      check_tile_geometry(hl);
+      for (int gi = 0; gi < 3; ++gi) {
+        const std::vector<int32_t> ex = group_extra(hl, 1 << gi);
+        dl.gx_extra_n[gi] = int(ex.size() / 2);
+        if (ex.empty()) continue;
+        dl.gx_extra[gi] = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * ex.size()));
+        DCG_HIP(hipMemcpy(dl.gx_extra[gi], ex.data(), sizeof(int32_t) * ex.size(),
+                          hipMemcpyHostToDevice));
+      }
       dl.fcls = static_cast<int32_t*>(ctx->alloc(sizeof(int32_t) * hl.tile_class.size()));
       DCG_HIP(hipMemcpy(dl.fcls, hl.tile_class.data(), sizeof(int32_t) * hl.tile_class.size(),
                         hipMemcpyHostToDevice));
@@ -268,14 +352,19 @@ void MeshContext::ensure_factors(bool fp32) {
     }
     if (k >= 2) {
       const size_t cnt = size_t(dl.classes) * 36 * 256;
+      const size_t fcnt = size_t(dl.classes) * 64 * 64 * 4;
       if (fp32) {
         dl.F32 = static_cast<float*>(alloc(sizeof(float) * cnt));
         upload_factors<float>(hl, dl.F32);
+        dl.Fm32 = static_cast<float*>(alloc(sizeof(float) * fcnt));
+        upload_fragments<float>(hl, dl.Fm32);
         dl.dw32 = static_cast<float*>(alloc(sizeof(float) * dl.ne));
         upload_weights<float>(hl, dl.dw32);
       } else {
         dl.F64 = static_cast<double*>(alloc(sizeof(double) * cnt));
         upload_factors<double>(hl, dl.F64);
+        dl.Fm64 = static_cast<double*>(alloc(sizeof(double) * fcnt));
+        upload_fragments<double>(hl, dl.Fm64);
         dl.dw64 = static_cast<double*>(alloc(sizeof(double) * dl.ne));
         upload_weights<double>(hl, dl.dw64);
       }

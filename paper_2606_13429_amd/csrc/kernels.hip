@@ -9,6 +9,7 @@
 // tree per workgroup, per-workgroup partials, and one fixed-order final
 // pass (no floating-point atomics anywhere).
 #include "kernels.hpp"
+#include "mg_common.hpp"
 
 #include <cmath>
 
@@ -36,16 +37,7 @@ __device__ inline double block_sum(double v, double* lds) {
   return s;
 }
 
-// ---------------------------------------------------------------- 4-vectors
-__device__ inline void ld4(const float* p, float v[4]) {
-  const float4 t = *reinterpret_cast<const float4*>(p);
-  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-}
-__device__ inline void ld4(const double* p, double v[4]) {
-  const double2 a = reinterpret_cast<const double2*>(p)[0];
-  const double2 b = reinterpret_cast<const double2*>(p)[1];
-  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-}
+using mg::ld4;   // 4-vector loads shared with the multigrid kernels
 
 inline int grid_for(int64_t items, int per_block, int cap) {
   int64_t g = (items + per_block - 1) / per_block;

@@ -182,6 +182,9 @@ hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st);
 template <typename T>
 struct SweepArgs {
   const T* F = nullptr;             // [classes][36][16][16] packed symmetric inverses
+  const T* Fm = nullptr;            // the same, full, in MFMA operand order [classes][8][8][64][4]
+  const int32_t* gextra = nullptr;  // grouped step: (group, class) of the extra workgroups
+  int nextra = 0;
   const int32_t* fcls = nullptr;    // [tiles] class of the tile's inverse in F
   const T* dw = nullptr;            // [ne] partition-of-unity weight 1 / #blocks
   const int32_t* ext = nullptr;     // [tiles][52] block squares + outside neighbours
@@ -217,6 +220,12 @@ struct RestrictArgs {
 
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T>& a, int waves_per_tile, hipStream_t st);
+// The same step with gx x gx tiles per workgroup and the tile solves as MFMA
+// products of each class inverse with the group's residuals (n / 4 must be
+// a multiple of gx; gx in {1, 2, 4}); a.gextra / a.nextra list the classes
+// after the first of every group, each run by a workgroup of its own.
+template <typename T>
+hipError_t launch_sweep_g(const SweepArgs<T>& a, int gx, hipStream_t st);
 template <typename T>
 hipError_t launch_restrict_res(const RestrictArgs<T>& a, hipStream_t st);
 // out = (has_z ? z : 0) + pending Ye

@@ -25,27 +25,6 @@ constexpr int kThreads = 256;
 constexpr int B = kBatch;
 constexpr int kCoarse = 1024;   // dofs of the 16 x 16 coarsest level
 
-// 16 x 16 x 4 MFMA of the level type.  Operand lanes: A holds (row l % 16,
-// k l / 16), B holds (k l / 16, column l % 16).  The accumulator of lane l
-// holds column l % 16 and rows 4 (l / 16) + v (FP32) or 4 v + l / 16 (FP64),
-// v = 0..3.
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-
 __device__ __forceinline__ int64_t at(int64_t e, int c) { return (e * B + c) * 4; }
 
 // z += pending tile outputs of square e, request c (blocks in increasing

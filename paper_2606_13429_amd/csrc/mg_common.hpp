@@ -32,6 +32,27 @@ __device__ __forceinline__ void st4(double* p, const double v[4]) {
   reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
 }
 
+// 16 x 16 x 4 MFMA of the level type.  Operand lanes: A holds (row l % 16,
+// k l / 16), B holds (k l / 16, column l % 16).  The accumulator of lane l
+// holds column l % 16 and rows 4 (l / 16) + v (FP32) or 4 v + l / 16 (FP64),
+// v = 0..3.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
 // Coefficient of coarse corner A at fine corner a of child ch (exact).
 template <typename T>
 __device__ __forceinline__ T pcoef(int ch, int a, int A) {

@@ -285,6 +285,281 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs<T> a) {
   }
 }
 
+// One RAS step for a GX x GX group of tiles per workgroup (4 GX x 4 GX core
+// squares), the tile solves as MFMA products.  On the uniform grid every
+// tile of a group has one of a few local problems (its class: interior,
+// edge, corner), so the group's residuals form a 128 x GX^2 matrix U whose
+// columns of one class are multiplied by that class's inverse in one
+// 16 x 16 x 4 MFMA product (columns of other classes enter as zeros, which
+// adds nothing); a boundary group runs one masked product per class present.
+// Compared with one tile per wavefront (k_sweep), the class inverse is read
+// once per group instead of once per tile, z is loaded once per frame square
+// instead of once per neighbouring tile, and the residual is formed once per
+// square instead of once per block containing it.
+//
+// The step is bound by memory latency, so every load that does not depend
+// on another is issued first (the iterate, pending outputs and, in the
+// first post-smoothing step (PROL), the coarse correction of the frame; f;
+// the operator's class table; the tile classes), and the class inverse,
+// which needs the first tile's class, as soon as the frame registers are
+// free.  The pending slot and weight of an output follow from the tile
+// geometry (checked against the host's cover lists when the context is
+// built), so the outputs need no table.
+//   1. z_new on the frame of squares within distance 2 of the group core
+//      (z_old + pending Y [+ P (z_coarse + pending Y_coarse)]), in LDS; the
+//      core squares are written to z_new;
+//   2. r = f - L_k z_new on the block squares (core + 1), in LDS, one
+//      thread per square, the operator rows from the class table in LDS;
+//   3. per class: wavefront w computes row blocks w and 7 - w of
+//      (L_k)_c^{-1} U_c, 8 column blocks x 4 k-steps, the operand fragments
+//      read in MFMA order (one 16 / 32 byte vector per lane and fragment);
+//   4. Y_t = D_t u_t written to the pending slot of each block square.
+template <typename T, bool PROL>
+__device__ __forceinline__ void load_frame(const SweepArgs<T>& a, int e, bool ok, T (&v)[PROL ? 8 : 4][4]) {
+  // v[0] z_old, v[1..3] pending Y, v[4] coarse z, v[5..7] coarse pending Y
+#pragma unroll
+  for (int i = 0; i < (PROL ? 8 : 4); ++i) v[i][0] = v[i][1] = v[i][2] = v[i][3] = T(0);
+  if (!ok) return;
+  if (a.has_z) ld4(a.z_old + 4 * (int64_t)e, v[0]);
+  if (a.has_y) {
+    ld4(a.Y_old + 12 * (int64_t)e, v[1]);
+    ld4(a.Y_old + 12 * (int64_t)e + 4, v[2]);
+    ld4(a.Y_old + 12 * (int64_t)e + 8, v[3]);
+  }
+  if constexpr (PROL) {
+    const int ex = e % a.n, ey = e / a.n;
+    const int E = (ey >> 1) * a.nc + (ex >> 1);
+    ld4(a.zc + 4 * (int64_t)E, v[4]);
+    if (a.c_has_y) {
+      ld4(a.Yc + 12 * (int64_t)E, v[5]);
+      ld4(a.Yc + 12 * (int64_t)E + 4, v[6]);
+      ld4(a.Yc + 12 * (int64_t)E + 8, v[7]);
+    }
+  }
+}
+
+// z_new of square e from its loaded values (the order of current_z)
+template <typename T, bool PROL>
+__device__ __forceinline__ void combine_frame(const SweepArgs<T>& a, int e,
+                                              const T (&v)[PROL ? 8 : 4][4], T z[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) z[j] = v[0][j];
+  if (a.has_y) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z[j] = ((z[j] + v[1][j]) + v[2][j]) + v[3][j];
+  }
+  if constexpr (PROL) {
+    T ec[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ec[j] = v[4][j];
+    if (a.c_has_y) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ec[j] = ((ec[j] + v[5][j]) + v[6][j]) + v[7][j];
+    }
+    const int ch = (e % a.n & 1) + 2 * (e / a.n & 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      z[j] += pcoef<T>(ch, j, 0) * ec[0] + pcoef<T>(ch, j, 1) * ec[1] +
+              pcoef<T>(ch, j, 2) * ec[2] + pcoef<T>(ch, j, 3) * ec[3];
+  }
+}
+
+template <typename T, int GX, bool PROL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2)))
+void k_sweep_g(SweepArgs<T> a) {
+  using V = typename Mfma<T>::v4;
+  constexpr int C = 4 * GX;        // core squares per side
+  constexpr int FS = C + 4;        // z frame: core +- 2
+  constexpr int RS = C + 2;        // residual frame: core +- 1
+  constexpr int NT = GX * GX;      // tiles = MFMA columns in use
+  constexpr int NZ = (FS * FS + kThreads - 1) / kThreads;   // frame squares per thread
+  constexpr int NR = (RS * RS + kThreads - 1) / kThreads;   // residual squares per thread
+  constexpr int NV = PROL ? 8 : 4; // loaded 4-vectors per frame square
+  constexpr int NLC = 9 * 5 * 16;  // class table of the level operator
+  constexpr int NLU = (NLC / 4 + kThreads - 1) / kThreads;
+  // class-inverse fragments requested ahead of the MFMA loop
+  constexpr int PD = 4;
+  static_assert(NT <= 16, "at most 16 tiles per group");
+  __shared__ __align__(16) T zf[FS * FS][4];
+  __shared__ __align__(16) T rf[RS * RS][4];
+  __shared__ __align__(16) T lc[NLC];
+  __shared__ int tcls[NT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tpr = a.n >> 2, gpr = tpr / GX, G0 = gpr * gpr;
+  // workgroups 0 .. G0 - 1 run the class of each group's first tile, the
+  // extra ones a further class of the group in the extra list
+  const bool extra = (int)blockIdx.x >= G0;
+  const int g = extra ? a.gextra[2 * (blockIdx.x - G0)] : xcd_band_index(blockIdx.x, G0);
+  const int X0 = C * (g % gpr), Y0 = C * (g / gpr);
+  const int t00 = GX * (g / gpr) * tpr + GX * (g % gpr);
+  const bool need_z = a.has_z || a.has_y || PROL;
+  const int r = lane & 15, k = lane >> 4;
+  const int Pw[2] = {wave, 7 - wave};
+
+  // ---- every load that needs no other one, in one batch: the tile
+  // classes, the operator's class table, f, and the frame values
+  const int c0 = extra ? a.gextra[2 * (blockIdx.x - G0) + 1] : a.fcls[t00];
+  const int tc = tid < NT ? a.fcls[t00 + (tid / GX) * tpr + tid % GX] : 0;
+  T lcv[NLU][4];
+#pragma unroll
+  for (int u = 0; u < NLU; ++u)
+    if (tid + u * kThreads < NLC / 4) ld4(a.Lc + 4 * (tid + u * kThreads), lcv[u]);
+  T fr[NR][4];
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int q = tid + u * kThreads;
+    const int rx = q % RS, ry = q / RS;
+    const int X = X0 + rx - 1, Y = Y0 + ry - 1;
+    fr[u][0] = fr[u][1] = fr[u][2] = fr[u][3] = T(0);
+    const bool corner = (rx == 0 || rx == RS - 1) && (ry == 0 || ry == RS - 1);
+    if (q < RS * RS && !corner && X >= 0 && Y >= 0 && X < a.n && Y < a.n)
+      ld4(a.f + 4 * ((int64_t)Y * a.n + X), fr[u]);
+  }
+  T fv[NZ][NV][4];
+  if (need_z) {
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) {
+      const int q = tid + u * kThreads;
+      const int fx = q % FS, fy = q / FS;
+      const int X = X0 + fx - 2, Y = Y0 + fy - 2;
+      const bool ox = fx < 2 || fx >= FS - 2, oy = fy < 2 || fy >= FS - 2;
+      // the four 2 x 2 frame corners hold no neighbour of a block square,
+      // except their inner squares (the diagonal corners of the layer)
+      const bool unused = ox && oy && !((fx == 1 || fx == FS - 2) && (fy == 1 || fy == FS - 2));
+      const bool ok = q < FS * FS && !unused && X >= 0 && Y >= 0 && X < a.n && Y < a.n;
+      load_frame<T, PROL>(a, ok ? Y * a.n + X : 0, ok, fv[u]);
+    }
+  }
+
+  // ---- LDS: tile classes, class table, z_new on the frame
+  if (tid < NT) tcls[tid] = tc;
+#pragma unroll
+  for (int u = 0; u < NLU; ++u)
+    if (tid + u * kThreads < NLC / 4) st4(&lc[4 * (tid + u * kThreads)], lcv[u]);
+  if (need_z) {
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) {
+      const int q = tid + u * kThreads;
+      if (q >= FS * FS) continue;
+      const int fx = q % FS, fy = q / FS;
+      const int X = X0 + fx - 2, Y = Y0 + fy - 2;
+      T z[4];
+      combine_frame<T, PROL>(a, Y * a.n + X, fv[u], z);
+      st4(&zf[q][0], z);
+      const bool core = fx >= 2 && fx < FS - 2 && fy >= 2 && fy < FS - 2;
+      if (a.write_z && !extra && core) st4(a.z_new + 4 * ((int64_t)Y * a.n + X), z);
+    }
+  }
+
+  // ---- the class inverse of this workgroup's class, requested now that the frame
+  // registers are free; it arrives while the residual is formed
+  auto load_q = [&](const T* F, int Q, T (&dst)[2][4]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) ld4(F + ((Pw[h] * 8 + Q) * 64 + lane) * 4, dst[h]);
+  };
+  T av[PD][2][4];
+  {
+    const T* F0 = a.Fm + (int64_t)c0 * (64 * 256);
+#pragma unroll
+    for (int Q = 0; Q < PD; ++Q) load_q(F0, Q, av[Q]);
+  }
+  __syncthreads();
+
+  // ---- residual on the block squares
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int q = tid + u * kThreads;
+    if (q >= RS * RS) continue;
+    const int rx = q % RS, ry = q / RS;
+    const int X = X0 + rx - 1, Y = Y0 + ry - 1;
+    const bool corner = (rx == 0 || rx == RS - 1) && (ry == 0 || ry == RS - 1);
+    T res[4] = {fr[u][0], fr[u][1], fr[u][2], fr[u][3]};
+    if (need_z && !corner && X >= 0 && Y >= 0 && X < a.n && Y < a.n) {
+      const T* lr = lc + square_class(X, Y, a.n) * 80;
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        const int dx = s == 1 ? -1 : (s == 2 ? 1 : 0), dy = s == 3 ? -1 : (s == 4 ? 1 : 0);
+        if (X + dx < 0 || X + dx >= a.n || Y + dy < 0 || Y + dy >= a.n) continue;
+        T zq[4];
+        ld4(zf[(ry + 1 + dy) * FS + rx + 1 + dx], zq);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const T* l = lr + 16 * s + 4 * j;
+          acc[j] += l[0] * zq[0] + l[1] * zq[1] + l[2] * zq[2] + l[3] * zq[3];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) res[j] -= acc[j];
+    }
+    st4(&rf[q][0], res);
+  }
+  __syncthreads();
+
+  // ---- MFMA product of the class inverse with the residual columns of the
+  // tiles of this class (other columns enter as zeros); the B operand of
+  // lane (r, k) is tile r's residual at block slot 4 Q + k
+  const int rtx = 4 * (r % GX) + 1, rty = 4 * (r / GX) + 1;   // tile r in the residual frame
+  const bool col = r < NT && tcls[r < NT ? r : 0] == c0;
+  const T* Fc = a.Fm + (int64_t)c0 * (64 * 256);
+  V acc0 = {T(0), T(0), T(0), T(0)}, acc1 = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int Q = 0; Q < 8; ++Q) {
+    T bq[4] = {T(0), T(0), T(0), T(0)};
+    if (col) {
+      int px, py;
+      slot_pos(4 * Q + k, px, py);
+      ld4(&rf[(rty + py) * RS + rtx + px][0], bq);
+    }
+    T aq[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) aq[h][kk] = av[Q % PD][h][kk];
+    if (Q + PD < 8) load_q(Fc, Q + PD, av[Q % PD]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      acc0 = Mfma<T>::mac(aq[0][kk], bq[kk], acc0);
+      acc1 = Mfma<T>::mac(aq[1][kk], bq[kk], acc1);
+    }
+  }
+
+  // ---- outputs: FP32 lanes hold rows 4 k + v of row block P (block slot
+  // 4 P + k, corner v), FP64 lanes rows 4 v + k (slot 4 P + v, corner k)
+  if (!col) return;
+  const int t = t00 + (r / GX) * tpr + r % GX;
+  constexpr int NO = sizeof(T) == 4 ? 1 : 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const V& acc = h == 0 ? acc0 : acc1;
+#pragma unroll
+    for (int v = 0; v < NO; ++v) {
+      const int p = NO == 1 ? 4 * Pw[h] + k : 4 * Pw[h] + v;
+      int px, py;
+      slot_pos(p, px, py);
+      const int X = X0 + rtx - 1 + px, Y = Y0 + rty - 1 + py;
+      if (X < 0 || Y < 0 || X >= a.n || Y >= a.n) continue;
+      // blocks containing (X, Y): its core tile T and the neighbour tile on
+      // each side where the square lies on T's core edge; the pending slot
+      // is this tile's rank among them in increasing order
+      const int TX = X >> 2, TY = Y >> 2, lx = X & 3, ly = Y & 3, Tc = TY * tpr + TX;
+      const bool below = ly == 0 && TY > 0, left = lx == 0 && TX > 0;
+      const bool right = lx == 3 && TX < tpr - 1, above = ly == 3 && TY < tpr - 1;
+      const int count = 1 + below + left + right + above;
+      const int rank = (below && Tc - tpr < t) + (left && Tc - 1 < t) + (Tc < t) +
+                       (right && Tc + 1 < t) + (above && Tc + tpr < t);
+      const T w = count == 1 ? T(1) : (count == 2 ? T(0.5) : T(1.0 / 3.0));
+      const int64_t slot = 3 * ((int64_t)Y * a.n + X) + rank;
+      if constexpr (NO == 1) {
+        const T y[4] = {w * acc[0], w * acc[1], w * acc[2], w * acc[3]};
+        st4(a.Y_new + 4 * slot, y);
+      } else {
+        a.Y_new[4 * slot + k] = w * acc[v];
+      }
+    }
+  }
+}
+
 // Pending update + residual + restriction: z_new = z_old + pending Y (written
 // for every square), r = f - L z_new, rc = P^T r.  One workgroup = 16
 // coarse squares x (4 children x 4 dofs).
@@ -380,6 +655,25 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int wpt, hipStream_t st) {
 }
 
 template <typename T>
+hipError_t launch_sweep_g(const SweepArgs<T>& a, int gx, hipStream_t st) {
+  const int tpr = a.n / 4;
+  if (gx <= 0 || tpr % gx || a.tiles != tpr * tpr) return hipErrorInvalidValue;
+  int grid = (tpr / gx) * (tpr / gx);
+  if (!a.Fm || (a.nextra > 0 && !a.gextra)) return hipErrorInvalidValue;
+  grid += a.nextra;
+  switch (gx * 2 + (a.prol ? 1 : 0)) {
+    case 2: k_sweep_g<T, 1, false><<<grid, kThreads, 0, st>>>(a); break;
+    case 3: k_sweep_g<T, 1, true><<<grid, kThreads, 0, st>>>(a); break;
+    case 4: k_sweep_g<T, 2, false><<<grid, kThreads, 0, st>>>(a); break;
+    case 5: k_sweep_g<T, 2, true><<<grid, kThreads, 0, st>>>(a); break;
+    case 8: k_sweep_g<T, 4, false><<<grid, kThreads, 0, st>>>(a); break;
+    case 9: k_sweep_g<T, 4, true><<<grid, kThreads, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_restrict_res(const RestrictArgs<T>& a, hipStream_t st) {
   const int nc = a.n / 2;
   const int grid = (nc * nc + 15) / 16;
@@ -405,6 +699,7 @@ hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T
 
 #define DCG_MG_INSTANTIATE(T)                                                                 \
   template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, hipStream_t);                 \
+  template hipError_t launch_sweep_g<T>(const SweepArgs<T>&, int, hipStream_t);               \
   template hipError_t launch_restrict_res<T>(const RestrictArgs<T>&, hipStream_t);            \
   template hipError_t launch_resolve<T>(int, bool, const T*, const T*, T*, hipStream_t);      \
   template hipError_t launch_refine_add<T>(int, bool, bool, bool, const T*, const T*, double*, \

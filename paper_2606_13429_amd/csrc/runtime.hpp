@@ -40,10 +40,18 @@ struct DeviceLevel {
   // class of every tile
   float* F32 = nullptr;
   double* F64 = nullptr;
+  // the same inverses in MFMA operand order, [classes][8][8][64][4]
+  float* Fm32 = nullptr;
+  double* Fm64 = nullptr;
   int32_t* fcls = nullptr;        // [tiles]
   int classes = 0;
   float* dw32 = nullptr;          // [ne] 1 / #blocks containing the square
   double* dw64 = nullptr;
+  // grouped RAS step with g x g tiles per workgroup (g = 1, 2, 4 at index
+  // 0, 1, 2): every class after the first of a group gets a workgroup of its
+  // own, listed as (group, class) pairs [gx_extra_n[i]][2]
+  int32_t* gx_extra[3] = {nullptr, nullptr, nullptr};
+  int gx_extra_n[3] = {0, 0, 0};
 };
 
 // Dt-independent operators of one mesh on one device; shared by handles and

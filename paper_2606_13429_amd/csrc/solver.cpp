@@ -100,6 +100,7 @@ template <typename T>
 Cycle<T> make_cycle(dcg_ctx* h) {
   Cycle<T> c(*h->mesh, h->ws.lvb, h->mp.pre, h->mp.post);
   c.base = h->lbase;
+  c.group = h->opt.ras_group;
   if (h->lbase > 0) c.cfdm = &h->cfdm;
   if (h->ktime && h->kcycle++ % h->kstride == 0) {   // a sampled W-cycle
     c.timer.ev = h->kev;
@@ -348,16 +349,16 @@ dcg_status outer_fcg(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_t
   store_reserve(fs, R, N);
   const int nbA = astar_blocks(ne);
   dcg_status status = DCG_OK;
-  while (true) {
+  for (int i = 0;; ++i) {   // i: iteration of this pass (the window restarts with a pass)
     if (rho <= lim) break;
     if (it >= h->opt.max_outer) {
       status = DCG_NOT_CONVERGED;
       break;
     }
-    const int mi = inf ? it : (it == 0 ? 0 : std::max(1, it % (h->opt.m_max + 1)));
-    const int slot = it % R;
+    const int mi = inf ? i : (i == 0 ? 0 : std::max(1, i % (h->opt.m_max + 1)));
+    const int slot = i % R;
     store_slot(fs, slot, N, true);
-    const int first = ((it - mi) % R + R) % R;
+    const int first = ((i - mi) % R + R) % R;
     DCG_HIP(launch_fcg_coef(N, ws.r, fs.qptr, fs.dq, first, mi, R, fs.part, fs.coef, st));
     int nbd = 0;
     DCG_HIP(launch_fcg_direction(N, ws.r, fs.dptr, first, mi, R, fs.coef, fs.d[slot], ws.part,
@@ -406,8 +407,9 @@ dcg_status outer_gmres(dcg_ctx* h, double lim, double& rho, int& it, int& cycles
   const int R = h->opt.max_outer + 2;
   store_reserve(fs, R, N);
   double rnorm = std::sqrt(std::max(rho, 0.0));
-  if (rho <= lim || h->opt.max_outer == 0)
+  if (rho <= lim || it >= h->opt.max_outer)
     return rho <= lim ? DCG_OK : DCG_NOT_CONVERGED;
+  const int it0 = it;   // the basis of this pass starts at slot 0
   store_slot(fs, 0, N, false);
   DCG_HIP(launch_scale(N, 1.0 / rnorm, ws.r, fs.d[0], st));
   std::vector<std::vector<double>> H;     // rotated Hessenberg columns
@@ -420,7 +422,7 @@ dcg_status outer_gmres(dcg_ctx* h, double lim, double& rho, int& it, int& cycles
       status = DCG_NOT_CONVERGED;
       break;
     }
-    const int j = it;
+    const int j = it - it0;
     // q = M_D v_j
     DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, fs.d[j], nullptr, nullptr, ws.sc,
                          nullptr, ws.w, ws.s, nullptr, st));
@@ -471,7 +473,7 @@ dcg_status outer_gmres(dcg_ctx* h, double lim, double& rho, int& it, int& cycles
     }
   }
   rho = rnorm * rnorm;
-  const int k = it;
+  const int k = it - it0;
   if (k > 0) {                               // y = R^{-1} g, x_hat += V y
     std::vector<double> y(k);
     for (int r = k - 1; r >= 0; --r) {
@@ -529,95 +531,111 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
     if (st) *st = stats;
     return DCG_OK;
   }
-  if (h->opt.x0_given) {
-    // x_hat_0 = x_0, r_0 = f_D - M_D x_0 with M_D x_0 = A* x_0 - A* Z y_0,
-    // y_0 = E^{-1} Z^T A* x_0 (Algorithm 1 applied to the deflated system)
-    DCG_HIP(launch_copy<double>(N, x, ws.xh, stream));
+  const double lim = tol * tol * b2;
+  auto tol_outer = [&](double rho_i) {
+    return adaptive ? h->opt.c_A * tol * std::sqrt(b2) / std::sqrt(rho_i) : tol_c;
+  };
+  int it = 0, pidx = 0, pass = 0;
+  bool warm = h->opt.x0_given != 0;
+  dcg_status status = DCG_OK;
+  double rel_true = 0.0, rho = 0.0;
+  while (true) {
+    if (warm) {
+      // x_hat_0 = x, r_0 = f_D - M_D x with M_D x = A* x - A* Z y_0,
+      // y_0 = E^{-1} Z^T A* x (Algorithm 1 applied to the deflated system);
+      // ws.r holds f_D
+      DCG_HIP(launch_copy<double>(N, x, ws.xh, stream));
+      DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
+                           ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
+      cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
+      ++inner_solves;
+      DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zt, ws.w, ws.w, ws.q, nullptr,
+                             ws.part, stream));
+      int nbu = 0;
+      DCG_HIP(launch_axpy_dot(N, -1.0, ws.q, ws.r, ws.part, &nbu, stream));
+      DCG_HIP(launch_reduce(ws.part, nbu, kRedRho, ws.sc, stream));
+      read_scalars(h, stream);
+    } else {
+      DCG_HIP(launch_fill<double>(N, 0.0, ws.xh, stream));
+    }
+    rho = ws.sc_host->rho;
+    if (h->opt.outer == DCG_OUTER_FCG) {
+      status = outer_fcg(h, lim, rho, it, cycles_total, cycles_outer, inner_solves, tol_outer,
+                         stream);
+    } else if (h->opt.outer == DCG_OUTER_GMRES) {
+      status = outer_gmres(h, lim, rho, it, cycles_total, cycles_outer, inner_solves, tol_outer,
+                           stream);
+    } else {
+      status = DCG_OK;
+      for (int i = 0;; ++i) {   // i: iteration of this pass
+        if (rho <= lim) break;
+        if (it >= h->opt.max_outer) {
+          status = DCG_NOT_CONVERGED;
+          break;
+        }
+        // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
+        const bool atimed = h->ktime;
+        if (atimed) DCG_HIP(hipEventRecord(h->aev[0], stream));
+        DCG_HIP(launch_astar(i == 0 ? kAstarFirst : kAstarDir, m.Cdiv, m.cols, m.M1, ne,
+                             ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
+                             stream));
+        if (atimed) DCG_HIP(hipEventRecord(h->aev[1], stream));
+        pidx = 1 - pidx;
+        const int c = inner(h, ws.s, ws.zref, tol_outer(rho), stream);
+        cycles_total += c;
+        cycles_outer += c;
+        ++inner_solves;
+        // q = w - A* Z y = M_D p  (y = (2/dt) z)
+        DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zref, ws.w, ws.p[pidx], ws.q,
+                               nullptr, ws.part, stream));
+        DCG_HIP(launch_reduce(ws.part, nbA, flex ? kRedFcgAlpha : kRedAlpha, ws.sc, stream));
+        int nbu = 0;
+        DCG_HIP(launch_cg_update(flex, N, ws.sc, ws.p[pidx], ws.q, ws.xh, ws.r, ws.part, &nbu,
+                                 stream));
+        DCG_HIP(launch_reduce(ws.part, nbu, flex ? kRedFcgBeta : kRedBeta, ws.sc, stream));
+        ++it;
+        read_scalars(h, stream);
+        if (atimed) {   // both events have completed: read_scalars synchronised the stream
+          float ms = 0.0f;
+          DCG_HIP(hipEventElapsedTime(&ms, h->aev[0], h->aev[1]));
+          h->atime_ms += ms;
+          ++h->alaunches;
+        }
+        if (ws.sc_host->breakdown) {
+          status = DCG_EBREAKDOWN;
+          break;
+        }
+        rho = ws.sc_host->rho;
+        if (!std::isfinite(rho)) {
+          status = DCG_EBREAKDOWN;
+          break;
+        }
+      }
+    }
+    stats.rel_res_recurrence = std::sqrt(std::max(rho, 0.0) / b2);
+
+    // epilogue: x = (x_hat - pi(A* x_hat)) + pi(b)  (eq. (x_defl))
     DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
                          ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
     cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
     ++inner_solves;
-    DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zt, ws.w, ws.w, ws.q, nullptr,
-                           ws.part, stream));
-    int nbu = 0;
-    DCG_HIP(launch_axpy_dot(N, -1.0, ws.q, ws.r, ws.part, &nbu, stream));
-    DCG_HIP(launch_reduce(ws.part, nbu, kRedRho, ws.sc, stream));
+    DCG_HIP(launch_reconstruct(ne, ws.xh, ws.zt, ws.zb, ws.sc, x, stream));
+    DCG_HIP(launch_astar(kAstarResidual, m.Cdiv, m.cols, m.M1, ne, x, nullptr, b, ws.sc,
+                         nullptr, ws.w, nullptr, ws.part, stream));
+    DCG_HIP(launch_reduce(ws.part, nbA, kRedRes, ws.sc, stream));
     read_scalars(h, stream);
-  } else {
-    DCG_HIP(launch_fill<double>(N, 0.0, ws.xh, stream));
+    rel_true = std::sqrt(ws.sc_host->res2 / b2);
+    if (status != DCG_OK || rel_true <= tol || pass >= h->opt.restarts) break;
+    // Algorithm 2 again from x_0 = x: restore r = f_D from the stored pi(b)
+    ++pass;
+    warm = true;
+    DCG_HIP(launch_deflate(true, m.AdivZ, m.cols, ne, kTwo, ws.zb, b, nullptr, ws.r, ws.p[0],
+                           ws.part, stream));
+    DCG_HIP(launch_reduce(ws.part, nbA, kRedB2Rho, ws.sc, stream));
   }
-
-  const double lim = tol * tol * b2;
-  double rho = ws.sc_host->rho;
-  auto tol_outer = [&](double rho_i) {
-    return adaptive ? h->opt.c_A * tol * std::sqrt(b2) / std::sqrt(rho_i) : tol_c;
-  };
-  int it = 0, pidx = 0;
-  dcg_status status = DCG_OK;
-  if (h->opt.outer == DCG_OUTER_FCG) {
-    status = outer_fcg(h, lim, rho, it, cycles_total, cycles_outer, inner_solves, tol_outer, stream);
-  } else if (h->opt.outer == DCG_OUTER_GMRES) {
-    status = outer_gmres(h, lim, rho, it, cycles_total, cycles_outer, inner_solves, tol_outer,
-                         stream);
-  } else {
-    while (true) {
-      if (rho <= lim) break;
-      if (it >= h->opt.max_outer) {
-        status = DCG_NOT_CONVERGED;
-        break;
-      }
-      // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
-      const bool atimed = h->ktime;
-      if (atimed) DCG_HIP(hipEventRecord(h->aev[0], stream));
-      DCG_HIP(launch_astar(it == 0 ? kAstarFirst : kAstarDir, m.Cdiv, m.cols, m.M1, ne,
-                           ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
-                           stream));
-      if (atimed) DCG_HIP(hipEventRecord(h->aev[1], stream));
-      pidx = 1 - pidx;
-      const int c = inner(h, ws.s, ws.zref, tol_outer(rho), stream);
-      cycles_total += c;
-      cycles_outer += c;
-      ++inner_solves;
-      // q = w - A* Z y = M_D p  (y = (2/dt) z)
-      DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, ws.zref, ws.w, ws.p[pidx], ws.q,
-                             nullptr, ws.part, stream));
-      DCG_HIP(launch_reduce(ws.part, nbA, flex ? kRedFcgAlpha : kRedAlpha, ws.sc, stream));
-      int nbu = 0;
-      DCG_HIP(launch_cg_update(flex, N, ws.sc, ws.p[pidx], ws.q, ws.xh, ws.r, ws.part, &nbu,
-                               stream));
-      DCG_HIP(launch_reduce(ws.part, nbu, flex ? kRedFcgBeta : kRedBeta, ws.sc, stream));
-      ++it;
-      read_scalars(h, stream);
-      if (atimed) {   // both events have completed: read_scalars synchronised the stream
-        float ms = 0.0f;
-        DCG_HIP(hipEventElapsedTime(&ms, h->aev[0], h->aev[1]));
-        h->atime_ms += ms;
-        ++h->alaunches;
-      }
-      if (ws.sc_host->breakdown) {
-        status = DCG_EBREAKDOWN;
-        break;
-      }
-      rho = ws.sc_host->rho;
-      if (!std::isfinite(rho)) {
-        status = DCG_EBREAKDOWN;
-        break;
-      }
-    }
-  }
-  stats.rel_res_recurrence = std::sqrt(std::max(rho, 0.0) / b2);
-
-  // epilogue: x = (x_hat - pi(A* x_hat)) + pi(b)  (eq. (x_defl))
-  DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, ws.xh, nullptr, nullptr,
-                       ws.sc, nullptr, ws.w, ws.s, nullptr, stream));
-  cycles_total += inner(h, ws.s, ws.zt, tol_c, stream);
-  ++inner_solves;
-  DCG_HIP(launch_reconstruct(ne, ws.xh, ws.zt, ws.zb, ws.sc, x, stream));
-  DCG_HIP(launch_astar(kAstarResidual, m.Cdiv, m.cols, m.M1, ne, x, nullptr, b, ws.sc,
-                       nullptr, ws.w, nullptr, ws.part, stream));
-  DCG_HIP(launch_reduce(ws.part, nbA, kRedRes, ws.sc, stream));
-  read_scalars(h, stream);
-  stats.rel_res_true = std::sqrt(ws.sc_host->res2 / b2);
+  if (h->opt.restarts > 0 && status == DCG_OK && rel_true > tol) status = DCG_NOT_CONVERGED;
+  stats.restarts = pass;
+  stats.rel_res_true = rel_true;
   stats.status = status;
   stats.outer_iters = it;
   stats.total_wcycles = cycles_total;
@@ -665,6 +683,7 @@ void apply_level(dcg_ctx* h, dcg_op op, int k, const void* in, const void* in2, 
   T* y = static_cast<T*>(out);
   Cycle<T> cyc(m, h->ws.lvb, h->mp.pre, h->mp.post);
   cyc.base = h->lbase;
+  cyc.group = h->opt.ras_group;
   if (h->lbase > 0) cyc.cfdm = &h->cfdm;
   switch (op) {
     case DCG_OP_LAPLACE:

@@ -25,6 +25,21 @@ struct SweepTimer {
 
 inline int waves_per_tile(int tiles) { return tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4); }
 
+// Tiles per side of a workgroup of the grouped (MFMA) RAS step, 0 for the
+// per-tile kernel.  ``choice`` is dcg_options.ras_group: 0 picks by level
+// size, -1 forces the per-tile kernel, 1 / 2 / 4 that group side.  Measured
+// on MI355X (FP32): 4 x 4 groups take 15 against 52 us per step at n = 512
+// and 9 against 17 us at n = 256; at n = 128 (64 groups) the per-tile kernel
+// with two wavefronts per tile is faster (9 against 11 us).
+#ifndef DCG_GROUP_MIN_TILES
+#define DCG_GROUP_MIN_TILES 4096
+#endif
+inline int ras_group_side(int tiles, int choice) {
+  if (choice < 0) return 0;
+  if (choice > 0) return choice;
+  return tiles >= DCG_GROUP_MIN_TILES ? 4 : 0;
+}
+
 template <typename T>
 const T* level_L(const DeviceLevel& d);
 template <>
@@ -44,6 +59,12 @@ inline const float* level_dw<float>(const DeviceLevel& d) { return d.dw32; }
 template <>
 inline const double* level_dw<double>(const DeviceLevel& d) { return d.dw64; }
 template <typename T>
+const T* level_Fm(const DeviceLevel& d);
+template <>
+inline const float* level_Fm<float>(const DeviceLevel& d) { return d.Fm32; }
+template <>
+inline const double* level_Fm<double>(const DeviceLevel& d) { return d.Fm64; }
+template <typename T>
 const T* level_F(const DeviceLevel& d);
 template <>
 inline const float* level_F<float>(const DeviceLevel& d) { return d.F32; }
@@ -62,6 +83,7 @@ struct Cycle {
   SweepTimer timer;
   int base = 0;
   const CoarseFdm* cfdm = nullptr;
+  int group = 0;                  // dcg_options.ras_group
 
   Cycle(const MeshContext& mesh, const LevelBuffers& bufs, int m1, int m2)
       : m(mesh), b(bufs), pre(m1), post(m2) {}
@@ -78,6 +100,7 @@ struct Cycle {
     const DeviceLevel& d = lev(k);
     SweepArgs<T> a;
     a.F = level_F<T>(d);
+    a.Fm = level_Fm<T>(d);
     a.fcls = d.fcls;
     a.dw = level_dw<T>(d);
     a.ext = d.tile_ext;
@@ -107,8 +130,15 @@ struct Cycle {
     a.Y_new = Y(k, 1 - s.yb);
     const bool timed = timer.ev && k + base == m.J && *timer.rec < timer.max;
     if (timed) DCG_HIP(hipEventRecord(timer.ev[2 * *timer.rec], st));
+    const int gx = ras_group_side(d.tiles, group);
     if (b.batched)
       DCG_HIP(launch_sweep_b<T>(a, st));
+    else if (gx > 0) {
+      const int gi = gx == 1 ? 0 : (gx == 2 ? 1 : 2);
+      a.gextra = d.gx_extra[gi];
+      a.nextra = d.gx_extra_n[gi];
+      DCG_HIP(launch_sweep_g<T>(a, gx, st));
+    }
     else
       DCG_HIP(launch_sweep<T>(a, waves_per_tile(d.tiles), st));
     if (timed) DCG_HIP(hipEventRecord(timer.ev[2 * (*timer.rec)++ + 1], st));

@@ -1,6 +1,7 @@
 """Parity at the headline size, n = 512 (J = 6), in the launch
-configuration the benchmark times: the finest RAS step runs one wavefront
-per tile over 16,384 tiles.  The oracle cannot form the whole step at this
+configuration the benchmark times: the finest RAS step runs one workgroup
+per 4 x 4 tiles (1,024 groups over the 16,384 tiles, MFMA tile solves); the
+per-tile kernel (one wavefront per tile) is checked beside it.  The oracle cannot form the whole step at this
 size in seconds, so sampled outputs are compared one by one: for a sampled
 square e, z'_e = z_e + sum over the blocks i containing e of
 (D_i (L_J)_i^{-1} R_i (f - L_J z))_e with the oracle's independently assembled
@@ -41,13 +42,14 @@ def _sampled_squares(n, rng, count=40):
     return sorted(set(fixed + [int(e) for e in rng.integers(0, n * n, count)]))
 
 
+@pytest.mark.parametrize("group", [0, -1], ids=["grouped", "per-tile"])
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_finest_ras_step_on_sampled_squares(prec):
+def test_finest_ras_step_on_sampled_squares(prec, group):
     fx = _fixture()
     L, blocks, weights, cover = fx["L"], fx["blocks"], fx["weights"], fx["cover"]
     J = lib.dcg_num_levels(N512)
     real = torch.float32 if prec == "mixed" else torch.float64
-    solver = dcg.Solver(N512, 1e-4, prec=prec)
+    solver = dcg.Solver(N512, 1e-4, prec=prec, ras_group=group)
     rng = np.random.default_rng(512)
     m = 4 * N512 * N512
     f_d = torch.from_numpy(rng.standard_normal(m)).to("cuda", real)

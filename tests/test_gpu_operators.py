@@ -249,3 +249,55 @@ def test_ras_sweep_and_wcycle_on_wide_levels(n, prec):
     rho_gpu = np.linalg.norm(fr - A @ got) / np.linalg.norm(fr)
     rho_ref = np.linalg.norm(fr - A @ ref) / np.linalg.norm(fr)
     assert abs(rho_gpu - rho_ref) <= (1e-3 if prec == "mixed" else 1e-10)
+
+
+# ---------------------------------------------------------------- RAS kernels
+# The RAS step has two kernels: one tile per wavefront group (ras_group = -1)
+# and one workgroup per g x g tiles with the tile solves as MFMA products of
+# each class inverse with the group's residual columns (g = 1, 2, 4; a group
+# at the boundary holds tiles of up to four classes and runs one masked
+# product per class).  At n = 32 and 64 every level has boundary groups, and
+# with g = 4 on the 16 x 16 level one group holds all nine classes.
+_GROUPED = {}
+
+
+def _grouped_solver(case, g):
+    key = (case.n, case.prec, g)
+    if key not in _GROUPED:
+        _GROUPED[key] = dcg.Solver(case.n, DT, prec=case.prec, ras_group=g)
+    return _GROUPED[key]
+
+
+@pytest.mark.parametrize("g", [-1, 1, 2, 4])
+def test_ras_step_of_every_kernel(case, g):
+    solver = _grouped_solver(case, g)
+    for k in range(2, case.H.J + 1):
+        nk = case.H.n[k]
+        rng = np.random.default_rng(150 + k)
+        f = rng.standard_normal(4 * nk * nk)
+        z = rng.standard_normal(4 * nk * nk) * 1e-3
+        out = torch.empty(4 * nk * nk, dtype=case.real, device="cuda")
+        solver.apply(lib.DCG_OP_RAS, _dev(f, case.real), out, level=k, in2=_dev(z, case.real))
+        fr, zr = _host(_dev(f, case.real)), _host(_dev(z, case.real))
+        ref = zr + case.H.S[k].apply(fr - case.H.A[k] @ zr)
+        assert _relerr(_host(out), ref) < 10 * case.tol, (g, k)
+
+
+@pytest.mark.parametrize("g", [-1, 1, 2, 4])
+def test_wcycle_of_every_kernel(case, g):
+    # the cycle adds the prolongated coarse correction inside the first
+    # post-smoothing step of each level, a path of the RAS kernel of its own
+    solver = _grouped_solver(case, g)
+    k = case.H.J
+    nk = case.H.n[k]
+    # FP64: a cycle's error grows like eps kappa(L_k) ~ eps n_k^2 (the bar of
+    # the wide-level test); FP32 as in test_wcycle
+    bar = 2e-3 if case.prec == "mixed" else 16 * float(np.finfo(np.float64).eps) * nk * nk
+    rng = np.random.default_rng(160)
+    f = rng.standard_normal(4 * nk * nk)
+    z0 = rng.standard_normal(4 * nk * nk) * 1e-3
+    out = torch.empty(4 * nk * nk, dtype=case.real, device="cuda")
+    solver.apply(lib.DCG_OP_WCYCLE, _dev(f, case.real), out, level=k, in2=_dev(z0, case.real))
+    fr, zr = _host(_dev(f, case.real)), _host(_dev(z0, case.real))
+    ref = mg.wcycle(case.H, fr, zr, k)
+    assert _relerr(_host(out), ref) < bar, g

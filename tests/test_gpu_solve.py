@@ -24,8 +24,8 @@ import paper_2606_13429_amd as dcg  # noqa: E402
 _ORACLE = {}
 
 
-def _oracle(n, dt, seed, tol, outer="cg", inner="mg"):
-    key = (n, dt, seed, tol, outer, inner)
+def _oracle(n, dt, seed, tol, outer="cg", inner="mg", **extra):
+    key = (n, dt, seed, tol, outer, inner, tuple(sorted(extra.items())))
     if key not in _ORACLE:
         As = d.operator(n, dt)
         V = d.deflation_basis(n)
@@ -33,7 +33,7 @@ def _oracle(n, dt, seed, tol, outer="cg", inner="mg"):
         f = elem_to_comp(rhs(n, seed), n)
         inn = kr.exact_inner(E) if inner == "exact" or n == 16 else kr.mg_inner(mg.Hierarchy(E, n))
         kw = dict(outer="fcg", m_max=1) if outer == "fcg1" else {}
-        _ORACLE[key] = kr.dcg(As, V, f, inn, tol=tol, **kw)
+        _ORACLE[key] = kr.dcg(As, V, f, inn, tol=tol, **kw, **extra)
     return _ORACLE[key]
 
 
@@ -266,3 +266,25 @@ def test_kernel_timing_samples_every_kth_wcycle():
     with pytest.raises(lib.DCGError):
         lib.dcg_kernel_timing(s.handle, -1)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_restart_meets_tol_on_the_true_residual(prec):
+    # c_F tol = 1e-8: the first pass stops on the recurrence residual with a
+    # true residual above tol, and one warm restart from the returned x meets
+    # tol; the oracle takes the same pass (counts and x as in the main gate)
+    n, dt, tol = 32, 1e-3, 1e-8
+    ref = _oracle(n, dt, 0, tol, c_F=1.0, restarts=2)
+    assert ref.restarts == 1 and ref.rel_res_true <= tol
+    status, st, x, _ = _gpu(n, dt, 0, tol, prec, c_F=1.0, restarts=2)
+    assert status == lib.DCG_OK
+    assert st.restarts == ref.restarts
+    assert abs(st.outer_iters - ref.iterations) <= 2, (st.outer_iters, ref.iterations)
+    assert st.rel_res_true <= tol
+    xr = comp_to_elem(ref.x, n)
+    assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr)
+    # without restarts the same solve ends on the recurrence test alone
+    plain = _oracle(n, dt, 0, tol, c_F=1.0)
+    status0, st0, _, _ = _gpu(n, dt, 0, tol, prec, c_F=1.0)
+    assert status0 == lib.DCG_OK and st0.restarts == 0
+    assert st0.rel_res_true > tol and plain.rel_res_true > tol
