@@ -275,11 +275,13 @@ __global__ __launch_bounds__(kThreads) void k_axpy_dot(int64_t n, double a,
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ part, int nb,
-                                                     int op, Scalars* __restrict__ sc, Slots sl) {
+                                                     int op, Scalars* __restrict__ sc, Slots sl,
+                                                     double aux, int iaux) {
   __shared__ double sm[kThreads];
   const int slot = slot_id(sl);
   part += slot * kSlotPart;
   sc += slot;
+  if (op == kRedInnerR2 && sc->inner_done) return;   // the partials were not recomputed
   const int nslot = op == kRedB2Rho ? 2 : (op == kRedFcgBeta ? 3 : 1);
   double sums[3] = {0.0, 0.0, 0.0};
   for (int slot = 0; slot < nslot; ++slot) {
@@ -328,6 +330,18 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ 
     case kRedS2:
       sc->s2 = sums[0];
       sc->r2 = sums[0];
+      break;
+    case kRedInnerS2:
+      sc->s2 = sums[0];
+      sc->r2 = sums[0];
+      sc->inner_lim2 = aux * sums[0];
+      sc->inner_cycles = 0;
+      sc->inner_done = !(sums[0] > aux * sums[0]) || iaux <= 0;
+      break;
+    case kRedInnerR2:
+      sc->r2 = sums[0];
+      sc->inner_cycles += 1;
+      sc->inner_done = !(sums[0] > sc->inner_lim2) || sc->inner_cycles >= iaux;
       break;
     case kRedR2:
       sc->r2 = sums[0];
@@ -477,8 +491,10 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, double c,
 template <typename T, bool FIRST>
 __global__ __launch_bounds__(kThreads) void k_refine_residual(
     const double* __restrict__ Lc, int n, int ne, const double* __restrict__ s,
-    const double* __restrict__ z, T* __restrict__ fJ, double* __restrict__ part, Slots sl) {
+    const double* __restrict__ z, T* __restrict__ fJ, double* __restrict__ part, Slots sl,
+    const Scalars* __restrict__ guard) {
   __shared__ double lds[4];
+  if (guard && guard->inner_done) return;
   const int slot = slot_id(sl);
   s += slot * sl.sstride;
   if (z) z += slot * sl.sstride;
@@ -714,8 +730,8 @@ hipError_t launch_axpy_dot(int64_t nvec, double a, const double* q, double* r, d
 }
 
 hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st,
-                         const Slots& sl, int count) {
-  k_reduce<<<dim3(1, count), kThreads, 0, st>>>(part, nblocks, op, sc, sl);
+                         const Slots& sl, int count, double aux, int iaux) {
+  k_reduce<<<dim3(1, count), kThreads, 0, st>>>(part, nblocks, op, sc, sl, aux, iaux);
   return hipGetLastError();
 }
 
@@ -755,13 +771,13 @@ int refine_blocks(int ne) { return grid_for(ne, 64, kPartStride); }
 template <typename T>
 hipError_t launch_refine_residual(bool first, const double* Lc64, int n, int ne, const double* s,
                                   const double* z, T* fJ, double* part, hipStream_t st,
-                                  const Slots& sl, int count) {
+                                  const Slots& sl, int count, const Scalars* guard) {
   if (!Lc64 || n < 3 || int64_t(n) * n != ne) return hipErrorInvalidValue;
   const dim3 grid(refine_blocks(ne), count);
   if (first)
-    k_refine_residual<T, true><<<grid, kThreads, 0, st>>>(Lc64, n, ne, s, z, fJ, part, sl);
+    k_refine_residual<T, true><<<grid, kThreads, 0, st>>>(Lc64, n, ne, s, z, fJ, part, sl, guard);
   else
-    k_refine_residual<T, false><<<grid, kThreads, 0, st>>>(Lc64, n, ne, s, z, fJ, part, sl);
+    k_refine_residual<T, false><<<grid, kThreads, 0, st>>>(Lc64, n, ne, s, z, fJ, part, sl, guard);
   return hipGetLastError();
 }
 
@@ -812,7 +828,7 @@ hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t st) {
 #define DCG_INSTANTIATE(T)                                                                      \
   template hipError_t launch_refine_residual<T>(bool, const double*, int, int, const double*,  \
                                                 const double*, T*, double*, hipStream_t,       \
-                                                const Slots&, int);                            \
+                                                const Slots&, int, const Scalars*);            \
   template hipError_t launch_lap<T>(bool, const T*, const int32_t*, int, const T*, const T*, T*, \
                                     hipStream_t);                                              \
   template hipError_t launch_restrict<T>(int, const T*, T*, hipStream_t);                      \

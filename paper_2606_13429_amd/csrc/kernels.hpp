@@ -36,9 +36,12 @@ struct Scalars {
   double res2;      // ||b - A* x||^2 or the last plain dot
   double s2, r2;    // inner iteration: ||s||^2 and ||s - L z||^2
   double dt, inv_nu;  // operator parameters of this request (A* = (1/nu) M + dt A_div)
-  double spare[5];
+  double inner_lim2;  // inner iteration tested on the device: tol_c^2 ||s||^2
+  double spare[4];
   int32_t breakdown;
-  int32_t pad[3];
+  int32_t inner_done;    // the inner iteration has met its test or its cycle cap
+  int32_t inner_cycles;  // W-cycles the inner iteration has counted
+  int32_t pad;
 };
 
 enum ReduceOp : int {
@@ -51,7 +54,10 @@ enum ReduceOp : int {
   kRedFcgAlpha = 6,  // slot (d,q)                  -> pq, alpha = dr / pq
   kRedFcgBeta = 7,   // slots (r,r),(r,q),(d,r)     -> rho, beta = -(r,q)/pq, dr
   kRedRho = 8,       // slot (r,r)                  -> rho (and dr = rho)
-  kRedDr = 9         // slot (d,r)                  -> dr
+  kRedDr = 9,        // slot (d,r)                  -> dr
+  // the inner iteration's test on the device (aux = tol_c^2, iaux = max cycles):
+  kRedInnerS2 = 10,  // slot ||s||^2                -> s2 = r2, inner_lim2 = aux s2, cycles 0, done
+  kRedInnerR2 = 11   // slot ||s - L z||^2          -> unless done: r2, ++cycles, done
 };
 
 constexpr int kPartStride = 1 << 16;   // max blocks of a reducing launch
@@ -121,7 +127,7 @@ hipError_t launch_cg_update(bool flexible, int64_t nvec, const Scalars* sc, cons
 hipError_t launch_axpy_dot(int64_t nvec, double a, const double* q, double* r, double* part,
                            int* nblocks, hipStream_t st);
 hipError_t launch_reduce(const double* part, int nblocks, int op, Scalars* sc, hipStream_t st,
-                         const Slots& sl = Slots(), int count = 1);
+                         const Slots& sl = Slots(), int count = 1, double aux = 0.0, int iaux = 0);
 
 hipError_t launch_zt(int ne, const double* w, double* s, hipStream_t st, const Slots& sl = Slots(),
                      int count = 1);
@@ -154,10 +160,12 @@ hipError_t launch_fcg_direction(int64_t n, const double* r, const double* const*
 
 // inner refinement (FP64 residual of the level-J Laplacian): Lc64 is the
 // class table of L_J on the n x n grid (ne = n^2 squares)
+// (guard: when non-null, the launch does nothing once guard->inner_done is set)
 template <typename T>
 hipError_t launch_refine_residual(bool first, const double* Lc64, int n, int ne, const double* s,
                                   const double* z, T* fJ, double* part, hipStream_t st,
-                                  const Slots& sl = Slots(), int count = 1);
+                                  const Slots& sl = Slots(), int count = 1,
+                                  const Scalars* guard = nullptr);
 
 // multigrid level kernels
 template <typename T>
@@ -235,7 +243,8 @@ hipError_t launch_resolve(int ne, bool has_z, const T* z, const T* Ye, T* out, h
 // (z and Ye addressed through sl.lsq / sl.lstride)
 template <typename T>
 hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T* z, const T* Ye,
-                             double* z64, hipStream_t st, const Slots& sl = Slots(), int count = 1);
+                             double* z64, hipStream_t st, const Slots& sl = Slots(), int count = 1,
+                             const Scalars* guard = nullptr);
 
 // ------------------------------------------------------------ batched cycle
 // The same steps on kBatch request-interleaved columns (mg_batch.hip): the

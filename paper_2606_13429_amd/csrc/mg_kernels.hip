@@ -623,7 +623,9 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_refine_add(int ne, int first, int has_z, int has_y,
                                                          const T* __restrict__ z,
                                                          const T* __restrict__ Ye,
-                                                         double* __restrict__ z64, Slots sl) {
+                                                         double* __restrict__ z64, Slots sl,
+                                                         const Scalars* __restrict__ guard) {
+  if (guard && guard->inner_done) return;
   const int slot = sl.list ? sl.list[blockIdx.y] : 0;
   z += slot * sl.lstride;
   Ye += slot * sl.lstride;
@@ -690,10 +692,11 @@ hipError_t launch_resolve(int ne, bool has_z, const T* z, const T* Ye, T* out, h
 
 template <typename T>
 hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T* z, const T* Ye,
-                             double* z64, hipStream_t st, const Slots& sl, int count) {
+                             double* z64, hipStream_t st, const Slots& sl, int count,
+                             const Scalars* guard) {
   const int64_t n = 4 * (int64_t)ne;
   k_refine_add<T><<<dim3(int((n + kThreads - 1) / kThreads), count), kThreads, 0, st>>>(
-      ne, first, has_z, has_y, z, Ye, z64, sl);
+      ne, first, has_z, has_y, z, Ye, z64, sl, guard);
   return hipGetLastError();
 }
 
@@ -703,7 +706,7 @@ hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T
   template hipError_t launch_restrict_res<T>(const RestrictArgs<T>&, hipStream_t);            \
   template hipError_t launch_resolve<T>(int, bool, const T*, const T*, T*, hipStream_t);      \
   template hipError_t launch_refine_add<T>(int, bool, bool, bool, const T*, const T*, double*, \
-                                           hipStream_t, const Slots&, int);
+                                           hipStream_t, const Slots&, int, const Scalars*);
 
 DCG_MG_INSTANTIATE(float)
 DCG_MG_INSTANTIATE(double)

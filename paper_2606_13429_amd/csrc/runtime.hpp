@@ -164,10 +164,10 @@ struct dcg_ctx {
   double t_setup_ms = 0.0;
   int device = 0;
   // live timing of the finest-level RAS tile kernel
-  static constexpr int kMaxTimed = 32;
+  static constexpr int kMaxTimed = 256;   // event pairs between two reads of the stream
   bool ktime = false;
   hipEvent_t kev[2 * kMaxTimed] = {};
-  int krec = 0;                 // event pairs recorded by the current cycle
+  int krec = 0;                 // event pairs recorded since they were last read
   int kstride = 1;              // time the finest steps of every kstride-th W-cycle
   int64_t kcycle = 0;           // W-cycles since timing was enabled
   double ktime_ms = 0.0;
@@ -176,6 +176,11 @@ struct dcg_ctx {
   hipEvent_t aev[2] = {};
   double atime_ms = 0.0;
   int64_t alaunches = 0;
+  // W-cycle counts of the last inner solves: the inner iteration enqueues as
+  // many cycles as the fewest of them before reading its device-side test
+  static constexpr int kInnerRecent = 4;
+  int inner_recent[kInnerRecent] = {1, 1, 1, 1};
+  int inner_next = 0;
   // exact inner solve (DCG_INNER_EXACT): fast-diagonalisation factors and
   // three scratch vectors, all in the workspace
   bool exact = false;

@@ -110,7 +110,7 @@ Cycle<T> make_cycle(dcg_ctx* h) {
   return c;
 }
 
-// Adds the elapsed times of the event pairs recorded by the last W-cycle
+// Adds the elapsed times of the event pairs recorded since the last call
 // (called after the stream has been synchronised).
 void collect_kernel_times(dcg_ctx* h) {
   if (!h->ktime) return;
@@ -120,6 +120,7 @@ void collect_kernel_times(dcg_ctx* h) {
     h->ktime_ms += ms;
     ++h->klaunches;
   }
+  h->krec = 0;
 }
 
 // Finest-level W-cycle from a zero initial guess; returns the finest state.
@@ -132,7 +133,6 @@ LvState run_wcycle_finest(dcg_ctx* h, hipStream_t st) {
   MeshContext& m = *h->mesh;
   const int J = m.J - h->lbase;   // levels of the cycle's own hierarchy
   const Cycle<T> cyc = make_cycle<T>(h);
-  h->krec = 0;
   LvState s;
   if (J == 1 || !h->opt.use_graph) {
     cyc.wcycle(J, s, st);
@@ -192,6 +192,13 @@ void read_scalars(dcg_ctx* h, hipStream_t st) {
 // cycle is applied to the current FP64 residual and added in FP64, which for
 // a linear cycle equals Wcycle(s, z) (iterative refinement form).  Returns
 // the number of W-cycles.
+//
+// The test runs on the device (the reduction of ||s - L z||^2 sets the
+// scalar block's inner_done), so the host enqueues cycles ahead of it: as
+// many as the fewest the last inner solves took, then one at a time until
+// the flag is read set.  A cycle enqueued after the test was met still runs
+// its level kernels on scratch buffers, but its update of z, residual and
+// count are no-ops, so z and the count are those of Algorithm 3.
 template <typename T>
 int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
   MeshContext& m = *h->mesh;
@@ -199,32 +206,39 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
   const int64_t mlen = 4 * int64_t(fine.ne);
   T* fJ = static_cast<T*>(h->ws.lvb.f[m.J - 1]);
   const int nb = refine_blocks(fine.ne);
+  const int max_inner = h->opt.max_inner;
+  const Scalars* guard = h->ws.sc;
   DCG_HIP(launch_refine_residual<T>(true, fine.Lc64, fine.n, fine.ne, s, nullptr, fJ, h->ws.part,
                                     st));
-  DCG_HIP(launch_reduce(h->ws.part, nb, kRedS2, h->ws.sc, st));
-  read_scalars(h, st);
-  const double s2 = h->ws.sc_host->s2;
-  if (!std::isfinite(s2)) throw Error(DCG_EINVAL, "non-finite inner right-hand side");
-  int cycles = 0;
-  if (s2 > 0.0) {
-    double r2 = s2;
-    const double lim = tol_c * tol_c * s2;
-    while (cycles < h->opt.max_inner && r2 > lim) {
+  DCG_HIP(launch_reduce(h->ws.part, nb, kRedInnerS2, h->ws.sc, st, Slots(), 1, tol_c * tol_c,
+                        max_inner));
+  DCG_HIP(launch_fill<double>(mlen, 0.0, z, st));
+  int ahead = max_inner;
+  for (int c : h->inner_recent) ahead = std::min(ahead, c);
+  ahead = std::max(ahead, 1);
+  int enqueued = 0;
+  while (true) {
+    const int batch = std::min(ahead, max_inner - enqueued);
+    for (int i = 0; i < batch; ++i, ++enqueued) {
       const LvState fs = run_wcycle_finest<T>(h, st);
-      DCG_HIP(launch_refine_add<T>(fine.ne, cycles == 0, fs.has_z, fs.has_y,
+      DCG_HIP(launch_refine_add<T>(fine.ne, false, fs.has_z, fs.has_y,
                                    static_cast<T*>(h->ws.lvb.z[fs.zb][m.J - 1]),
-                                   static_cast<T*>(h->ws.lvb.Y[fs.yb][m.J - 1]), z, st));
+                                   static_cast<T*>(h->ws.lvb.Y[fs.yb][m.J - 1]), z, st, Slots(), 1,
+                                   guard));
       DCG_HIP(launch_refine_residual<T>(false, fine.Lc64, fine.n, fine.ne, s, z, fJ, h->ws.part,
-                                        st));
-      DCG_HIP(launch_reduce(h->ws.part, nb, kRedR2, h->ws.sc, st));
-      read_scalars(h, st);
-      collect_kernel_times(h);
-      r2 = h->ws.sc_host->r2;
-      ++cycles;
-      if (!std::isfinite(r2)) throw Error(DCG_EBREAKDOWN, "non-finite inner residual");
+                                        st, Slots(), 1, guard));
+      DCG_HIP(launch_reduce(h->ws.part, nb, kRedInnerR2, h->ws.sc, st, Slots(), 1, 0.0,
+                            max_inner));
     }
+    read_scalars(h, st);
+    collect_kernel_times(h);
+    if (!std::isfinite(h->ws.sc_host->s2)) throw Error(DCG_EINVAL, "non-finite inner right-hand side");
+    if (h->ws.sc_host->inner_done || enqueued >= max_inner) break;
+    ahead = 1;
   }
-  if (cycles == 0) DCG_HIP(launch_fill<double>(mlen, 0.0, z, st));
+  if (!std::isfinite(h->ws.sc_host->r2)) throw Error(DCG_EBREAKDOWN, "non-finite inner residual");
+  const int cycles = h->ws.sc_host->inner_cycles;
+  h->inner_recent[h->inner_next++ % dcg_ctx::kInnerRecent] = std::max(cycles, 1);
   return cycles;
 }
 

@@ -247,18 +247,22 @@ def test_no_deflation_is_plain_cg(n, dt):
 
 def test_kernel_timing_samples_every_kth_wcycle():
     # m1 + m2 = 4 finest-level RAS steps per W-cycle; with stride k the steps
-    # of W-cycles 0, k, 2k, ... since the enable are timed
+    # of enqueued W-cycles 0, k, 2k, ... since the enable are timed.  The
+    # inner iteration enqueues cycles ahead of its device-side test, so the
+    # enqueued cycles are the counted ones plus a few that ran after the test
+    # was met (same kernels, same work)
     s = dcg.Solver(64, 1e-3, prec="mixed")
     b = torch.from_numpy(rhs(64, 2)).cuda()
     x = torch.empty_like(b)
     lib.dcg_kernel_timing(s.handle, 1)
     _, st = s.solve(b, x, 1e-8)
     ms1, n1 = lib.dcg_kernel_timing_read(s.handle)
-    assert n1 == 4 * st.total_wcycles and ms1 > 0
+    assert n1 % 4 == 0 and n1 >= 4 * st.total_wcycles and ms1 > 0
+    assert n1 <= 4 * (st.total_wcycles + st.inner_solves * 2)
     lib.dcg_kernel_timing(s.handle, 4)
     _, st = s.solve(b, x, 1e-8)
     ms4, n4 = lib.dcg_kernel_timing_read(s.handle)
-    assert n4 == 4 * ((st.total_wcycles + 3) // 4) and ms4 > 0
+    assert n4 % 4 == 0 and abs(n4 - n1 / 4) <= 4 and ms4 > 0
     assert 0.5 < (ms4 / n4) / (ms1 / n1) < 2.0
     lib.dcg_kernel_timing(s.handle, 0)
     _, st = s.solve(b, x, 1e-8)
