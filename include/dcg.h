@@ -234,6 +234,26 @@ typedef enum {
 dcg_status dcg_apply(dcg_handle h, dcg_op op, int32_t level, const void* in,
                      const void* in2, void* out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): dcg_apply's
+ * DCG_OP_INNER and DCG_OP_DEFLATED (same operands, same kernels, same result)
+ * with every buffer the kernels write besides `out` -- the scalar block,
+ * partial sums, the inner iterate, the W-cycle's level vectors and, for
+ * DCG_OP_DEFLATED, A* p and Z^T A* p -- in one static device array of
+ * dcg_noalloc_bytes() bytes (48 MiB: every mesh up to n = 256 in either
+ * precision) instead of the handle's workspace.  The call allocates nothing;
+ * each device it runs on holds its own copy of the array until the process
+ * ends.  The handle must use the multigrid inner solve (DCG_INNER_MG).
+ * Returns DCG_EINVAL for another op or inner solver, and for a mesh whose
+ * buffers exceed the array (the message gives both sizes).  The handle's
+ * device is made current for the call.  The array is shared by every call
+ * on a device and keeps the previous call's contents: calls that overlap on
+ * one device (other threads, other streams) race and must be serialised by
+ * the caller.  Blocks until done, like dcg_apply. */
+dcg_status dcg_apply_noalloc(dcg_handle h, dcg_op op, const double* in, double* out,
+                             void* hip_stream);
+int64_t dcg_noalloc_bytes(void);
+
 /* Number of multigrid levels J of a mesh (log2(n/16) + 1), or -1. */
 int32_t dcg_num_levels(int32_t n);
 

@@ -69,6 +69,8 @@ _SIGS = {
     "dcg_setup": (ctypes.c_int, [_P(dcg_mesh), ctypes.c_double, ctypes.c_double, _P(dcg_options), _P(_h)]),
     "dcg_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.c_double, _P(dcg_stats), _vp]),
     "dcg_apply": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    "dcg_apply_noalloc": (ctypes.c_int, [_h, ctypes.c_int, _vp, _vp, _vp]),
+    "dcg_noalloc_bytes": (ctypes.c_int64, []),
     "dcg_num_levels": (ctypes.c_int32, [ctypes.c_int32]),
     "dcg_host_assemble": (ctypes.c_int, [_P(dcg_mesh), ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double),
                                          ctypes.c_int64, _P(ctypes.c_int32), ctypes.c_int64, _P(ctypes.c_int64)]),
@@ -184,6 +186,15 @@ def dcg_solve(handle, b, x, tol, stream=None):
 def dcg_apply(handle, op, level, inp, in2, out, stream=None):
     return _check(_lib.dcg_apply(handle, op, level, _ptr(inp, name="in"), _ptr(in2, name="in2"),
                                  _ptr(out, name="out"), _stream(stream)), handle)
+
+
+def dcg_apply_noalloc(handle, op, inp, out, stream=None):
+    return _check(_lib.dcg_apply_noalloc(handle, op, _ptr(inp, name="in"), _ptr(out, name="out"),
+                                         _stream(stream)), handle)
+
+
+def dcg_noalloc_bytes():
+    return _lib.dcg_noalloc_bytes()
 
 
 def dcg_host_assemble(mesh, which, level=0):

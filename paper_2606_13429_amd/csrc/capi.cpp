@@ -154,6 +154,26 @@ dcg_status dcg_apply(dcg_handle h, dcg_op op, int32_t level, const void* in, con
   });
 }
 
+dcg_status dcg_apply_noalloc(dcg_handle h, dcg_op op, const double* in, double* out,
+                             void* hip_stream) {
+  if (!h) return fail(nullptr, DCG_EINVAL, "NULL handle");
+  return guarded(h, [&]() {
+    int cur = 0;
+    DCG_HIP(hipGetDevice(&cur));
+    if (cur != h->device) DCG_HIP(hipSetDevice(h->device));
+    try {
+      const dcg_status s = dcg::apply_noalloc(h, op, in, out, static_cast<hipStream_t>(hip_stream));
+      if (cur != h->device) DCG_HIP(hipSetDevice(cur));
+      return s;
+    } catch (...) {
+      if (cur != h->device) (void)hipSetDevice(cur);
+      throw;
+    }
+  });
+}
+
+int64_t dcg_noalloc_bytes(void) { return int64_t(dcg::noalloc_capacity()); }
+
 dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level, double* dst,
                              int64_t dst_len, int32_t* cols, int64_t cols_len, int64_t* needed) {
   if (!mesh) return fail(nullptr, DCG_EINVAL, "mesh must not be NULL");

@@ -190,6 +190,9 @@ struct dcg_ctx {
   // solved by fast diagonalisation (cfdm, factors in the workspace)
   int lbase = 0;
   dcg::CoarseFdm cfdm;
+  // level-buffer view of dcg_apply_noalloc (pointers into the static scratch
+  // array; the tables are sized at setup so that the call allocates nothing)
+  dcg::LevelBuffers noalloc_lvb;
   ~dcg_ctx();
 };
 
@@ -200,4 +203,8 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
 void kernel_timing(dcg_ctx* h, int stride);   // 0 = off
 dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* in2, void* out,
                  hipStream_t stream);
+// DCG_OP_INNER / DCG_OP_DEFLATED with every work buffer in the static scratch
+// array (no device allocation); noalloc_capacity() is its size in bytes.
+dcg_status apply_noalloc(dcg_ctx* h, dcg_op op, const double* in, double* out, hipStream_t stream);
+size_t noalloc_capacity();
 }  // namespace dcg

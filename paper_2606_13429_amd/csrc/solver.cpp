@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "fdm_host.hpp"
 #include "wcycle.hpp"
@@ -96,12 +98,31 @@ namespace {
 constexpr double kTwo = 2.0;   // Z^T A* Z = (dt/2) L  =>  A* Z (2/dt) = 2 A_div Z
 constexpr double kApplyTol = 1e-8;   // outer tolerance assumed by DCG_OP_INNER / DEFLATED
 
+// Device buffers an inner solve works in: the handle's workspace, or the
+// static scratch of dcg_apply_noalloc.
+struct InnerWs {
+  const LevelBuffers* lvb = nullptr;
+  Scalars* sc = nullptr;
+  double* part = nullptr;
+  const CoarseFdm* cfdm = nullptr;   // coarsest solve of a shortened hierarchy
+  bool graph = true;                 // the coarse correction may be a captured graph
+};
+
+InnerWs handle_ws(dcg_ctx* h) {
+  InnerWs w;
+  w.lvb = &h->ws.lvb;
+  w.sc = h->ws.sc;
+  w.part = h->ws.part;
+  w.cfdm = h->lbase > 0 ? &h->cfdm : nullptr;
+  return w;
+}
+
 template <typename T>
-Cycle<T> make_cycle(dcg_ctx* h) {
-  Cycle<T> c(*h->mesh, h->ws.lvb, h->mp.pre, h->mp.post);
+Cycle<T> make_cycle(dcg_ctx* h, const InnerWs& w) {
+  Cycle<T> c(*h->mesh, *w.lvb, h->mp.pre, h->mp.post);
   c.base = h->lbase;
   c.group = h->opt.ras_group;
-  if (h->lbase > 0) c.cfdm = &h->cfdm;
+  c.cfdm = w.cfdm;
   if (h->ktime && h->kcycle++ % h->kstride == 0) {   // a sampled W-cycle
     c.timer.ev = h->kev;
     c.timer.max = dcg_ctx::kMaxTimed;
@@ -129,12 +150,12 @@ void collect_kernel_times(dcg_ctx* h) {
 // correction below it -- two W-cycles of level J-1, about a hundred short
 // launches -- is replayed as one captured HIP graph.
 template <typename T>
-LvState run_wcycle_finest(dcg_ctx* h, hipStream_t st) {
+LvState run_wcycle_finest(dcg_ctx* h, const InnerWs& w, hipStream_t st) {
   MeshContext& m = *h->mesh;
   const int J = m.J - h->lbase;   // levels of the cycle's own hierarchy
-  const Cycle<T> cyc = make_cycle<T>(h);
+  const Cycle<T> cyc = make_cycle<T>(h, w);
   LvState s;
-  if (J == 1 || !h->opt.use_graph) {
+  if (J == 1 || !h->opt.use_graph || !w.graph) {
     cyc.wcycle(J, s, st);
     return s;
   }
@@ -181,10 +202,12 @@ void set_params(dcg_ctx* h, hipStream_t st) {
   DCG_HIP(hipStreamSynchronize(st));
 }
 
-void read_scalars(dcg_ctx* h, hipStream_t st) {
-  DCG_HIP(hipMemcpyAsync(h->ws.sc_host, h->ws.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+void read_scalars(dcg_ctx* h, const Scalars* sc, hipStream_t st) {
+  DCG_HIP(hipMemcpyAsync(h->ws.sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
   DCG_HIP(hipStreamSynchronize(st));
 }
+
+void read_scalars(dcg_ctx* h, hipStream_t st) { read_scalars(h, h->ws.sc, st); }
 
 // ------------------------------------------------------------ inner solve
 // z ~= L^{-1} s (FP64) by the Multigrid iteration (Algorithm 3): W-cycles
@@ -200,18 +223,17 @@ void read_scalars(dcg_ctx* h, hipStream_t st) {
 // its level kernels on scratch buffers, but its update of z, residual and
 // count are no-ops, so z and the count are those of Algorithm 3.
 template <typename T>
-int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
+int inner_solve(dcg_ctx* h, const InnerWs& w, const double* s, double* z, double tol_c,
+                hipStream_t st) {
   MeshContext& m = *h->mesh;
   const DeviceLevel& fine = m.lv[m.J - 1];
   const int64_t mlen = 4 * int64_t(fine.ne);
-  T* fJ = static_cast<T*>(h->ws.lvb.f[m.J - 1]);
+  T* fJ = static_cast<T*>(w.lvb->f[m.J - 1]);
   const int nb = refine_blocks(fine.ne);
   const int max_inner = h->opt.max_inner;
-  const Scalars* guard = h->ws.sc;
-  DCG_HIP(launch_refine_residual<T>(true, fine.Lc64, fine.n, fine.ne, s, nullptr, fJ, h->ws.part,
-                                    st));
-  DCG_HIP(launch_reduce(h->ws.part, nb, kRedInnerS2, h->ws.sc, st, Slots(), 1, tol_c * tol_c,
-                        max_inner));
+  const Scalars* guard = w.sc;
+  DCG_HIP(launch_refine_residual<T>(true, fine.Lc64, fine.n, fine.ne, s, nullptr, fJ, w.part, st));
+  DCG_HIP(launch_reduce(w.part, nb, kRedInnerS2, w.sc, st, Slots(), 1, tol_c * tol_c, max_inner));
   DCG_HIP(launch_fill<double>(mlen, 0.0, z, st));
   int ahead = max_inner;
   for (int c : h->inner_recent) ahead = std::min(ahead, c);
@@ -220,17 +242,16 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
   while (true) {
     const int batch = std::min(ahead, max_inner - enqueued);
     for (int i = 0; i < batch; ++i, ++enqueued) {
-      const LvState fs = run_wcycle_finest<T>(h, st);
+      const LvState fs = run_wcycle_finest<T>(h, w, st);
       DCG_HIP(launch_refine_add<T>(fine.ne, false, fs.has_z, fs.has_y,
-                                   static_cast<T*>(h->ws.lvb.z[fs.zb][m.J - 1]),
-                                   static_cast<T*>(h->ws.lvb.Y[fs.yb][m.J - 1]), z, st, Slots(), 1,
+                                   static_cast<T*>(w.lvb->z[fs.zb][m.J - 1]),
+                                   static_cast<T*>(w.lvb->Y[fs.yb][m.J - 1]), z, st, Slots(), 1,
                                    guard));
-      DCG_HIP(launch_refine_residual<T>(false, fine.Lc64, fine.n, fine.ne, s, z, fJ, h->ws.part,
-                                        st, Slots(), 1, guard));
-      DCG_HIP(launch_reduce(h->ws.part, nb, kRedInnerR2, h->ws.sc, st, Slots(), 1, 0.0,
-                            max_inner));
+      DCG_HIP(launch_refine_residual<T>(false, fine.Lc64, fine.n, fine.ne, s, z, fJ, w.part, st,
+                                        Slots(), 1, guard));
+      DCG_HIP(launch_reduce(w.part, nb, kRedInnerR2, w.sc, st, Slots(), 1, 0.0, max_inner));
     }
-    read_scalars(h, st);
+    read_scalars(h, w.sc, st);
     collect_kernel_times(h);
     if (!std::isfinite(h->ws.sc_host->s2)) throw Error(DCG_EINVAL, "non-finite inner right-hand side");
     if (h->ws.sc_host->inner_done || enqueued >= max_inner) break;
@@ -242,7 +263,8 @@ int inner_solve(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_
   return cycles;
 }
 
-int inner(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
+int inner(dcg_ctx* h, const InnerWs& w, const double* s, double* z, double tol_c,
+          hipStream_t st) {
   if (h->opt.inner == DCG_INNER_NONE) {   // no deflation: pi = 0 turns Algorithm 2 into CG on A*
     DCG_HIP(launch_fill<double>(4 * int64_t(h->mesh->ne), 0.0, z, st));
     return 0;
@@ -251,7 +273,12 @@ int inner(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) 
     DCG_HIP(launch_fdm_solve2d(h->mesh->n, h->fV, h->fVT, h->flam, s, z, h->ft[0], h->ft[1], h->ft[2], st));
     return 0;
   }
-  return h->fp32 ? inner_solve<float>(h, s, z, tol_c, st) : inner_solve<double>(h, s, z, tol_c, st);
+  return h->fp32 ? inner_solve<float>(h, w, s, z, tol_c, st)
+                 : inner_solve<double>(h, w, s, z, tol_c, st);
+}
+
+int inner(dcg_ctx* h, const double* s, double* z, double tol_c, hipStream_t st) {
+  return inner(h, handle_ws(h), s, z, tol_c, st);
 }
 
 void check_ptr(const void* p, const char* what) {
@@ -275,6 +302,13 @@ void handle_init(dcg_ctx* h) {
   std::memset(ws.sc_host, 0, sizeof(Scalars));
   DCG_HIP(hipMemcpy(ws.sc, ws.sc_host, sizeof(Scalars), hipMemcpyHostToDevice));
   ws.lvb.allocate(m, h->fp32, false, ws);
+  LevelBuffers& nl = h->noalloc_lvb;
+  nl.f.assign(m.J, nullptr);
+  nl.rr.assign(m.J, nullptr);
+  for (int b = 0; b < 2; ++b) {
+    nl.z[b].assign(m.J, nullptr);
+    nl.Y[b].assign(m.J, nullptr);
+  }
   DCG_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
   if (h->opt.inner == DCG_INNER_EXACT) {
     const FdmAxis f = fdm_axis_factor(m.n, h->mp.penalty * m.n, true);
@@ -820,6 +854,139 @@ dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* i
         apply_level<float>(h, op, level, in, in2, out, st);
       else
         apply_level<double>(h, op, level, in, in2, out, st);
+  }
+  DCG_HIP(hipStreamSynchronize(st));
+  return DCG_OK;
+}
+
+}  // namespace dcg
+
+namespace dcg {
+
+// ------------------------------------------------------------ no-allocation apply
+// dcg_apply_noalloc runs DCG_OP_INNER and DCG_OP_DEFLATED with every buffer
+// its kernels write beside the caller's output -- scalars, partial sums, the
+// inner iterate, the level vectors of the W-cycle, the coarsest-solve
+// intermediates and, for DCG_OP_DEFLATED, A* p and Z^T A* p -- carved from
+// one static device array instead of the handle's workspace.  Each device
+// holds its own copy of the array (kNoallocBytes) until the process ends;
+// its address on a device is read once with hipGetSymbolAddress, with that
+// device current.  Calls that overlap on one device share the array and race.
+constexpr size_t kNoallocBytes = size_t(48) << 20;
+
+}  // namespace dcg
+
+static __device__ __align__(256) unsigned char scratch[dcg::kNoallocBytes];
+
+namespace dcg {
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch;   // device -> address of its scratch
+
+unsigned char* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it != g_scratch.end()) return it->second;
+  void* ptr = nullptr;
+  DCG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  unsigned char* p = static_cast<unsigned char*>(ptr);
+  g_scratch[device] = p;
+  return p;
+}
+
+// Bump allocation inside the scratch array (256-byte aligned pieces); with
+// base == nullptr it only counts the bytes.
+struct Carve {
+  unsigned char* base;
+  size_t used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t off = used;
+    used += (sizeof(T) * count + 255) & ~size_t(255);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+// Lays out the buffers of one call; returns the bytes it needs.
+size_t noalloc_layout(dcg_ctx* h, bool deflated, unsigned char* base, InnerWs& w, double*& zref,
+                      double*& wv, double*& sv, CoarseFdm& cf) {
+  MeshContext& m = *h->mesh;
+  const size_t rs = h->fp32 ? sizeof(float) : sizeof(double);
+  Carve c{base};
+  w.sc = c.take<Scalars>(1);
+  w.part = c.take<double>(3 * size_t(kPartStride));
+  zref = c.take<double>(4 * size_t(m.ne));
+  wv = deflated ? c.take<double>(16 * size_t(m.ne)) : nullptr;
+  sv = deflated ? c.take<double>(4 * size_t(m.ne)) : nullptr;
+  LevelBuffers& lb = h->noalloc_lvb;
+  for (int k = 1; k <= m.J; ++k) {
+    const size_t ne = size_t(m.lv[k - 1].ne);
+    lb.f[k - 1] = c.take<unsigned char>(rs * 4 * ne);
+    lb.rr[k - 1] = c.take<unsigned char>(rs * 4 * ne);
+    for (int b = 0; b < 2; ++b) {
+      lb.z[b][k - 1] = c.take<unsigned char>(rs * 4 * ne);
+      lb.Y[b][k - 1] = k >= 2 ? c.take<unsigned char>(rs * 12 * ne) : nullptr;
+    }
+  }
+  w.lvb = &lb;
+  w.cfdm = nullptr;
+  w.graph = false;
+  if (h->lbase > 0) {
+    cf = h->cfdm;
+    const size_t nn = size_t(2 * cf.n) * size_t(2 * cf.n);
+    for (double*& t : cf.t) t = c.take<double>(nn);
+    w.cfdm = &cf;
+  }
+  return c.used;
+}
+
+}  // namespace
+
+size_t noalloc_capacity() { return kNoallocBytes; }
+
+dcg_status apply_noalloc(dcg_ctx* h, dcg_op op, const double* in, double* out, hipStream_t st) {
+  check_ptr(in, "in");
+  check_ptr(out, "out");
+  if (op != DCG_OP_INNER && op != DCG_OP_DEFLATED)
+    throw Error(DCG_EINVAL, "dcg_apply_noalloc runs DCG_OP_INNER and DCG_OP_DEFLATED only");
+  if (h->opt.inner != DCG_INNER_MG)
+    throw Error(DCG_EINVAL, "dcg_apply_noalloc needs the multigrid inner solve (DCG_INNER_MG)");
+  const bool deflated = op == DCG_OP_DEFLATED;
+  InnerWs w;
+  double *zref = nullptr, *wv = nullptr, *sv = nullptr;
+  CoarseFdm cf;
+  const size_t need = noalloc_layout(h, deflated, nullptr, w, zref, wv, sv, cf);
+  if (need > kNoallocBytes)
+    throw Error(DCG_EINVAL, "dcg_apply_noalloc: this mesh needs " + std::to_string(need) +
+                                " bytes of scratch, the static array holds " +
+                                std::to_string(kNoallocBytes) + " (n <= 256 fits)");
+  noalloc_layout(h, deflated, scratch_address(h->device), w, zref, wv, sv, cf);
+  MeshContext& m = *h->mesh;
+  const int ne = m.ne;
+  // the pending-output buffers of a level hold zeros in the cover slots no
+  // block writes; the array keeps the previous call's values, so clear them
+  for (int k = 2; k <= m.J; ++k)
+    for (int b = 0; b < 2; ++b) {
+      const int64_t len = 12 * int64_t(m.lv[k - 1].ne);
+      if (h->fp32)
+        DCG_HIP(launch_fill<float>(len, 0.f, static_cast<float*>(w.lvb->Y[b][k - 1]), st));
+      else
+        DCG_HIP(launch_fill<double>(len, 0.0, static_cast<double*>(w.lvb->Y[b][k - 1]), st));
+    }
+  if (deflated) {
+    Scalars init{};
+    init.dt = h->dt;
+    init.inv_nu = 1.0 / h->nu;
+    *h->ws.sc_host = init;
+    DCG_HIP(hipMemcpyAsync(w.sc, h->ws.sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st));
+    DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, in, nullptr, nullptr, w.sc, nullptr,
+                         wv, sv, nullptr, st));
+    inner(h, w, sv, zref, h->opt.c_F * kApplyTol, st);
+    DCG_HIP(launch_deflate(false, m.AdivZ, m.cols, ne, kTwo, zref, wv, in, out, nullptr, w.part, st));
+  } else {
+    inner(h, w, in, zref, h->opt.c_F * kApplyTol, st);
+    DCG_HIP(launch_scale(4 * int64_t(ne), 2.0 / h->dt, zref, out, st));
   }
   DCG_HIP(hipStreamSynchronize(st));
   return DCG_OK;
