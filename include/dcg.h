@@ -293,22 +293,24 @@ dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
 dcg_status dcg_bdf2_rhs(dcg_handle h, const double* s1, const double* s2, const double* F,
                         double c, double* f, double* x0, void* hip_stream);
 
-/* Live timing of the dominant kernel of the solve, the RAS tile solves of
- * the finest level (Section 4.2, (A_J)_i^{-1} applied to every block).
- * enable = k > 0: the finest-level launches of every k-th W-cycle made by
- * dcg_solve on this handle (k = 1: every launch) are bracketed by a pair of
- * HIP events recorded on the solve's stream (those launches are issued
- * outside the captured graph); the elapsed times are accumulated at the
- * solver's convergence syncs.  enable = 0 switches the timing off.  A
- * recorded event costs a few microseconds of stream time, hence the
- * sampling.  Enabling or disabling discards the captured graph.  _read
- * returns the accumulated milliseconds and launch count since the last
- * enable. */
+/* Live timing of the dominant kernel of the solve, the RAS step of the
+ * finest level (Section 4.2, (A_J)_i^{-1} applied to every block).
+ * enable = k > 0: the finest-level launches of every k-th W-cycle enqueued by
+ * dcg_solve on this handle (k = 1: every launch; the inner iteration
+ * enqueues a few cycles beyond its test, which run the same kernels) carry a
+ * pair of HIP events on the solve's stream: recorded in the dispatch packet
+ * of the grouped RAS kernel (the kernel's own start and end), around the
+ * launch for the per-tile kernel.  Those launches are issued outside the
+ * captured graph; the elapsed times are accumulated at the solver's syncs.
+ * enable = 0 switches the timing off.  Enabling or disabling discards the
+ * captured graph.  _read returns the accumulated milliseconds and launch
+ * count since the last enable. */
 dcg_status dcg_kernel_timing(dcg_handle h, int32_t enable);
 dcg_status dcg_kernel_timing_read(dcg_handle h, double* total_ms, int64_t* launches);
 /* The same for the A* product with the fused direction update of the CG outer
- * loop (eq. (pb_study), Section 3.1): summed duration and count of its launches since
- * dcg_kernel_timing enabled the timing (CG and FCG(1) outer variants). */
+ * loop (eq. (pb_study), Section 3.1; events in its dispatch packet): summed
+ * duration and count of its launches since dcg_kernel_timing enabled the
+ * timing (CG and FCG(1) outer variants). */
 dcg_status dcg_kernel_timing_read_astar(dcg_handle h, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------- serving

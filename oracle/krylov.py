@@ -44,7 +44,7 @@ coefficients formed from r_i as printed; FCG(m_max) equals FCG(inf) up to
 the first wrap); a warm restart closing the gap between the recurrence and
 the true residual; the Delta-t trends of Tables 1-2; the adaptive rule of eq. (tol)
 reaching the target and the sparse direct solution with FCG(inf), and costing
-fewer cycles than the fixed rule (Table 3's finding) with late inner solves
+fewer cycles than the fixed rule (the cost comparison of Table 3) with late inner solves
 cheaper than early ones; GMRES iterates equal the minimal-residual points of
 the Krylov spaces (dense least squares), GMRES reaches the dense solution in
 no more steps than CG, and converges with the adaptive inexact inner solves
@@ -157,9 +157,11 @@ def dcg(Astar, V, f, inner, tol=1e-8, max_iter=100000, x0=None, outer='cg',
     same inner solve of the same vector).  Outer iterations and inner cycles
     are counted over all passes, and max_iter caps their total.
 
-    ``trace`` (FCG only): a list that receives, for every iteration i, the
+    ``trace``: a list that receives, for every iteration i, with FCG the
     residual r_i the direction was built from, the direction d_i and
-    q_i = M_D d_i."""
+    q_i = M_D d_i; with CG the norms of r_i and of its component V^T r_i in
+    the deflation space, relative to ||f|| (an exact inner solve keeps that
+    component zero: V^T M_D = 0 and V^T f_D = 0)."""
     fnorm = np.linalg.norm(f)
     cycles = []
     outer_cycles = []
@@ -185,6 +187,9 @@ def dcg(Astar, V, f, inner, tol=1e-8, max_iter=100000, x0=None, outer='cg',
         p = r.copy()
         rho = r @ r
         while it < max_iter and np.sqrt(rho) > tol * fnorm:
+            if trace is not None:
+                trace.append(dict(rnorm=np.sqrt(rho) / fnorm,
+                                  vtr=np.linalg.norm(V.T @ r) / fnorm))
             q = M_D(p, tol_c(np.sqrt(rho)), True)
             alpha = rho / (p @ q)
             x = x + alpha * p

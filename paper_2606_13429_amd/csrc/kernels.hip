@@ -8,6 +8,8 @@
 // two-stage and deterministic: a fixed-order wave64 shuffle tree and an LDS
 // tree per workgroup, per-workgroup partials, and one fixed-order final
 // pass (no floating-point atomics anywhere).
+#include <hip/hip_ext.h>
+
 #include "kernels.hpp"
 #include "mg_common.hpp"
 
@@ -644,24 +646,25 @@ __global__ __launch_bounds__(kThreads) void k_copy(int64_t n, const T* __restric
 hipError_t launch_astar(int mode, const double2* C, const int32_t* cols, const double* M1, int ne,
                         const double* x, const double* p_old, const double* b, const Scalars* sc,
                         double* p_new, double* w, double* s, double* part, hipStream_t st,
-                        const Slots& sl, int count) {
+                        const Slots& sl, int count, hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 grid(grid_for(ne, 16, kPartStride), count);
+  // timed launches record their events in the dispatch packet itself
   switch (mode) {
     case kAstarPlain:
-      k_astar<kAstarPlain><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
-                                                      part, sl);
+      hipExtLaunchKernelGGL(k_astar<kAstarPlain>, grid, dim3(kThreads), 0, st, ev0, ev1, 0, C, cols,
+                            M1, ne, x, p_old, b, sc, p_new, w, s, part, sl);
       break;
     case kAstarDir:
-      k_astar<kAstarDir><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
-                                                    part, sl);
+      hipExtLaunchKernelGGL(k_astar<kAstarDir>, grid, dim3(kThreads), 0, st, ev0, ev1, 0, C, cols,
+                            M1, ne, x, p_old, b, sc, p_new, w, s, part, sl);
       break;
     case kAstarFirst:
-      k_astar<kAstarFirst><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w, s,
-                                                      part, sl);
+      hipExtLaunchKernelGGL(k_astar<kAstarFirst>, grid, dim3(kThreads), 0, st, ev0, ev1, 0, C, cols,
+                            M1, ne, x, p_old, b, sc, p_new, w, s, part, sl);
       break;
     case kAstarResidual:
-      k_astar<kAstarResidual><<<grid, kThreads, 0, st>>>(C, cols, M1, ne, x, p_old, b, sc, p_new, w,
-                                                         s, part, sl);
+      hipExtLaunchKernelGGL(k_astar<kAstarResidual>, grid, dim3(kThreads), 0, st, ev0, ev1, 0, C,
+                            cols, M1, ne, x, p_old, b, sc, p_new, w, s, part, sl);
       break;
     default:
       return hipErrorInvalidValue;

@@ -106,10 +106,12 @@ __host__ __device__ inline int square_class(int ex, int ey, int n) {
 int astar_blocks(int ne);     // launch_astar and launch_deflate
 int refine_blocks(int ne);    // launch_refine_residual
 
+// (ev0, ev1: when non-null, recorded at the start and end of the dispatch)
 hipError_t launch_astar(int mode, const double2* C, const int32_t* cols, const double* M1, int ne,
                         const double* x, const double* p_old, const double* b, const Scalars* sc,
                         double* p_new, double* w, double* s, double* part, hipStream_t st,
-                        const Slots& sl = Slots(), int count = 1);
+                        const Slots& sl = Slots(), int count = 1, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 // q = w - c * (A_div Z) z ; partial (p, q).  With ``prologue``: r = w - c AZ z
 // written to q and to p_out, partials (w, w) and (q, q).
 hipError_t launch_deflate(bool prologue, const double2* AZ, const int32_t* cols, int ne, double c,
@@ -233,7 +235,8 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int waves_per_tile, hipStream_t s
 // a multiple of gx; gx in {1, 2, 4}); a.gextra / a.nextra list the classes
 // after the first of every group, each run by a workgroup of its own.
 template <typename T>
-hipError_t launch_sweep_g(const SweepArgs<T>& a, int gx, hipStream_t st);
+hipError_t launch_sweep_g(const SweepArgs<T>& a, int gx, hipStream_t st, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_restrict_res(const RestrictArgs<T>& a, hipStream_t st);
 // out = (has_z ? z : 0) + pending Ye

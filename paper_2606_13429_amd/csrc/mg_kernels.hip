@@ -22,6 +22,8 @@
 //   3. Y_new[t] = D_t (L_k)_t^{-1} r: the factor rows are streamed with
 //      16-byte loads, each lane owning 4 (FP32) or 2 (FP64) output columns,
 //      the WPT wavefronts splitting the 128 rows and reducing in LDS.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -657,21 +659,26 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int wpt, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_sweep_g(const SweepArgs<T>& a, int gx, hipStream_t st) {
+hipError_t launch_sweep_g(const SweepArgs<T>& a, int gx, hipStream_t st, hipEvent_t ev0,
+                          hipEvent_t ev1) {
   const int tpr = a.n / 4;
   if (gx <= 0 || tpr % gx || a.tiles != tpr * tpr) return hipErrorInvalidValue;
   int grid = (tpr / gx) * (tpr / gx);
   if (!a.Fm || (a.nextra > 0 && !a.gextra)) return hipErrorInvalidValue;
   grid += a.nextra;
+  // timed launches record their events in the dispatch packet itself
+#define DCG_SWEEP_G(G, P)                                                                        \
+  hipExtLaunchKernelGGL(k_sweep_g<T, G, P>, dim3(grid), dim3(kThreads), 0, st, ev0, ev1, 0, a)
   switch (gx * 2 + (a.prol ? 1 : 0)) {
-    case 2: k_sweep_g<T, 1, false><<<grid, kThreads, 0, st>>>(a); break;
-    case 3: k_sweep_g<T, 1, true><<<grid, kThreads, 0, st>>>(a); break;
-    case 4: k_sweep_g<T, 2, false><<<grid, kThreads, 0, st>>>(a); break;
-    case 5: k_sweep_g<T, 2, true><<<grid, kThreads, 0, st>>>(a); break;
-    case 8: k_sweep_g<T, 4, false><<<grid, kThreads, 0, st>>>(a); break;
-    case 9: k_sweep_g<T, 4, true><<<grid, kThreads, 0, st>>>(a); break;
+    case 2: DCG_SWEEP_G(1, false); break;
+    case 3: DCG_SWEEP_G(1, true); break;
+    case 4: DCG_SWEEP_G(2, false); break;
+    case 5: DCG_SWEEP_G(2, true); break;
+    case 8: DCG_SWEEP_G(4, false); break;
+    case 9: DCG_SWEEP_G(4, true); break;
     default: return hipErrorInvalidValue;
   }
+#undef DCG_SWEEP_G
   return hipGetLastError();
 }
 
@@ -702,7 +709,8 @@ hipError_t launch_refine_add(int ne, bool first, bool has_z, bool has_y, const T
 
 #define DCG_MG_INSTANTIATE(T)                                                                 \
   template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, hipStream_t);                 \
-  template hipError_t launch_sweep_g<T>(const SweepArgs<T>&, int, hipStream_t);               \
+  template hipError_t launch_sweep_g<T>(const SweepArgs<T>&, int, hipStream_t, hipEvent_t,    \
+                                        hipEvent_t);                                           \
   template hipError_t launch_restrict_res<T>(const RestrictArgs<T>&, hipStream_t);            \
   template hipError_t launch_resolve<T>(int, bool, const T*, const T*, T*, hipStream_t);      \
   template hipError_t launch_refine_add<T>(int, bool, bool, bool, const T*, const T*, double*, \

@@ -622,12 +622,11 @@ dcg_status solve(dcg_ctx* h, const double* b, double* x, double tol, dcg_stats* 
           break;
         }
         // p_i = r_i + beta p_{i-1} fused into w = A* p_i, s = Z^T w
-        const bool atimed = h->ktime;
-        if (atimed) DCG_HIP(hipEventRecord(h->aev[0], stream));
+        const bool atimed = h->ktime;   // events recorded in the dispatch packet
         DCG_HIP(launch_astar(i == 0 ? kAstarFirst : kAstarDir, m.Cdiv, m.cols, m.M1, ne,
                              ws.r, ws.p[pidx], nullptr, ws.sc, ws.p[1 - pidx], ws.w, ws.s, nullptr,
-                             stream));
-        if (atimed) DCG_HIP(hipEventRecord(h->aev[1], stream));
+                             stream, Slots(), 1, atimed ? h->aev[0] : nullptr,
+                             atimed ? h->aev[1] : nullptr));
         pidx = 1 - pidx;
         const int c = inner(h, ws.s, ws.zref, tol_outer(rho), stream);
         cycles_total += c;

@@ -28,11 +28,11 @@ inline int waves_per_tile(int tiles) { return tiles >= 4096 ? 1 : (tiles >= 1024
 // Tiles per side of a workgroup of the grouped (MFMA) RAS step, 0 for the
 // per-tile kernel.  ``choice`` is dcg_options.ras_group: 0 picks by level
 // size, -1 forces the per-tile kernel, 1 / 2 / 4 that group side.  Measured
-// on MI355X (FP32): 4 x 4 groups take 15 against 52 us per step at n = 512
-// and 9 against 17 us at n = 256; at n = 128 (64 groups) the per-tile kernel
-// with two wavefronts per tile is faster (9 against 11 us).
+// on MI355X (FP32, per step): 4 x 4 groups take 17.7 / 10.0 / 7.5 us at
+// n = 512 / 256 / 128, 2 x 2 groups 36 / 14 / 8.3 us, single tiles
+// 106 / 32 / 11 us, the per-tile kernel 60 / 18 / 9.2 us.
 #ifndef DCG_GROUP_MIN_TILES
-#define DCG_GROUP_MIN_TILES 4096
+#define DCG_GROUP_MIN_TILES 1024
 #endif
 inline int ras_group_side(int tiles, int choice) {
   if (choice < 0) return 0;
@@ -129,19 +129,24 @@ struct Cycle {
     a.z_new = z(k, zb_new);
     a.Y_new = Y(k, 1 - s.yb);
     const bool timed = timer.ev && k + base == m.J && *timer.rec < timer.max;
-    if (timed) DCG_HIP(hipEventRecord(timer.ev[2 * *timer.rec], st));
     const int gx = ras_group_side(d.tiles, group);
-    if (b.batched)
-      DCG_HIP(launch_sweep_b<T>(a, st));
-    else if (gx > 0) {
+    if (b.batched || gx <= 0) {
+      if (timed) DCG_HIP(hipEventRecord(timer.ev[2 * *timer.rec], st));
+      if (b.batched)
+        DCG_HIP(launch_sweep_b<T>(a, st));
+      else
+        DCG_HIP(launch_sweep<T>(a, waves_per_tile(d.tiles), st));
+      if (timed) DCG_HIP(hipEventRecord(timer.ev[2 * (*timer.rec)++ + 1], st));
+    } else {
       const int gi = gx == 1 ? 0 : (gx == 2 ? 1 : 2);
       a.gextra = d.gx_extra[gi];
       a.nextra = d.gx_extra_n[gi];
-      DCG_HIP(launch_sweep_g<T>(a, gx, st));
+      // the grouped step records its timing events in the dispatch packet
+      hipEvent_t e0 = timed ? timer.ev[2 * *timer.rec] : nullptr;
+      hipEvent_t e1 = timed ? timer.ev[2 * *timer.rec + 1] : nullptr;
+      DCG_HIP(launch_sweep_g<T>(a, gx, st, e0, e1));
+      if (timed) ++*timer.rec;
     }
-    else
-      DCG_HIP(launch_sweep<T>(a, waves_per_tile(d.tiles), st));
-    if (timed) DCG_HIP(hipEventRecord(timer.ev[2 * (*timer.rec)++ + 1], st));
     s.has_z = s.has_z || changes;
     s.zb = zb_new;
     s.has_y = true;

@@ -362,3 +362,34 @@ def test_restart_brings_the_true_residual_to_tol():
     assert again.total_cycles > plain.total_cycles
     exact = kr.dcg(As, V, f, kr.exact_inner(E), tol=tol, restarts=2)
     assert exact.restarts == 0 and exact.rel_res_true <= tol
+
+
+def test_inexact_projections_leave_a_deflation_space_residual_that_cg_cannot_remove():
+    # With exact inner solves V^T M_D = 0 and V^T f_D = 0, so every CG
+    # residual has no component in the deflation space.  Inexact inner
+    # solves inject one; CG reduces the rest of the residual down to about
+    # its size, then the recurrence residual climbs again by orders of
+    # magnitude before it converges (the extra outer iterations of the fixed
+    # inner tolerance on fine grids).  A tighter inner tolerance keeps that
+    # component, and with it the detour, away.
+    from dcg_workloads import rhs
+    n, dt = 16, 1e-2
+    As, V, E, _ = _problem(n, dt)
+    f = rhs(n, 0).reshape(n * n, 4, 4).transpose(1, 0, 2).reshape(-1)
+    inner = kr.mg_inner(mg.Hierarchy(E, n, coarsest=8))
+
+    def history(c_F, inn=inner):
+        tr = []
+        r = kr.dcg(As, V, f, inn, tol=1e-8, c_F=c_F, max_iter=3000, trace=tr)
+        return r, np.array([t["rnorm"] for t in tr]), np.array([t["vtr"] for t in tr])
+
+    r, rn, vt = history(1.0)                   # inner tolerance 1e-8
+    i = int(np.argmin(rn[:len(rn) // 2]))
+    assert rn[i] <= 10 * vt[i] and vt[i] > 1e-8
+    assert rn[i:].max() >= 100 * rn[i]
+    assert r.rel_res_recurrence <= 1e-8
+    r, rn, vt = history(0.01)                  # inner tolerance 1e-10
+    i = int(np.argmin(rn[:len(rn) // 2]))
+    assert rn[i:].max() <= 1.0001 * rn[i] and vt.max() < 1e-8
+    _, rn, vt = history(0.01, kr.exact_inner(E))
+    assert vt.max() <= 1e-13
