@@ -19,6 +19,10 @@ discretisation  DG-Q1 assembly of M, the div-div SIPG form A, A* = M + alpha A,
 multigrid       nested 2x2-agglomeration transfers, Galerkin hierarchy, RAS
                 smoother, W-cycle and the Multigrid iteration
                 (Section 4.2, Algorithms 3 and 4).
+discretisation3d  the d = 3 forms on hexahedra (Section 3.1 for d = 3, Corollary 1).
+multigrid3d     the three-dimensional hierarchy (2x2x2 agglomeration, trilinear
+                transfers, RAS blocks of a cube and its face neighbours) for the
+                same W-cycle (Section 4.2, the 3D case).
 krylov          CG, deflated CG and FCG(m) (Section 4.1, eqs. (x_defl),
                 (defl_sys), (fixed_tol), (tol), Algorithms 1 and 2).
 timestep        BDF2 right-hand side for a time-stepping run (Section 2.3).
