@@ -94,6 +94,7 @@ TIMING_STRIDE = 8
 
 SWEEP_CLASSES = 9    # distinct RAS local problems and operator rows per level
 FP32_MFMA_PEAK_TFS = 157.3   # MI355X dense FP32 matrix peak
+FP64_VECTOR_PEAK_TFS = 78.6   # MI355X FP64 vector peak (FMA)
 
 
 def sweep_launch_bytes(n, s):
@@ -298,6 +299,20 @@ def serving_cpu_estimate(per_request, tol, c_F=0.01):
                       "(estimate %.0f s for the trace, requests run back to back)" % total}
 
 
+def converged_stats(done, makespan, ok):
+    """Throughput and latency over the requests that met tol: solves that
+    converged per second of the trace's makespan, p50 / p99 of their latency."""
+    import numpy as np
+    conv = [d for d in done if d["status"] == ok]
+    if not conv:
+        return None
+    lat = np.array([d["latency"] for d in conv])
+    return {"requests": len(conv), "solves_per_s": round(len(conv) / makespan, 3),
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+            "max_rel_res_true": max(d["rel_res_true"] for d in conv)}
+
+
 def serving(args):
     """The serving workload: a Poisson trace of requests replayed in real time
     against one dcg server; latency = arrival to completion."""
@@ -385,6 +400,10 @@ def serving(args):
                                   "adaptive c_A=%g" % args.serve_c_A if args.serve_c_A else "fixed c_F=0.01")},
         "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
         "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+        "converged_only": converged_stats(done, makespan, lib.DCG_OK),
+        "capped": [{"n": d["n"], "dt": round(d["dt"], 8), "outer": d["outer"],
+                    "rel_res_true": d["rel_res_true"], "latency_s": round(d["latency"], 2)}
+                   for d in capped],
         "makespan_s": round(makespan, 2), "not_converged": len(capped), "failed": len(failed),
         "failures": [{"n": d["n"], "dt": d["dt"], "status": d["status"]} for d in failed],
         "batch_occupancy": round(slot_steps / max(steps, 1), 2), "server_steps": steps,
@@ -410,9 +429,10 @@ def dt_sweep(args):
     x = torch.empty_like(b)
     rows = []
     s_bytes = {"fp64": 8, "mixed": 4}
-    for dt in (1e-5, 1e-4, 1e-3, 1e-2, 1e-1):
-        for prec in ("fp64", "mixed"):
-            solver = dcg.Solver(n, dt, prec=prec, max_outer=args.sweep_max_outer)
+    dts = [float(v) for v in args.sweep_dts.split(",")]
+    for dt in dts:
+        for prec in args.sweep_precs.split(","):
+            solver = dcg.Solver(n, dt, prec=prec, max_outer=args.sweep_max_outer, c_F=args.sweep_cF)
             solver.solve(b, x, tol)                      # warm-up (graph capture)
             lib.dcg_kernel_timing(solver.handle, True)
             torch.cuda.synchronize()
@@ -446,7 +466,8 @@ def dt_sweep(args):
             log("dt=%g %s: status %d outer %d %.2f s" % (dt, "plain CG" if inner == "none" else "DCG exact inner",
                                                           status, st.outer_iters, t))
     print(json.dumps({"metric": "dCG outer iterations / Tot / Inn against dt", "n": n, "tol": tol,
-                      "max_outer": args.sweep_max_outer, "rows": rows}), flush=True)
+                      "c_F": args.sweep_cF, "max_outer": args.sweep_max_outer, "rows": rows}),
+          flush=True)
 
 
 def timestep(args):
@@ -479,13 +500,17 @@ def timestep(args):
     t_all = time.perf_counter() - t_all
     k_ms, k_n = lib.dcg_kernel_timing_read(stepper.solver.handle)
     k_avg = k_ms / max(k_n, 1)
+    tflops = sweep_launch_flops(n) / (k_avg * 1e-3) / 1e12
     gbs = sweep_launch_bytes(n, 4) / (k_avg * 1e-3) / 1e9
     print(json.dumps({"metric": "BDF2 steps/s, n=1024 dt=1e-5, mixed form, warm start",
                       "value": round(len(rows) / t_all, 5), "unit": "steps/s", "steps": len(rows),
-                      "of_steps": TIMESTEP["steps"],
-                      "roofline": {"bound": "hbm", "kernel": "k_sweep<float,1> (finest-level RAS step)",
-                                   "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "of_steps": TIMESTEP["steps"], "seconds": round(t_all, 2),
+                      "roofline": {"bound": "mfma", "kernel": "k_sweep_g<float,4> (finest-level RAS step)",
+                                   "achieved": round(tflops, 2), "peak": FP32_MFMA_PEAK_TFS,
+                                   "unit": "TFLOP/s", "frac": round(tflops / FP32_MFMA_PEAK_TFS, 4),
+                                   "flops_per_launch": sweep_launch_flops(n),
+                                   "hbm_achieved_gbs": round(gbs, 1),
+                                   "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                                    "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n},
                       "rows": rows}), flush=True)
 
@@ -507,11 +532,38 @@ def astar3_bytes(n):
     return 8 * (576 * nblocks + 144 * ne)
 
 
+def mg3_ras_flops(n):
+    """Algorithmic flops of one finest-level RAS step of the 3D multigrid
+    (k_mg3_ras): per cube 8 rows times 8 values of every diamond cube inside
+    the domain (the cube's blocks' solutions restricted to it, combined into
+    one 8 x 200 update per class), two flops per multiply-add."""
+    import numpy as np
+    x = np.arange(n)
+    total = 0
+    for dz in range(-2, 3):
+        for dy in range(-2, 3):
+            for dx in range(-2, 3):
+                if abs(dx) + abs(dy) + abs(dz) > 2:
+                    continue
+                cnt = [int(((x + d >= 0) & (x + d < n)).sum()) for d in (dx, dy, dz)]
+                total += cnt[0] * cnt[1] * cnt[2]
+    return 2 * 64 * total
+
+
+def mg3_ras_bytes(n):
+    """Algorithmic bytes of one finest-level RAS step of the 3D multigrid:
+    r read and z read and written once (8 FP64 values per cube each), plus
+    the class tables the level holds (343 x 8 x 200 FP64), read once."""
+    return 8 * (24 * n ** 3 + 343 * 8 * 200)
+
+
 def three_d(args):
     """The 3D solver (d = 3 block structure) at n^3 = 32^3 cubes, dt = 1e-3,
     FP64, with the exact inner solve (fast diagonalisation, the setting of
-    Table 5 left) or block-Jacobi CG (--3d-inner cg): solves/s, outer and
-    inner counts, and the roofline of the dominant kernel (A* resp. the inner
+    Table 5 left), the multigrid inner solve (--3d-inner mg: W-cycles with the
+    RAS smoother, m = 10, Table 5 right; --3d-cA for the adaptive rule) or
+    block-Jacobi CG (--3d-inner cg): solves/s, outer and inner counts, and the
+    roofline of the dominant kernel (A*, the finest RAS step, resp. the inner
     Laplacian product), timed with HIP events inside the library."""
     import torch
     import paper_2606_13429_amd as dcg
@@ -520,7 +572,8 @@ def three_d(args):
     n, dt, tol = args.n3, THREE_D["dt"], THREE_D["tol"]
     torch.cuda.set_device(0)
     t0 = time.time()
-    s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], inner=args.inner3)
+    s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], inner=args.inner3,
+                     c_A=args.cA3)
     log("3d setup n=%d (%d elements) %.1f s" % (n, n ** 3, time.time() - t0))
     bs = [torch.from_numpy(rhs3d(n, i)).cuda() for i in range(max(args.steps, 1))]
     x = torch.empty_like(bs[0])
@@ -544,23 +597,38 @@ def three_d(args):
     k_ms, k_n = lib.dcg3d_kernel_timing_read(s.handle)
     lib.dcg3d_kernel_timing(s.handle, False)
     k_avg = k_ms / max(k_n, 1)
-    exact = args.inner3 == "exact"
-    nbytes = astar3_bytes(n) if exact else lap3_bytes(n)
-    kname = "k_astar3 (A* product)" if exact else "k_lap3 (inner Laplacian product)"
-    gbs = nbytes / (k_avg * 1e-3) / 1e9
+    inner_name = {"exact": "exact (fast diagonalisation)", "cg": "block-Jacobi CG",
+                  "mg": "W-cycle multigrid, RAS, m = 10, %s" % (
+                      "adaptive c_A=%g" % args.cA3 if args.cA3 else "fixed c_F=0.01")}[args.inner3]
+    if args.inner3 == "mg":
+        flops = mg3_ras_flops(n)
+        nbytes = mg3_ras_bytes(n)
+        tfs = flops / (k_avg * 1e-3) / 1e12
+        gbs = nbytes / (k_avg * 1e-3) / 1e9
+        roof = {"bound": "alu", "kernel": "k_mg3_ras (finest-level RAS step, FP64 FMA)",
+                "achieved": round(tfs, 3), "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": round(tfs / FP64_VECTOR_PEAK_TFS, 4), "traffic": None,
+                "flops_per_launch": flops, "bytes_per_launch": nbytes,
+                "hbm_achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n}
+    else:
+        exact = args.inner3 == "exact"
+        nbytes = astar3_bytes(n) if exact else lap3_bytes(n)
+        kname = "k_astar3 (A* product)" if exact else "k_lap3 (inner Laplacian product)"
+        gbs = nbytes / (k_avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": kname,
+                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic3(n) if exact else None,
+                "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n,
+                "bytes_per_launch": nbytes}
     print(json.dumps({
-        "metric": "3D dCG solves/s, %d^3 DG-Q1 cubes, dt=%g, FP64, inner %s"
-                  % (n, dt, "exact (fast diagonalisation)" if exact else "block-Jacobi CG"),
+        "metric": "3D dCG solves/s, %d^3 DG-Q1 cubes, dt=%g, FP64, inner %s" % (n, dt, inner_name),
         "value": round(args.steps / t_all, 5), "unit": "solves/s", "steps": args.steps,
         "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "3D pseudo-stress A* x = b, n=%d, dt=%g, nu=%g, penalty=%g, tol=%g"
                    % (n, dt, THREE_D["nu"], THREE_D["penalty"], tol)},
-        "roofline": {"bound": "hbm", "kernel": kname,
-                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic3(n) if exact else None,
-                     "avg_launch_us": round(k_avg * 1e3, 2), "launches": k_n,
-                     "bytes_per_launch": nbytes},
+        "roofline": roof,
         "rows": rows}), flush=True)
     s.close()
 
@@ -627,6 +695,37 @@ def three_d_sweep(args):
                     % (n, dt, rows[-1]["method"], status, st.outer_iters, st.rel_res_true, st.t_solve_ms))
     print(json.dumps({"metric": "3D outer iterations vs dt: DCG (exact inner solve) and plain CG, n = 8, 16, 32",
                       "unit": "iterations", "tol": THREE_D["tol"], "rows": rows}), flush=True)
+
+
+def three_d_table5(args):
+    """The analogue of Table 5 (right): deflated CG with the multigrid inner
+    solve (W-cycles, RAS, m = 10) at --n3 cubes per side, Out / Tot / Inn for
+    dt in {0.5, 0.1, 1e-2, 1e-3, 1e-4} with the fixed rule c_F = 0.01 and the
+    adaptive rule c_A = 0.02 and 0.005, tol 1e-8, b = rhs3d(n, 0)."""
+    import torch
+    import paper_2606_13429_amd as dcg
+    from dcg_workloads import THREE_D, rhs3d
+    n = args.n3
+    torch.cuda.set_device(0)
+    b = torch.from_numpy(rhs3d(n, 0)).cuda()
+    x = torch.empty_like(b)
+    rows = []
+    for dt in (0.5, 0.1, 1e-2, 1e-3, 1e-4):
+        for rule, c in (("c_F", 0.01), ("c_A", 0.02), ("c_A", 0.005)):
+            kw = {"c_F": c} if rule == "c_F" else {"c_A": c}
+            s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], inner="mg",
+                             max_outer=args.sweep_max_outer, **kw)
+            status, st = s.solve(b, x, THREE_D["tol"])
+            s.close()
+            rows.append({"dt": dt, "rule": rule, "c": c, "status": status, "outer": st.outer_iters,
+                         "tot": st.total_wcycles, "inn": round(st.inner_per_outer, 2),
+                         "rel_res_true": st.rel_res_true, "ms": round(st.t_solve_ms, 1)})
+            log("3d table5 n=%d dt=%g %s=%g: status=%d Out %d Tot %d Inn %.1f res %.2e %.1f ms"
+                % (n, dt, rule, c, status, st.outer_iters, st.total_wcycles, st.inner_per_outer,
+                   st.rel_res_true, st.t_solve_ms))
+    print(json.dumps({"metric": "3D DCG with the multigrid inner solve: Out / Tot / Inn against dt "
+                                "and the inner tolerance rule (Table 5, right)", "n": n,
+                      "tol": THREE_D["tol"], "rows": rows}), flush=True)
 
 
 def variants(args):
@@ -705,12 +804,21 @@ def main():
                     help="time per W-cycle against the multigrid depth at --n (capped solves)")
     ap.add_argument("--sweep-n", type=int, default=128)
     ap.add_argument("--sweep-max-outer", type=int, default=20000)
+    ap.add_argument("--sweep-dts", default="1e-5,1e-4,1e-3,1e-2,1e-1",
+                    help="dt sweep: comma-separated time steps")
+    ap.add_argument("--sweep-cF", type=float, default=0.01, help="dt sweep: inner tolerance factor")
+    ap.add_argument("--sweep-precs", default="fp64,mixed", help="dt sweep: forms to run")
     ap.add_argument("--timestep", action="store_true", help="run BDF2 time stepping at n=1024")
     ap.add_argument("--ts-steps", type=int, default=3)
     ap.add_argument("--3d", dest="three_d", action="store_true",
                     help="run the 3D solver at --n3 cubes per side")
     ap.add_argument("--n3", type=int, default=32)
-    ap.add_argument("--3d-inner", dest="inner3", choices=("exact", "cg"), default="exact")
+    ap.add_argument("--3d-inner", dest="inner3", choices=("exact", "cg", "mg"), default="exact")
+    ap.add_argument("--3d-cA", dest="cA3", type=float, default=0.0,
+                    help="3D: adaptive inner tolerance constant (0 = fixed c_F = 0.01)")
+    ap.add_argument("--3d-table5", dest="three_d_table5", action="store_true",
+                    help="3D multigrid inner solve: Out / Tot / Inn against dt and the inner "
+                         "tolerance rule at --n3 (the analogue of Table 5, right)")
     ap.add_argument("--3d-sweep", dest="three_d_sweep", action="store_true",
                     help="outer iterations of the 3D solver against dt at n = 8, 16, 32")
     ap.add_argument("--variants", action="store_true",
@@ -748,6 +856,9 @@ def main():
         return
     if args.three_d_sweep:
         three_d_sweep(args)
+        return
+    if args.three_d_table5:
+        three_d_table5(args)
         return
 
     import numpy as np

@@ -131,6 +131,10 @@ typedef struct {
                           with the group's residuals; -1 = one tile per
                           wavefront group, scalar FMAs.  Same step either way
                           (up to rounding).  Not used by the server. [0]     */
+  int32_t smooth3d;    /* 3D solver with DCG3D_INNER_MG: m pre- and m post-
+                          smoothing RAS steps per level visit of the W-cycle
+                          (the 3D runs of Section 4.2 use m = 10).  Ignored
+                          elsewhere. [10]                                    */
 } dcg_options;
 
 /* Inner solver of dcg_solve.  DCG_INNER_MG is the paper's method: the
@@ -415,7 +419,9 @@ typedef struct dcg3d_ctx* dcg3d_handle;
 typedef enum {
   DCG3D_INNER_FDM = 0,    /* exact inner solve by fast diagonalisation (default)  */
   DCG3D_INNER_PCG = 1,    /* block-Jacobi CG to c_F * tol                           */
-  DCG3D_INNER_NONE = 2    /* no deflation: plain CG on A* (the CG column of Table 5)  */
+  DCG3D_INNER_NONE = 2,   /* no deflation: plain CG on A* (the CG column of Table 5)  */
+  DCG3D_INNER_MG = 3      /* the Multigrid iteration of Algorithm 3 with W-cycles and
+                             the RAS smoother (Section 4.2, the 3D case; see below)   */
 } dcg3d_inner;
 
 typedef enum {
@@ -431,8 +437,24 @@ typedef enum {
 /* Assembles the operators on the host and uploads them (2 <= n <= 64,
  * penalty > 0, dt > 0, nu = mu > 0, inner a dcg3d_inner).  opt may be NULL (defaults of
  * dcg_defaults with prec = DCG_FP64 and max_inner = DCG3D_DEFAULT_MAX_INNER);
- * the 3D solver takes prec = DCG_FP64, outer = DCG_OUTER_CG, c_A = 0 and
- * x0_given = 0 and rejects other values with DCG_EINVAL. */
+ * the 3D solver takes prec = DCG_FP64, outer = DCG_OUTER_CG and x0_given = 0
+ * and rejects other values with DCG_EINVAL.  The iterative inner solves stop
+ * at the relative residual c_F tol (eq. (fixed_tol)), or with c_A > 0 at
+ * c_A tol ||b|| / ||r_i|| inside the outer loop and c_A tol for the prologue
+ * and epilogue (eq. (tol)); max_inner is their n_max.
+ *
+ * DCG3D_INNER_MG: the Galerkin hierarchy of L = B_11 + B_22 + B_33 (levels
+ * k = 1..J by 2 x 2 x 2 agglomeration, trilinear injection P_k, L_{k-1} =
+ * P_k^T L_k P_k; opt->levels = J, 0 = down to the smallest coarsest size
+ * c = n / 2^(J-1) >= 2, which must lie in [2, 4], else DCG_EINVAL), a RAS
+ * smoother with one block per cube -- the cube and its face neighbours, the
+ * local problems solved exactly, D = 1 / (blocks holding the dof) -- with
+ * opt->smooth3d steps before and after each coarse correction, gamma = 2,
+ * and the exact solve on level 1 by a dense inverse.  The multigrid runs on
+ * L and returns (3/dt) z (E = (dt/3) L, the same relative residual); every
+ * step runs on the device, the stopping test too (each pass of Algorithm 3
+ * is one captured HIP graph when opt->use_graph, enqueued ahead of the
+ * test's result); total_wcycles counts W-cycles. */
 dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, int32_t inner,
                        const dcg_options* opt, dcg3d_handle* out);
 /* Solves A* x = b to ||r|| <= tol ||b|| (the recurrence residual of the
@@ -444,6 +466,29 @@ dcg_status dcg3d_solve(dcg3d_handle h, const double* b, double* x, double tol, d
 dcg_status dcg3d_apply(dcg3d_handle h, dcg3d_op op, const double* in, double* out, double tol);
 dcg_status dcg3d_destroy(dcg3d_handle h);
 const char* dcg3d_last_error(dcg3d_handle h);
+
+/* Level operators of the DCG3D_INNER_MG hierarchy (for verification; the
+ * Laplacian hierarchy L_k, not scaled by dt).  Level vectors: device, FP64,
+ * 8 n_k^3 values, idx = 8 e + a as above, n_k = n / 2^(J-k).
+ *
+ *  op                  in            in2              out         computes
+ *  DCG3D_MG_LAPLACE    z (level k)   -                v (k)       L_k z
+ *  DCG3D_MG_RAS        f (k)         z (k) or NULL=0  z' (k)      z + S_k (f - L_k z), k >= 2
+ *  DCG3D_MG_RESTRICT   r (k)         -                rc (k - 1)  P_k^T r, k >= 2
+ *  DCG3D_MG_PROLONG    e (k - 1)     -                v (k)       P_k e, k >= 2
+ *  DCG3D_MG_COARSE     f (1)         -                z (1)       L_1^{-1} f (dense FP64 inverse)
+ *  DCG3D_MG_WCYCLE     f (k)         z0 (k) or NULL=0 z (k)       Wcycle_k(f, z0), Algorithm 4
+ *
+ * Blocks until done; DCG_EINVAL for another inner solver, a bad op or
+ * level, or a NULL in / out. */
+typedef enum {
+  DCG3D_MG_LAPLACE = 0, DCG3D_MG_RAS = 1, DCG3D_MG_RESTRICT = 2, DCG3D_MG_PROLONG = 3,
+  DCG3D_MG_COARSE = 4, DCG3D_MG_WCYCLE = 5
+} dcg3d_mg_op;
+dcg_status dcg3d_mg_apply(dcg3d_handle h, int32_t op, int32_t level, const double* in,
+                          const double* in2, double* out);
+/* The hierarchy of a DCG3D_INNER_MG handle: J and the coarsest size c. */
+dcg_status dcg3d_mg_levels(dcg3d_handle h, int32_t* levels, int32_t* coarsest);
 /* Measurement: while enabled, every launch of the dominant kernel of the 3D
  * solve -- the A* product with the exact inner solve, the inner Laplacian
  * product with block-Jacobi CG -- is bracketed by HIP events on
@@ -466,6 +511,25 @@ dcg_status dcg3d_kernel_timing_read(dcg3d_handle h, double* total_ms, int64_t* l
  * row-major (column i = eigenvector i), lambda_x [2n], then V_y, lambda_y. */
 #define DCG3D_MAX_HOST_BLOCKS_N 16
 dcg_status dcg3d_host_blocks(int32_t n, double penalty, double dt, int32_t which, double* out);
+
+/* Host only (no device call, 2 <= n <= 16): the class tables the multigrid
+ * inner solve uploads, for level `level` of the hierarchy with `levels`
+ * levels (as opt->levels), into the HOST buffer out.  On the uniform grid a
+ * cube's operator rows depend only on the domain sides it touches and its
+ * RAS update only on its distance 0, 1, 2 or >= 3 from each side.  which = 0:
+ * the operator table [27][7][8][8], entry (cls, slot, a, b) = L_k(row a of a
+ * cube of class cls = cx + 3 cy + 9 cz -- c_axis 0 at the low side, 2 at the
+ * high side, 1 inside -- column b of its slot neighbour), row-major, zero
+ * for classes and neighbours absent on the level; 1 (k >= 2): the RAS
+ * update table [343][8][200], (S_k r) on a cube of class px + 7 py + 49 pz
+ * (p = x for x < 3, 6 - (n_k - 1 - x) for n_k - 1 - x < 3, else 3; on
+ * levels with n_k < 6 the class is the cube index e) equals
+ * table[cls] times r on the 25 cubes (dx, dy, dz) with |dx|+|dy|+|dz| <= 2
+ * (ordered by dz, then dy, then dx ascending; column 8 d + b), zero rows for
+ * absent classes; 2 (k = 1): the inverse of L_1, [8 c^3][8 c^3] row-major.
+ * DCG_EINVAL for a bad n, levels, level or which. */
+dcg_status dcg3d_host_mg(int32_t n, double penalty, int32_t levels, int32_t level, int32_t which,
+                         double* out);
 
 #ifdef __cplusplus
 }

@@ -20,30 +20,44 @@ __all__ = ["Solver", "Solver3D", "Server", "DCGError", "LIB_PATH"]
 class Solver3D:
     """The three-dimensional solver (dcg3d_setup / dcg3d_solve): deflated CG
     for the d = 3 block structure on n^3 cubes, FP64; the inner system solved
-    exactly by fast diagonalisation (inner="exact") or by block-Jacobi CG to
-    c_F * tol (inner="cg"); inner="none" switches the deflation off (plain CG
-    on A*).
+    exactly by fast diagonalisation (inner="exact"), by the Multigrid
+    iteration of W-cycles with the RAS smoother (inner="mg", ``smooth`` pre-
+    and post-smoothing steps, ``levels`` levels, 0 = all) or by block-Jacobi
+    CG (inner="cg"), the iterative ones to c_F * tol, or with c_A > 0 to the
+    adaptive tolerance of eq. (tol); inner="none" switches the deflation off
+    (plain CG on A*).
 
     >>> s = Solver3D(n=16, dt=1e-3)
     >>> status, stats = s.solve(b, x, tol=1e-8)     # 72 n^3 cuda float64 tensors
     """
 
     def __init__(self, n, dt, nu=1.0, penalty=40.0, c_F=0.01, max_outer=50000,
-                 max_inner=DCG3D_DEFAULT_MAX_INNER, inner="exact"):
+                 max_inner=None, inner="exact", c_A=0.0, levels=0, smooth=10, use_graph=True):
         _, opt = dcg_defaults()
-        opt.prec, opt.outer, opt.c_A, opt.x0_given = DCG_FP64, DCG_OUTER_CG, 0.0, 0
+        opt.prec, opt.outer, opt.c_A, opt.x0_given = DCG_FP64, DCG_OUTER_CG, c_A, 0
+        if max_inner is None:
+            max_inner = 100 if inner == "mg" else DCG3D_DEFAULT_MAX_INNER
         opt.c_F, opt.max_outer, opt.max_inner = c_F, max_outer, max_inner
+        opt.levels, opt.smooth3d, opt.use_graph = levels, smooth, int(use_graph)
         self.n, self.dt, self.nu, self.penalty, self.opt = n, dt, nu, penalty, opt
         self.inner = inner
         self.handle = dcg3d_setup(n, penalty, dt, nu, opt,
                                   {"exact": DCG3D_INNER_FDM, "cg": DCG3D_INNER_PCG,
-                                   "none": DCG3D_INNER_NONE}[inner])
+                                   "none": DCG3D_INNER_NONE, "mg": DCG3D_INNER_MG}[inner])
 
     def solve(self, b, x, tol=1e-8):
         return dcg3d_solve(self.handle, b, x, tol)
 
     def apply(self, op, inp, out, tol=0.0):
         return dcg3d_apply(self.handle, op, inp, out, tol)
+
+    def mg_apply(self, op, level, inp, out, in2=None):
+        from ._binding import dcg3d_mg_apply
+        return dcg3d_mg_apply(self.handle, op, level, inp, in2, out)
+
+    def mg_levels(self):
+        from ._binding import dcg3d_mg_levels
+        return dcg3d_mg_levels(self.handle)
 
     def close(self):
         if self.handle is not None:

@@ -30,7 +30,9 @@ BATCH = 16   # vectors of the _BATCH operators and requests per serving batch
 (DCG3D_OP_ASTAR, DCG3D_OP_ZT, DCG3D_OP_Z, DCG3D_OP_DEFLATED, DCG3D_OP_REDUCED, DCG3D_OP_INNER,
  DCG3D_OP_ADIVZ) = range(7)
 DCG3D_MAX_N, DCG3D_DEFAULT_MAX_INNER, DCG3D_MAX_HOST_BLOCKS_N = 64, 20000, 16
-DCG3D_INNER_FDM, DCG3D_INNER_PCG, DCG3D_INNER_NONE = 0, 1, 2
+DCG3D_INNER_FDM, DCG3D_INNER_PCG, DCG3D_INNER_NONE, DCG3D_INNER_MG = 0, 1, 2, 3
+(DCG3D_MG_LAPLACE, DCG3D_MG_RAS, DCG3D_MG_RESTRICT, DCG3D_MG_PROLONG, DCG3D_MG_COARSE,
+ DCG3D_MG_WCYCLE) = range(6)
 
 
 class dcg_mesh(ctypes.Structure):
@@ -45,7 +47,7 @@ class dcg_options(ctypes.Structure):
                 ("hbm_budget_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int32),
                 ("c_A", ctypes.c_double), ("m_max", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("ras_group", ctypes.c_int32)]
+                ("ras_group", ctypes.c_int32), ("smooth3d", ctypes.c_int32)]
 
 
 class dcg_stats(ctypes.Structure):
@@ -100,6 +102,10 @@ _SIGS = {
     "dcg3d_last_error": (ctypes.c_char_p, [_h]),
     "dcg3d_host_blocks": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                          _P(ctypes.c_double)]),
+    "dcg3d_mg_apply": (ctypes.c_int, [_h, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
+    "dcg3d_mg_levels": (ctypes.c_int, [_h, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "dcg3d_host_mg": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, _P(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -349,6 +355,37 @@ def dcg3d_host_blocks(n, penalty, dt, which):
     size = {0: 7 * ne * 576, 1: 7 * ne * 64, 2: ne * 64, 3: 64, 4: 2 * (N * N + N)}[which]
     out = np.empty(size, dtype=np.float64)
     _check3(_lib.dcg3d_host_blocks(n, penalty, dt, which, out.ctypes.data_as(_P(ctypes.c_double))))
+    return out
+
+
+def dcg3d_mg_apply(handle, op, level, inp, inp2, out):
+    """One level operator of the 3D multigrid hierarchy (inp2 may be None)."""
+    _sync_torch_stream()
+    return _check3(_lib.dcg3d_mg_apply(handle, op, level, _ptr(inp, _f64(), None, "in"),
+                                       _ptr(inp2, _f64(), None, "in2"), _ptr(out, _f64(), None, "out")),
+                   handle)
+
+
+def dcg3d_mg_levels(handle):
+    """(J, coarsest cubes per side) of a DCG3D_INNER_MG handle."""
+    J, c = ctypes.c_int32(), ctypes.c_int32()
+    _check3(_lib.dcg3d_mg_levels(handle, ctypes.byref(J), ctypes.byref(c)), handle)
+    return J.value, c.value
+
+
+def dcg3d_host_mg(n, penalty, levels, level, which, coarsest=None):
+    """Host copy of a class table of the 3D multigrid hierarchy (no device
+    call): which 0 the operator table (27, 7, 8, 8), 1 the RAS update table
+    (343, 8, 200), 2 the coarsest inverse (m, m); ``coarsest`` (cubes per
+    side of level 1) sizes the latter."""
+    import numpy as np
+    if which == 2:
+        m = 8 * coarsest ** 3
+        shape = (m, m)
+    else:
+        shape = {0: (27, 7, 8, 8), 1: (343, 8, 200)}[which]
+    out = np.empty(shape, dtype=np.float64)
+    _check3(_lib.dcg3d_host_mg(n, penalty, levels, level, which, out.ctypes.data_as(_P(ctypes.c_double))))
     return out
 
 

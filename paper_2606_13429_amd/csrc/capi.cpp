@@ -91,6 +91,7 @@ void dcg_defaults(dcg_mesh* mesh, dcg_options* opt) {
     opt->max_pending = 4096;
     opt->c_A = 0.0;
     opt->m_max = 8;
+    opt->smooth3d = 10;
   }
 }
 

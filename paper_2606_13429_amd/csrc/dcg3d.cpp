@@ -10,8 +10,11 @@
 //
 // Solve: deflated CG with V of eq. (Vmatrix) for d = 3 (called Z), whose
 // inner system Z^T A* Z = (dt/3)(B_11 + B_22 + B_33) (Corollary 1) is solved
-// by block-Jacobi preconditioned CG to the relative tolerance c_F * tol
-// (eq. (fixed_tol)); every vector operation runs in the kernels of dcg3d_kernels.hip.
+// exactly by fast diagonalisation, by the Multigrid iteration of Algorithm 3
+// (W-cycles with the RAS smoother of Section 4.2, mg3d_*.{cpp,hip}) or by
+// block-Jacobi preconditioned CG, the iterative ones to the relative
+// tolerance of eq. (fixed_tol) or eq. (tol); every vector operation runs in
+// the kernels of dcg3d_kernels.hip and mg3d_kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +29,7 @@
 #include "../../include/dcg.h"
 #include "dcg3d.hpp"
 #include "fdm_host.hpp"
+#include "mg3d.hpp"
 
 namespace {
 
@@ -270,7 +274,19 @@ struct dcg3d_ctx {
   std::string last_error;
   double t_setup_ms = 0;
   int64_t inner_total = 0, inner_solves = 0;
-  // optional HIP-event timing of the Laplacian launches of the inner solves
+  // multigrid inner solve: level k at index k - 1
+  int mg_J = 0, mg_m = 10;
+  std::vector<int> mg_n;
+  std::vector<double*> mg_op, mg_ras, mg_f, mg_z, mg_r;
+  double* mg_cinv = nullptr;
+  double* mg_part = nullptr;
+  dcg3::Mg3Scalars* mg_sc = nullptr;
+  dcg3::Mg3Scalars* mg_sc_host = nullptr;
+  hipStream_t mg_cap = nullptr;
+  hipGraphExec_t mg_graph = nullptr;
+  int mg_recent[4] = {0, 0, 0, 0};
+  int mg_nrecent = 0;
+  // optional HIP-event timing of the dominant launches of the inner solves
   bool timing = false;
   std::vector<hipEvent_t> evs;
   size_t ev_used = 0;
@@ -283,12 +299,32 @@ struct dcg3d_ctx {
     }
     H3(hipEventRecord(evs[ev_used++], nullptr));
   }
+  // A start / stop pair for a launch that records them itself.
+  void event_pair(hipEvent_t& e0, hipEvent_t& e1) {
+    while (evs.size() < ev_used + 2) {
+      hipEvent_t e;
+      H3(hipEventCreate(&e));
+      evs.push_back(e);
+    }
+    e0 = evs[ev_used];
+    e1 = evs[ev_used + 1];
+    ev_used += 2;
+  }
 
   ~dcg3d_ctx() {
     for (double* b : {Cd, Ld, Dinv, Me, w, r, p, q, xh, pf, tz, s, yh, ir, iz, ip, iq, part, part2, dots,
                       fVx, fVxT, fVy, fVyT, flx, fly})
       if (b) (void)hipFree(b);
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    for (auto* v : {&mg_op, &mg_ras, &mg_f, &mg_z, &mg_r})
+      for (double* b : *v)
+        if (b) (void)hipFree(b);
+    for (double* b : {mg_cinv, mg_part})
+      if (b) (void)hipFree(b);
+    if (mg_sc) (void)hipFree(mg_sc);
+    if (mg_sc_host) (void)hipHostFree(mg_sc_host);
+    if (mg_graph) (void)hipGraphExecDestroy(mg_graph);
+    if (mg_cap) (void)hipStreamDestroy(mg_cap);
     if (sc) (void)hipFree(sc);
     if (sc_host) (void)hipHostFree(sc_host);
     if (dots_host) (void)hipHostFree(dots_host);
@@ -327,6 +363,7 @@ struct dcg3d_ctx {
       H3(hipMemcpy(flx, fx.lam.data(), N * sizeof(double), hipMemcpyHostToDevice));
       H3(hipMemcpy(fly, fy.lam.data(), N * sizeof(double), hipMemcpyHostToDevice));
     }
+    if (inner_kind == DCG3D_INNER_MG) setup_mg(ld);
     for (double** b : {&w, &r, &p, &q, &xh, &pf, &tz}) *b = dev_alloc<double>(nt);
     for (double** b : {&s, &yh, &ir, &iz, &ip, &iq}) *b = dev_alloc<double>(ns);
     const int64_t np = 2 * ((ns + 255) / 256) + 1024;
@@ -336,6 +373,135 @@ struct dcg3d_ctx {
     H3(hipMalloc(&sc, sizeof(dcg3::PcgScalars)));
     H3(hipHostMalloc(&sc_host, sizeof(dcg3::PcgScalars), hipHostMallocDefault));
     H3(hipHostMalloc(&dots_host, 8 * sizeof(double), hipHostMallocDefault));
+  }
+
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* d = dev_alloc<T>(v.size());
+    H3(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+  }
+
+  // The Galerkin hierarchy of L, its class tables and level vectors.
+  void setup_mg(const std::vector<double>& ld) {
+    mg_J = dcg3::mg3_num_levels(n, opt.levels);
+    if (mg_J < 1) throw Err3(DCG_EINVAL, "no multigrid hierarchy for this n and levels");
+    mg_m = opt.smooth3d;
+    const dcg3::Mg3Hierarchy H = dcg3::build_mg3(n, mg_J, ld);
+    for (int k = 1; k <= mg_J; ++k) {
+      const dcg3::Mg3Level& L = H.lev[k - 1];
+      const int64_t len = 8 * (int64_t)L.n * L.n * L.n;
+      mg_n.push_back(L.n);
+      mg_op.push_back(upload(L.op));
+      mg_ras.push_back(k >= 2 ? upload(L.ras) : nullptr);
+      mg_f.push_back(dev_alloc<double>(len));
+      mg_z.push_back(dev_alloc<double>(len));
+      mg_r.push_back(dev_alloc<double>(len));
+    }
+    mg_cinv = upload(H.coarse_inv);
+    mg_part = dev_alloc<double>(dcg3::mg3_res_blocks(n));
+    H3(hipMalloc(&mg_sc, sizeof(dcg3::Mg3Scalars)));
+    H3(hipHostMalloc(&mg_sc_host, sizeof(dcg3::Mg3Scalars), hipHostMallocDefault));
+    H3(hipStreamCreateWithFlags(&mg_cap, hipStreamNonBlocking));
+  }
+
+  // ---- the W-cycle (Algorithm 4) on level k, every launch guarded by g
+  enum { kZero = 0, kWarm = 1, kResidualGiven = 2 };
+
+  void mg_smooth(int k, int step, int mode, hipStream_t st, const int32_t* g, bool timed) {
+    const int i = k - 1, nk = mg_n[i];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) event_pair(e0, e1);
+    if (step == 0 && mode == kZero) {          // z = S f
+      H3(dcg3::launch_mg3_ras(nk, mg_ras[i], mg_f[i], mg_z[i], true, g, st, e0, e1));
+      return;
+    }
+    if (!(step == 0 && mode == kResidualGiven))
+      H3(dcg3::launch_mg3_res(nk, mg_op[i], mg_f[i], mg_z[i], mg_r[i], nullptr, g, st));
+    H3(dcg3::launch_mg3_ras(nk, mg_ras[i], mg_r[i], mg_z[i], false, g, st, e0, e1));
+  }
+
+  void mg_cycle(int k, int mode, hipStream_t st, const int32_t* g) {
+    const int i = k - 1;
+    if (k == 1) {   // exact solve on the coarsest level
+      H3(dcg3::launch_mg3_dense(8 * mg_n[0] * mg_n[0] * mg_n[0], mg_cinv, mg_f[0], mg_z[0], g, st));
+      return;
+    }
+    const bool timed = timing && k == mg_J && st == nullptr;
+    for (int s = 0; s < mg_m; ++s) mg_smooth(k, s, mode, st, g, timed);
+    H3(dcg3::launch_mg3_res(mg_n[i], mg_op[i], mg_f[i], mg_z[i], mg_r[i], nullptr, g, st));
+    H3(dcg3::launch_mg3_restrict(mg_n[i], mg_r[i], mg_f[i - 1], g, st));
+    // coarse correction: gamma = 2 cycles from zero (the exact solve once)
+    mg_cycle(k - 1, kZero, st, g);
+    if (k - 1 > 1) mg_cycle(k - 1, kWarm, st, g);
+    H3(dcg3::launch_mg3_prolong(mg_n[i], mg_z[i - 1], mg_z[i], false, g, st));
+    for (int s = 0; s < mg_m; ++s) mg_smooth(k, s, kWarm, st, g, timed);
+  }
+
+  // One pass of Algorithm 3: the residual of the finest iterate, the
+  // stopping test, and (while active) the W-cycle that starts from it.
+  void mg_iteration(hipStream_t st) {
+    const int J = mg_J, i = J - 1;
+    const int32_t* g = &mg_sc->active;
+    H3(dcg3::launch_mg3_res(mg_n[i], mg_op[i], mg_f[i], mg_z[i], mg_r[i], mg_part, g, st));
+    H3(dcg3::launch_mg3_test(dcg3::mg3_res_blocks(mg_n[i]), mg_part, mg_sc, st));
+    if (J == 1) {
+      H3(dcg3::launch_mg3_dense(8 * mg_n[0] * mg_n[0] * mg_n[0], mg_cinv, mg_f[0], mg_z[0], g, st));
+      return;
+    }
+    mg_cycle(J, kResidualGiven, st, g);
+  }
+
+  void mg_launch_iteration() {
+    if (!opt.use_graph || timing) {
+      mg_iteration(nullptr);
+      return;
+    }
+    if (!mg_graph) {
+      hipGraph_t gr = nullptr;
+      H3(hipStreamBeginCapture(mg_cap, hipStreamCaptureModeThreadLocal));
+      try {
+        mg_iteration(mg_cap);
+      } catch (...) {
+        (void)hipStreamEndCapture(mg_cap, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      H3(hipStreamEndCapture(mg_cap, &gr));
+      const hipError_t e = hipGraphInstantiate(&mg_graph, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      H3(e);
+    }
+    H3(hipGraphLaunch(mg_graph, nullptr));
+  }
+
+  // yh = E^{-1} s, E = (dt/3) L, by Algorithm 3 on L to ||s - L z|| <= rel ||s||
+  // (the same test as on E, yh = (3/dt) z).  Iterations are enqueued ahead of
+  // the device-side test: as many as the fewest cycles of the last four
+  // solves plus one, then one at a time.
+  int inner_mg(const double* rhs, double* out, double rel) {
+    const int i = mg_J - 1;
+    const int64_t len = 8 * ne;
+    copy(rhs, mg_f[i], len);
+    H3(dcg3::launch_mg3_start(len, mg_z[i], mg_sc, rel * rel, opt.max_inner, nullptr));
+    int pred = 0;
+    if (mg_nrecent > 0) {
+      pred = mg_recent[0];
+      for (int j = 1; j < std::min(mg_nrecent, 4); ++j) pred = std::min(pred, mg_recent[j]);
+    }
+    int launched = 0;
+    for (;;) {
+      const int chunk = launched == 0 ? pred + 1 : 1;
+      for (int c = 0; c < chunk; ++c) mg_launch_iteration();
+      launched += chunk;
+      H3(hipMemcpyAsync(mg_sc_host, mg_sc, sizeof(*mg_sc), hipMemcpyDeviceToHost, nullptr));
+      H3(hipStreamSynchronize(nullptr));
+      if (!mg_sc_host->active || launched > opt.max_inner + 1) break;
+    }
+    const int iters = mg_sc_host->iters;
+    H3(dcg3::launch_mg3_scale(len, 3.0 / dt, mg_z[i], out, nullptr));
+    mg_recent[mg_nrecent++ % 4] = iters;
+    return iters;
   }
 
   // ---- building blocks on the legacy default stream
@@ -349,7 +515,8 @@ struct dcg3d_ctx {
     H3(hipMemcpyAsync(y, x, len * sizeof(double), hipMemcpyDeviceToDevice, nullptr));
   }
   void astar(const double* x, double* y) {
-    const bool timed = timing && inner_kind != DCG3D_INNER_PCG;   // the dominant kernel then
+    // the dominant kernel with the exact inner solve or none
+    const bool timed = timing && (inner_kind == DCG3D_INNER_FDM || inner_kind == DCG3D_INNER_NONE);
     if (timed) time_mark();
     H3(dcg3::launch_astar3(n, Cd, Me, 1.0 / nu, dt, x, y, nullptr));
     if (timed) time_mark();
@@ -367,6 +534,12 @@ struct dcg3d_ctx {
       H3(dcg3::launch_fdm_solve(n, fVx, fVxT, fVy, fVyT, flx, fly, 3.0 / dt, rhs, out, ir, iz, nullptr));
       inner_solves += 1;
       return 0;
+    }
+    if (inner_kind == DCG3D_INNER_MG) {
+      const int it = inner_mg(rhs, out, rel);
+      inner_total += it;
+      inner_solves += 1;
+      return it;
     }
     H3(dcg3::launch_pcg_start(ne, Dinv, rhs, out, ir, iz, ip, part, sc, rel * rel, nullptr));
     H3(hipMemcpyAsync(sc_host, sc, sizeof(*sc), hipMemcpyDeviceToHost, nullptr));
@@ -394,7 +567,8 @@ struct dcg3d_ctx {
   dcg_status solve(const double* f, double* x, double tol, dcg_stats* st) {
     const auto t0 = std::chrono::steady_clock::now();
     inner_total = inner_solves = 0;
-    const double rel_in = opt.c_F * tol;
+    // inner tolerance: eq. (fixed_tol), or eq. (tol) inside the outer loop
+    const double rel_in = opt.c_A > 0.0 ? opt.c_A * tol : opt.c_F * tol;
     const double fnorm = std::sqrt(dot(f, f, nt));
     dcg_stats out{};
     out.t_setup_ms = t_setup_ms;
@@ -422,7 +596,7 @@ struct dcg3d_ctx {
       // q = M_D p = w - dt A_div Z E^{-1} Z^T w, w = A* p
       astar(p, w);
       H3(dcg3::launch_zt3(ne, w, s, nullptr));
-      inner(s, yh, rel_in);
+      inner(s, yh, opt.c_A > 0.0 ? opt.c_A * tol * fnorm / std::sqrt(rho) : rel_in);
       H3(dcg3::launch_adivz3(n, Cd, dt, w, yh, q, nullptr));
       const double pq = dot(p, q, nt);
       if (!(pq > 0.0) || !std::isfinite(pq)) {
@@ -496,6 +670,51 @@ struct dcg3d_ctx {
     }
     H3(hipStreamSynchronize(nullptr));
   }
+
+  // Level operators of the multigrid inner solve (dcg3d_mg_apply).
+  void mg_apply(int op, int k, const double* in, const double* in2, double* outv) {
+    if (inner_kind != DCG3D_INNER_MG) throw Err3(DCG_EINVAL, "the handle has no multigrid hierarchy");
+    if (k < 1 || k > mg_J) throw Err3(DCG_EINVAL, "level out of range");
+    const int i = k - 1, nk = mg_n[i];
+    const int64_t len = 8 * (int64_t)nk * nk * nk;
+    switch (op) {
+      case DCG3D_MG_LAPLACE:    // out = -(0 - L z)
+        H3(dcg3::launch_mg3_res(nk, mg_op[i], nullptr, in, mg_r[i], nullptr, nullptr, nullptr));
+        H3(dcg3::launch_mg3_scale(len, -1.0, mg_r[i], outv, nullptr));
+        break;
+      case DCG3D_MG_RAS:
+        if (k < 2) throw Err3(DCG_EINVAL, "the coarsest level has no smoother");
+        if (!in2) {
+          H3(dcg3::launch_mg3_ras(nk, mg_ras[i], in, outv, true, nullptr, nullptr));
+        } else {
+          copy(in2, outv, len);
+          H3(dcg3::launch_mg3_res(nk, mg_op[i], in, in2, mg_r[i], nullptr, nullptr, nullptr));
+          H3(dcg3::launch_mg3_ras(nk, mg_ras[i], mg_r[i], outv, false, nullptr, nullptr));
+        }
+        break;
+      case DCG3D_MG_RESTRICT:
+        if (k < 2) throw Err3(DCG_EINVAL, "restriction needs level >= 2");
+        H3(dcg3::launch_mg3_restrict(nk, in, outv, nullptr, nullptr));
+        break;
+      case DCG3D_MG_PROLONG:
+        if (k < 2) throw Err3(DCG_EINVAL, "prolongation needs level >= 2");
+        H3(dcg3::launch_mg3_prolong(nk, in, outv, true, nullptr, nullptr));
+        break;
+      case DCG3D_MG_COARSE:
+        if (k != 1) throw Err3(DCG_EINVAL, "the exact solve is on level 1");
+        H3(dcg3::launch_mg3_dense(int(len), mg_cinv, in, outv, nullptr, nullptr));
+        break;
+      case DCG3D_MG_WCYCLE:
+        copy(in, mg_f[i], len);
+        if (in2) copy(in2, mg_z[i], len);
+        mg_cycle(k, in2 ? kWarm : kZero, nullptr, nullptr);
+        copy(mg_z[i], outv, len);
+        break;
+      default:
+        throw Err3(DCG_EINVAL, "unknown multigrid operator");
+    }
+    H3(hipStreamSynchronize(nullptr));
+  }
 };
 
 namespace {
@@ -528,8 +747,9 @@ dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, int32_t 
   if (!out) return fail3(nullptr, DCG_EINVAL, "out is NULL");
   *out = nullptr;
   if (n < 2 || n > DCG3D_MAX_N) return fail3(nullptr, DCG_EINVAL, "n must be in [2, 64]");
-  if (inner != DCG3D_INNER_FDM && inner != DCG3D_INNER_PCG && inner != DCG3D_INNER_NONE)
-    return fail3(nullptr, DCG_EINVAL, "inner must be DCG3D_INNER_FDM, DCG3D_INNER_PCG or DCG3D_INNER_NONE");
+  if (inner != DCG3D_INNER_FDM && inner != DCG3D_INNER_PCG && inner != DCG3D_INNER_NONE &&
+      inner != DCG3D_INNER_MG)
+    return fail3(nullptr, DCG_EINVAL, "inner must be a dcg3d_inner");
   if (!(penalty > 0.0) || !std::isfinite(penalty)) return fail3(nullptr, DCG_EINVAL, "penalty must be positive");
   if (!(dt > 0.0) || !std::isfinite(dt) || !(nu > 0.0) || !std::isfinite(nu))
     return fail3(nullptr, DCG_EINVAL, "dt and nu must be positive");
@@ -544,10 +764,16 @@ dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, int32_t 
   }
   if (o.prec != DCG_FP64) return fail3(nullptr, DCG_EINVAL, "the 3D solver computes in FP64 only");
   if (o.outer != DCG_OUTER_CG) return fail3(nullptr, DCG_EINVAL, "the 3D solver runs the CG outer iteration");
-  if (o.c_A != 0.0) return fail3(nullptr, DCG_EINVAL, "the 3D solver uses the fixed inner tolerance (c_A = 0)");
+  if (!(o.c_A >= 0.0) || !std::isfinite(o.c_A)) return fail3(nullptr, DCG_EINVAL, "c_A must be >= 0");
   if (o.x0_given) return fail3(nullptr, DCG_EINVAL, "the 3D solver starts from x0 = 0");
   if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
     return fail3(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
+  if (inner == DCG3D_INNER_MG) {
+    if (o.smooth3d < 1) return fail3(nullptr, DCG_EINVAL, "smooth3d must be >= 1");
+    if (dcg3::mg3_num_levels(n, o.levels) < 1)
+      return fail3(nullptr, DCG_EINVAL,
+                   "multigrid needs n = c 2^(J-1) with a coarsest size c in [2, 4] (levels = J, 0 = all)");
+  }
   auto* h = new (std::nothrow) dcg3d_ctx();
   if (!h) return fail3(nullptr, DCG_ENOMEM, "host allocation failed");
   h->n = n;
@@ -587,6 +813,23 @@ dcg_status dcg3d_apply(dcg3d_handle h, dcg3d_op op, const double* in, double* ou
   });
 }
 
+dcg_status dcg3d_mg_apply(dcg3d_handle h, int32_t op, int32_t level, const double* in,
+                          const double* in2, double* out) {
+  if (!h || !in || !out) return fail3(h, DCG_EINVAL, "NULL argument");
+  return guarded3(h, [&] {
+    h->mg_apply(op, level, in, in2, out);
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg3d_mg_levels(dcg3d_handle h, int32_t* levels, int32_t* coarsest) {
+  if (!h || !levels || !coarsest) return fail3(h, DCG_EINVAL, "NULL argument");
+  if (h->inner_kind != DCG3D_INNER_MG) return fail3(h, DCG_EINVAL, "the handle has no multigrid hierarchy");
+  *levels = h->mg_J;
+  *coarsest = h->mg_n[0];
+  return DCG_OK;
+}
+
 dcg_status dcg3d_destroy(dcg3d_handle h) {
   delete h;
   return DCG_OK;
@@ -613,6 +856,27 @@ dcg_status dcg3d_host_blocks(int32_t n, double penalty, double dt, int32_t which
     assemble3d(n, penalty, dt, cd, ld, dinv, me);
     const std::vector<double>* src[4] = {&cd, &ld, &dinv, &me};
     std::memcpy(out, src[which]->data(), src[which]->size() * sizeof(double));
+    return DCG_OK;
+  });
+}
+
+dcg_status dcg3d_host_mg(int32_t n, double penalty, int32_t levels, int32_t level, int32_t which,
+                         double* out) {
+  if (!out) return fail3(nullptr, DCG_EINVAL, "out is NULL");
+  if (n < 2 || n > DCG3D_MAX_HOST_BLOCKS_N) return fail3(nullptr, DCG_EINVAL, "n must be in [2, 16]");
+  if (!(penalty > 0.0)) return fail3(nullptr, DCG_EINVAL, "penalty must be positive");
+  const int J = dcg3::mg3_num_levels(n, levels);
+  if (J < 1) return fail3(nullptr, DCG_EINVAL, "no multigrid hierarchy for this n and levels");
+  if (level < 1 || level > J) return fail3(nullptr, DCG_EINVAL, "level out of range");
+  if (which < 0 || which > 2 || (which == 1 && level < 2) || (which == 2 && level != 1))
+    return fail3(nullptr, DCG_EINVAL, "which must be 0, 1 (level >= 2) or 2 (level 1)");
+  return guarded3(nullptr, [&] {
+    std::vector<double> cd, ld, dinv, me;
+    assemble3d(n, penalty, 1.0, cd, ld, dinv, me);
+    const dcg3::Mg3Hierarchy H = dcg3::build_mg3(n, J, ld);
+    const std::vector<double>& src =
+        which == 0 ? H.lev[level - 1].op : (which == 1 ? H.lev[level - 1].ras : H.coarse_inv);
+    std::memcpy(out, src.data(), src.size() * sizeof(double));
     return DCG_OK;
   });
 }

@@ -1,0 +1,283 @@
+"""The multigrid inner solve of the 3D path (DCG3D_INNER_MG) against the
+oracle's three-dimensional hierarchy (Section 4.2, the 3D case).
+
+Level operators: every dcg3d_mg_apply operator element by element against
+the oracle (L_k, S_k, P_k, P_k^T, the coarsest solve, the W-cycle of
+Algorithm 4 from zero and from a given iterate, m = 10 and m = 2) on
+hierarchies with 2 and 3 levels and coarsest sizes 2, 3 and 4.  Bar: max
+abs difference <= 1e-12 x max |oracle| for the single operators, 1e-11 for
+the W-cycle (FP64, different summation order).
+
+Solves: small cases against the oracle's Algorithm 2 run here (n = 4, both
+inner-tolerance rules): outer counts within +-2, Tot within +-2 % and x
+within 1e-6; the analogue of Table 5 (right) at n = 8 against the oracle's
+stored results (tests/golden/make_3d_mg_golden.py); graph replays against
+direct launches bit for bit.  At the benchmark size (n = 32) the RAS step is
+checked on sampled cubes against the RAS definition applied to the oracle's
+Laplacian, the W-cycle by its contraction, and the solve by its true
+residual and its repeatability."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from dcg_workloads import THREE_D, rhs3d
+from layout import elem_to_comp3
+from oracle import discretisation3d as d3
+from oracle import krylov as kr
+from oracle import multigrid as mg
+from oracle import multigrid3d as mg3
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lib = pytest.importorskip("paper_2606_13429_amd._binding")
+import paper_2606_13429_amd as dcg  # noqa: E402
+
+PEN, NU = THREE_D["penalty"], THREE_D["nu"]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mg3d_table5_n8_seed0.txt")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _close(got, ref, rel):
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(got - ref).max() / scale
+    assert err <= rel, "max rel error %.3e" % err
+
+
+def _coarsest(n, levels):
+    if levels:
+        return n >> (levels - 1)
+    c = n
+    while c % 2 == 0 and c // 2 >= 2:
+        c //= 2
+    return c
+
+
+@pytest.mark.parametrize("n,levels,m", [(4, 0, 10), (6, 0, 2), (8, 0, 10), (16, 3, 2)])
+def test_level_operators_match_oracle(n, levels, m):
+    print("3d mg operators n=%d levels=%d m=%d" % (n, levels, m), flush=True)
+    H = mg3.Hierarchy(d3.sipg_laplacian(n, PEN), n, coarsest=_coarsest(n, levels))
+    s = dcg.Solver3D(n, 1e-3, nu=NU, penalty=PEN, inner="mg", levels=levels, smooth=m)
+    assert s.mg_levels() == (H.J, H.n[1])
+    rng = np.random.default_rng(n + m)
+    for k in range(1, H.J + 1):
+        size = 8 * H.n[k] ** 3
+        A = H.A[k]
+        f, z = rng.standard_normal(size), rng.standard_normal(size)
+        out = torch.empty(size, dtype=torch.float64, device="cuda")
+        s.mg_apply(lib.DCG3D_MG_LAPLACE, k, _dev(z), out)
+        _close(_host(out), A @ z, 1e-12)
+        if k >= 2:
+            s.mg_apply(lib.DCG3D_MG_RAS, k, _dev(f), out)
+            _close(_host(out), H.S[k].apply(f), 1e-12)
+            s.mg_apply(lib.DCG3D_MG_RAS, k, _dev(f), out, in2=_dev(z))
+            _close(_host(out), z + H.S[k].apply(f - A @ z), 1e-12)
+            small = torch.empty(8 * H.n[k - 1] ** 3, dtype=torch.float64, device="cuda")
+            s.mg_apply(lib.DCG3D_MG_RESTRICT, k, _dev(f), small)
+            _close(_host(small), H.P[k].T @ f, 1e-12)
+            e = rng.standard_normal(small.numel())
+            s.mg_apply(lib.DCG3D_MG_PROLONG, k, _dev(e), out)
+            _close(_host(out), H.P[k] @ e, 1e-12)
+        else:
+            s.mg_apply(lib.DCG3D_MG_COARSE, 1, _dev(f), out)
+            _close(_host(out), sla.cho_solve(H.chol, f), 1e-11)
+        s.mg_apply(lib.DCG3D_MG_WCYCLE, k, _dev(f), out)
+        _close(_host(out), mg.wcycle(H, f, np.zeros(size), k, m, m), 1e-11)
+        s.mg_apply(lib.DCG3D_MG_WCYCLE, k, _dev(f), out, in2=_dev(z))
+        _close(_host(out), mg.wcycle(H, f, z, k, m, m), 1e-11)
+    with pytest.raises(lib.DCGError):
+        s.mg_apply(lib.DCG3D_MG_RAS, 1, _dev(np.zeros(8 * H.n[1] ** 3)), out)
+    s.close()
+
+
+def test_inner_solve_is_the_multigrid_iteration():
+    # DCG3D_OP_INNER: (dt/3 L)^{-1} s by Algorithm 3 to the relative residual,
+    # the oracle's Multigrid on its own Galerkin hierarchy of E = V^T A* V
+    n, dt, rel = 8, 1e-2, 1e-10
+    print("3d mg inner n=%d" % n, flush=True)
+    As = d3.operator(n, dt, nu=NU, penalty=PEN)
+    V = d3.deflation_basis(n)
+    E = (V.T @ As @ V).tocsr()
+    H = mg3.Hierarchy(E, n)
+    y = np.random.default_rng(5).standard_normal(8 * n ** 3)
+    z_ref, cycles = mg.multigrid(H, y, m1=10, m2=10, tol=rel)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg")
+    out = torch.empty(8 * n ** 3, dtype=torch.float64, device="cuda")
+    s.apply(lib.DCG3D_OP_INNER, _dev(y), out, rel)
+    z = _host(out)
+    assert np.linalg.norm(E @ z - y) <= rel * np.linalg.norm(y)
+    # the same number of cycles: one cycle fewer or more moves z by about
+    # the contraction factor times its error
+    _close(z, z_ref, 1e-12 * cycles)
+    s.close()
+
+
+_SMALL = {}
+
+
+def _small_oracle(n, dt, rule, c):
+    key = (n, dt, rule, c)
+    if key not in _SMALL:
+        As = d3.operator(n, dt, nu=NU, penalty=PEN)
+        V = d3.deflation_basis(n)
+        E = (V.T @ As @ V).tocsr()
+        f = elem_to_comp3(rhs3d(n, 4), n)
+        kw = dict(c_F=c) if rule == "F" else dict(c_A=c)
+        _SMALL[key] = kr.dcg(As, V, f, kr.mg_inner(mg3.Hierarchy(E, n), 10, 10), tol=1e-8, **kw)
+    return _SMALL[key]
+
+
+@pytest.mark.parametrize("dt,rule,c", [(1e-1, "F", 0.01), (1e-1, "A", 0.02), (1e-3, "F", 0.01),
+                                       (1e-3, "A", 0.005)])
+def test_small_solve_matches_oracle(dt, rule, c):
+    n = 4
+    res = _small_oracle(n, dt, rule, c)
+    print("3d mg solve n=%d dt=%g %s=%g" % (n, dt, rule, c), flush=True)
+    kw = dict(c_F=c) if rule == "F" else dict(c_A=c)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg", **kw)
+    b = _dev(rhs3d(n, 4))
+    x = torch.empty_like(b)
+    status, st = s.solve(b, x, 1e-8)
+    s.close()
+    assert status == lib.DCG_OK
+    assert abs(st.outer_iters - res.iterations) <= 2, (st.outer_iters, res.iterations)
+    assert abs(st.total_wcycles - res.total_cycles) <= max(2, 0.02 * res.total_cycles), \
+        (st.total_wcycles, res.total_cycles)
+    assert st.inner_solves == st.outer_iters + 2
+    xg = elem_to_comp3(_host(x), n)
+    assert np.linalg.norm(xg - res.x) <= 1e-6 * np.linalg.norm(res.x)
+    assert st.rel_res_true <= 10 * 1e-8
+
+
+def _golden():
+    rows, xs = {}, {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            p = line.split()
+            if not p or p[0].startswith("#"):
+                continue
+            key = (float(p[1]), p[2], float(p[3]))
+            if p[0] == "row":
+                rows[key] = dict(outer=int(p[4]), tot=int(p[5]), solves=int(p[6]), rec=float(p[7]),
+                                 true=float(p[8]), x_norm=float(p[9]))
+            else:
+                xs.setdefault(key, []).append((int(p[4]), float(p[5])))
+    return rows, xs
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle golden file not written")
+@pytest.mark.parametrize("dt", [0.5, 0.1, 1e-2, 1e-3, 1e-4])
+@pytest.mark.parametrize("rule,c", [("F", 0.01), ("A", 0.02), ("A", 0.005)])
+def test_table5_right_analogue_matches_stored_oracle(dt, rule, c):
+    rows, xs = _golden()
+    ref = rows[(dt, rule, c)]
+    n = 8
+    b = _dev(rhs3d(n, 0))
+    kw = dict(c_F=c) if rule == "F" else dict(c_A=c)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg", max_outer=20000, **kw)
+    x = torch.empty_like(b)
+    print("3d mg n=8 dt=%g %s=%g" % (dt, rule, c), flush=True)
+    status, st = s.solve(b, x, 1e-8)
+    s.close()
+    print("  Out %d (oracle %d) Tot %d (oracle %d)"
+          % (st.outer_iters, ref["outer"], st.total_wcycles, ref["tot"]), flush=True)
+    assert status == lib.DCG_OK
+    assert abs(st.outer_iters - ref["outer"]) <= max(2, 0.02 * ref["outer"])
+    assert abs(st.total_wcycles - ref["tot"]) <= max(2, 0.02 * ref["tot"])
+    assert st.inner_solves == ref["solves"] + (st.outer_iters - ref["outer"])
+    idx, val = np.array(xs[(dt, rule, c)]).T
+    xg = _host(x)
+    assert np.linalg.norm(xg[idx.astype(int)] - val) <= 1e-6 * np.linalg.norm(val)
+    assert abs(np.linalg.norm(xg) - ref["x_norm"]) <= 1e-6 * ref["x_norm"]
+
+
+def test_graph_replay_equals_direct_launches():
+    n, dt = 8, 1e-2
+    print("3d mg graph vs direct n=%d" % n, flush=True)
+    b = _dev(rhs3d(n, 3))
+    out = []
+    for use_graph in (True, False):
+        s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg", use_graph=use_graph)
+        x = torch.empty_like(b)
+        status, st = s.solve(b, x, 1e-8)
+        s.close()
+        assert status == lib.DCG_OK
+        out.append((x, st.outer_iters, st.total_wcycles))
+    assert torch.equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
+
+
+def _ras_on_cube(L, n, r, cube):
+    """(S r) on one cube from the RAS definition (Section 4.2): the blocks of
+    the cube and of each face neighbour, the local problems of the oracle's
+    Laplacian solved densely, weighted by 1 / (blocks holding the cube)."""
+    def inside(c):
+        return all(0 <= v < n for v in c)
+
+    def nbrs(c):
+        return [tuple(c[i] + (d if i == a else 0) for i in range(3))
+                for a in range(3) for d in (-1, 1)]
+
+    def dofs(cubes):
+        return np.concatenate([8 * d3.element_index(n, *q) + np.arange(8) for q in cubes])
+
+    owners = [cube] + [q for q in nbrs(cube) if inside(q)]
+    out = np.zeros(8)
+    for b in owners:
+        cubes = [b] + [q for q in nbrs(b) if inside(q)]
+        idx = dofs(cubes)
+        y = np.linalg.solve(L[idx][:, idx].toarray(), r[idx])
+        k = cubes.index(cube)
+        out += y[8 * k:8 * k + 8]
+    return out / len(owners)
+
+
+def test_full_size_ras_step_wcycle_and_solve():
+    n, dt, tol = THREE_D["n"], THREE_D["dt"], THREE_D["tol"]
+    print("3d mg full size n=%d" % n, flush=True)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg")
+    J, c = s.mg_levels()
+    assert (J, c) == (5, 2)
+    L = sp.csr_matrix(d3.sipg_laplacian(n, PEN))
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(8 * n ** 3)
+    out = torch.empty_like(_dev(r))
+    s.mg_apply(lib.DCG3D_MG_RAS, J, _dev(r), out)
+    got = _host(out).reshape(-1, 8)
+    cubes = [(0, 0, 0), (1, 0, 0), (2, 1, 0), (n - 1, n - 1, n - 1), (n - 2, 3, n - 3), (n // 2, n // 2, n // 2),
+             (13, 21, 3), (n - 1, 17, 9), (1, 30, 30), (31, 0, 16), (2, 2, 2), (3, n - 4, 5)]
+    for q in cubes:
+        ref = _ras_on_cube(L, n, r, q)
+        assert np.abs(got[d3.element_index(n, *q)] - ref).max() <= 1e-12 * np.abs(ref).max(), q
+    # the W-cycle contracts the error of L z = f (two-grid radius 0.52 at m = 10)
+    f = rng.standard_normal(8 * n ** 3)
+    fd, z = _dev(f), torch.zeros(8 * n ** 3, dtype=torch.float64, device="cuda")
+    Lz = torch.empty_like(z)
+    res = [1.0]
+    for _ in range(4):
+        s.mg_apply(lib.DCG3D_MG_WCYCLE, J, fd, out, in2=z)
+        z = out.clone()
+        s.mg_apply(lib.DCG3D_MG_LAPLACE, J, z, Lz)
+        res.append(float((fd - Lz).norm() / fd.norm()))
+    assert all(b < 0.7 * a for a, b in zip(res, res[1:])), res
+    # the solve converges, twice bit for bit
+    b = _dev(rhs3d(n, 0))
+    x1, x2 = torch.empty_like(b), torch.empty_like(b)
+    status, st = s.solve(b, x1, tol)
+    print("  n=%d solve: Out %d Tot %d true %.2e %.1f s"
+          % (n, st.outer_iters, st.total_wcycles, st.rel_res_true, st.t_solve_ms / 1e3), flush=True)
+    assert status == lib.DCG_OK and st.rel_res_true <= 10 * tol
+    assert 20 <= st.total_wcycles / st.inner_solves <= 60
+    status, st2 = s.solve(b, x2, tol)
+    s.close()
+    assert torch.equal(x1, x2) and (st2.outer_iters, st2.total_wcycles) == (st.outer_iters, st.total_wcycles)
