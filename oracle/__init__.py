@@ -24,7 +24,11 @@ multigrid3d     the three-dimensional hierarchy (2x2x2 agglomeration, trilinear
                 transfers, RAS blocks of a cube and its face neighbours) for the
                 same W-cycle (Section 4.2, the 3D case).
 krylov          CG, deflated CG and FCG(m) (Section 4.1, eqs. (x_defl),
-                (defl_sys), (fixed_tol), (tol), Algorithms 1 and 2).
+                (defl_sys), (fixed_tol), (tol), Algorithms 1 and 2), with an
+                optional preconditioner in the flexible form.
+precond         multigrid on A* itself (tensor Galerkin hierarchy, RAS blocks of
+                a square and its edge neighbours) as that preconditioner: the
+                outer multigrid the paper's conclusions leave to future work.
 timestep        BDF2 right-hand side for a time-stepping run (Section 2.3).
 
 Every function cites the passage it follows.  Parity status of each function

@@ -145,7 +145,7 @@ def _gmres(M_D, r0, x0, eps, max_iter, tol_c):
 
 
 def dcg(Astar, V, f, inner, tol=1e-8, max_iter=100000, x0=None, outer='cg',
-        m_max=None, c_F=0.01, c_A=None, restarts=0, trace=None):
+        m_max=None, c_F=0.01, c_A=None, restarts=0, trace=None, precond=None):
     """Deflated (flexible) CG, Algorithm 2.  Returns a DCGResult with x,
     outer iterations, total inner cycles (Tot), the per-solve inner cycle
     counts, and recurrence / true relative residuals.
@@ -156,6 +156,12 @@ def dcg(Astar, V, f, inner, tol=1e-8, max_iter=100000, x0=None, outer='cg',
     most ``restarts`` times; pi(f) and f_D are those of the first pass (the
     same inner solve of the same vector).  Outer iterations and inner cycles
     are counted over all passes, and max_iter caps their total.
+
+    ``precond``: with outer='fcg', a map B ~ (A*)^{-1} applied to each
+    residual; the direction is built from z_i = B(r_i) in place of r_i
+    (d_i = z_i - sum_k (z_i, q_k) / (d_k, q_k) d_k over the window, alpha_i =
+    (d_i, r_i) / (d_i, q_i)), the flexible preconditioned form of Algorithm 1
+    (oracle/precond.py).
 
     ``trace``: a list that receives, for every iteration i, with FCG the
     residual r_i the direction was built from, the direction d_i and
@@ -209,9 +215,10 @@ def dcg(Astar, V, f, inner, tol=1e-8, max_iter=100000, x0=None, outer='cg',
                 m_i = i
             else:
                 m_i = 0 if i == 0 else max(1, i % (m_max + 1))
-            d = r.copy()
+            z = precond(r) if precond is not None else r
+            d = z.copy()
             for k in range(i - m_i, i):
-                d -= (r @ qs[k]) / dqs[k] * ds[k]
+                d -= (z @ qs[k]) / dqs[k] * ds[k]
             q = M_D(d, tol_c(np.linalg.norm(r)), True)
             dq = d @ q
             alpha = (d @ r) / dq
@@ -236,6 +243,8 @@ def dcg(Astar, V, f, inner, tol=1e-8, max_iter=100000, x0=None, outer='cg',
     runs = dict(cg=run_cg, fcg=run_fcg, gmres=run_gmres)
     if outer not in runs:
         raise ValueError(outer)
+    if precond is not None and outer != 'fcg':
+        raise ValueError("a preconditioner needs the flexible outer iteration")
     pf = pi(f, tol_c())                       # pi(f), reused in the epilogue
     f_D = f - Astar @ pf
     x = np.zeros_like(f) if x0 is None else x0.copy()
