@@ -573,7 +573,7 @@ def three_d(args):
     torch.cuda.set_device(0)
     t0 = time.time()
     s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], inner=args.inner3,
-                     c_A=args.cA3)
+                     c_A=args.cA3, max_outer=args.max_outer3)
     log("3d setup n=%d (%d elements) %.1f s" % (n, n ** 3, time.time() - t0))
     bs = [torch.from_numpy(rhs3d(n, i)).cuda() for i in range(max(args.steps, 1))]
     x = torch.empty_like(bs[0])
@@ -814,6 +814,8 @@ def main():
                     help="run the 3D solver at --n3 cubes per side")
     ap.add_argument("--n3", type=int, default=32)
     ap.add_argument("--3d-inner", dest="inner3", choices=("exact", "cg", "mg"), default="exact")
+    ap.add_argument("--3d-max-outer", dest="max_outer3", type=int, default=50000,
+                    help="3D: cap on outer iterations (profiling runs only)")
     ap.add_argument("--3d-cA", dest="cA3", type=float, default=0.0,
                     help="3D: adaptive inner tolerance constant (0 = fixed c_F = 0.01)")
     ap.add_argument("--3d-table5", dest="three_d_table5", action="store_true",

@@ -392,8 +392,9 @@ struct dcg3d_ctx {
       const dcg3::Mg3Level& L = H.lev[k - 1];
       const int64_t len = 8 * (int64_t)L.n * L.n * L.n;
       mg_n.push_back(L.n);
-      mg_op.push_back(upload(L.op));
-      mg_ras.push_back(k >= 2 ? upload(L.ras) : nullptr);
+      const bool split = dcg3::mg3_split(L.n);   // small levels: row-major tables
+      mg_op.push_back(upload(split ? L.op : dcg3::op_rows_fastest(L.op)));
+      mg_ras.push_back(k >= 2 ? upload(split ? L.ras : dcg3::rows_fastest(L.ras, dcg3::kRasCols)) : nullptr);
       mg_f.push_back(dev_alloc<double>(len));
       mg_z.push_back(dev_alloc<double>(len));
       mg_r.push_back(dev_alloc<double>(len));

@@ -375,6 +375,65 @@ void build_tiles(HostLevel& lv) {
     if (!o) throw std::runtime_error("RAS local matrix not positive definite");
 }
 
+// The element and face integrals of one mesh size, and the five 16 x 16
+// A_div blocks of square (ex, ey) (slot order self, x-1, x+1, y-1, y+1;
+// added into blk, which the caller zeroes).
+struct SquareForms {
+  Vol vol;
+  Face Fv, Fh, Fl, Fb;
+  double mass[16];
+};
+
+SquareForms square_forms(int n, double penalty) {
+  const double h = 1.0 / n, gamma = penalty / h;
+  SquareForms F;
+  F.vol = volume_forms(h);
+  const Side vert[2] = {{0, 1.0, {1.0, 0.0}}, {0, 0.0, {-1.0, 0.0}}};    // left | right
+  const Side horz[2] = {{1, 1.0, {0.0, 1.0}}, {1, 0.0, {0.0, -1.0}}};    // lower | upper
+  const Side left[1] = {{0, 0.0, {-1.0, 0.0}}};
+  const Side bottom[1] = {{1, 0.0, {0.0, -1.0}}};
+  F.Fv = face_forms(vert, 2, h, gamma);
+  F.Fh = face_forms(horz, 2, h, gamma);
+  F.Fl = face_forms(left, 1, h, gamma);
+  F.Fb = face_forms(bottom, 1, h, gamma);
+  std::memset(F.mass, 0, sizeof F.mass);
+  for (int qy = 0; qy < 2; ++qy)
+    for (int qx = 0; qx < 2; ++qx)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+          F.mass[a * 4 + b] += kGaussW[qx] * kGaussW[qy] * h * h * q1(a, kGauss[qx], kGauss[qy]) *
+                               q1(b, kGauss[qx], kGauss[qy]);
+  return F;
+}
+
+void square_adiv(const SquareForms& F, int n, int ex, int ey, double* blk) {
+  double* self = blk;
+  auto face = [](const Face& Fc, int st, int ss) {
+    return [&Fc, st, ss](int i, int j, int a, int b) { return Fc.f[i][j][st][ss][a][b]; };
+  };
+  add_tensor_block(self, [&](int i, int j, int a, int b) { return F.vol.s[i][j][a][b]; });
+  if (ex > 0) {                                   // face x = ex h, e is the right side
+    add_tensor_block(self, face(F.Fv, 1, 1));
+    add_tensor_block(blk + 1 * 256, face(F.Fv, 1, 0));
+  } else {
+    add_tensor_block(self, face(F.Fl, 0, 0));     // traction boundary x = 0
+  }
+  if (ex < n - 1) {                               // face x = (ex+1) h, e is the left side
+    add_tensor_block(self, face(F.Fv, 0, 0));
+    add_tensor_block(blk + 2 * 256, face(F.Fv, 0, 1));
+  }
+  if (ey > 0) {                                   // face y = ey h, e is the upper side
+    add_tensor_block(self, face(F.Fh, 1, 1));
+    add_tensor_block(blk + 3 * 256, face(F.Fh, 1, 0));
+  } else {
+    add_tensor_block(self, face(F.Fb, 0, 0));     // traction boundary y = 0
+  }
+  if (ey < n - 1) {                               // face y = (ey+1) h, e is the lower side
+    add_tensor_block(self, face(F.Fh, 0, 0));
+    add_tensor_block(blk + 4 * 256, face(F.Fh, 0, 1));
+  }
+}
+
 }  // namespace
 
 int num_levels(int n) {
@@ -388,6 +447,30 @@ int num_levels(int n) {
   return J;
 }
 
+void astar_class_blocks(int n, double penalty, double dt, double nu, std::vector<double>& out) {
+  if (n < 3) throw std::runtime_error("n must be >= 3");
+  const SquareForms F = square_forms(n, penalty);
+  // the dev-dev coefficients of Section 3.1 (d = 2), components 11, 12, 21, 22
+  const double C[4][4] = {{0.5, 0, 0, -0.5}, {0, 1, 0, 0}, {0, 0, 1, 0}, {-0.5, 0, 0, 0.5}};
+  out.assign(9 * kSlots * 256, 0.0);
+  const int pos[3] = {0, 1, n - 1};
+  std::vector<double> adiv(kSlots * 256);
+  for (int cy = 0; cy < 3; ++cy)
+    for (int cx = 0; cx < 3; ++cx) {
+      std::fill(adiv.begin(), adiv.end(), 0.0);
+      square_adiv(F, n, pos[cx], pos[cy], adiv.data());
+      double* blk = &out[(cx + 3 * cy) * kSlots * 256];
+      for (int s = 0; s < kSlots; ++s)
+        for (int i = 0; i < 256; ++i) blk[s * 256 + i] = dt * adiv[s * 256 + i];
+      for (int c = 0; c < 4; ++c)
+        for (int c2 = 0; c2 < 4; ++c2)
+          if (C[c][c2] != 0.0)
+            for (int a = 0; a < 4; ++a)
+              for (int b = 0; b < 4; ++b)
+                blk[(4 * c + a) * 16 + 4 * c2 + b] += C[c][c2] * F.mass[a * 4 + b] / nu;
+    }
+}
+
 void build_host_context(int n, double penalty, bool with_tiles, bool with_coarse,
                         HostContext& out) {
   const int J = num_levels(n);
@@ -397,25 +480,9 @@ void build_host_context(int n, double penalty, bool with_tiles, bool with_coarse
   out.n = n;
   out.J = J;
   out.penalty = penalty;
-  const double h = 1.0 / n, gamma = penalty / h;
   const int64_t ne = int64_t(n) * n;
-
-  const Vol vol = volume_forms(h);
-  const Side vert[2] = {{0, 1.0, {1.0, 0.0}}, {0, 0.0, {-1.0, 0.0}}};    // left | right
-  const Side horz[2] = {{1, 1.0, {0.0, 1.0}}, {1, 0.0, {0.0, -1.0}}};    // lower | upper
-  const Side left[1] = {{0, 0.0, {-1.0, 0.0}}};
-  const Side bottom[1] = {{1, 0.0, {0.0, -1.0}}};
-  const Face Fv = face_forms(vert, 2, h, gamma), Fh = face_forms(horz, 2, h, gamma);
-  const Face Fl = face_forms(left, 1, h, gamma), Fb = face_forms(bottom, 1, h, gamma);
-
-  double mass[16];
-  std::memset(mass, 0, sizeof mass);
-  for (int qy = 0; qy < 2; ++qy)
-    for (int qx = 0; qx < 2; ++qx)
-      for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b)
-          mass[a * 4 + b] += kGaussW[qx] * kGaussW[qy] * h * h * q1(a, kGauss[qx], kGauss[qy]) *
-                             q1(b, kGauss[qx], kGauss[qy]);
+  const SquareForms F = square_forms(n, penalty);
+  const double* mass = F.mass;
 
   set_cols(n, out.cols);
   out.Adiv.assign(ne * kSlots * 256, 0.0);
@@ -423,38 +490,14 @@ void build_host_context(int n, double penalty, bool with_tiles, bool with_coarse
   out.M1.resize(ne * 16);
   parallel_for(ne, [&](int64_t e) {
     const int ex = int(e % n), ey = int(e / n);
-    double* self = &out.Adiv[(e * kSlots + 0) * 256];
-    auto face = [](const Face& F, int st, int ss) {
-      return [&F, st, ss](int i, int j, int a, int b) { return F.f[i][j][st][ss][a][b]; };
-    };
-    add_tensor_block(self, [&](int i, int j, int a, int b) { return vol.s[i][j][a][b]; });
-    if (ex > 0) {                                   // face x = ex h, e is the right side
-      add_tensor_block(self, face(Fv, 1, 1));
-      add_tensor_block(&out.Adiv[(e * kSlots + 1) * 256], face(Fv, 1, 0));
-    } else {
-      add_tensor_block(self, face(Fl, 0, 0));       // traction boundary x = 0
-    }
-    if (ex < n - 1) {                               // face x = (ex+1) h, e is the left side
-      add_tensor_block(self, face(Fv, 0, 0));
-      add_tensor_block(&out.Adiv[(e * kSlots + 2) * 256], face(Fv, 0, 1));
-    }
-    if (ey > 0) {                                   // face y = ey h, e is the upper side
-      add_tensor_block(self, face(Fh, 1, 1));
-      add_tensor_block(&out.Adiv[(e * kSlots + 3) * 256], face(Fh, 1, 0));
-    } else {
-      add_tensor_block(self, face(Fb, 0, 0));       // traction boundary y = 0
-    }
-    if (ey < n - 1) {                               // face y = (ey+1) h, e is the lower side
-      add_tensor_block(self, face(Fh, 0, 0));
-      add_tensor_block(&out.Adiv[(e * kSlots + 4) * 256], face(Fh, 0, 1));
-    }
+    square_adiv(F, n, ex, ey, &out.Adiv[e * kSlots * 256]);
     for (int s = 0; s < kSlots; ++s) {              // A_div Z: Z puts q / sqrt(2) in 11, 22
       const double* A = &out.Adiv[(e * kSlots + s) * 256];
       double* AZ = &out.AdivZ[(e * kSlots + s) * 64];
       for (int r = 0; r < 16; ++r)
         for (int b = 0; b < 4; ++b) AZ[r * 4 + b] = (A[r * 16 + b] + A[r * 16 + 12 + b]) * kInvSqrt2;
     }
-    std::memcpy(&out.M1[e * 16], mass, sizeof mass);
+    std::memcpy(&out.M1[e * 16], mass, sizeof F.mass);
   });
 
   // finest Laplacian L_J = 2 Z^T A_div Z (Corollary 1 with dt factored out)

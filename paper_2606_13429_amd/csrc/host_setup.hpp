@@ -44,6 +44,13 @@ struct HostContext {
   std::vector<double> coarse_inv;  // [1024][1024]
 };
 
+// The 16 x 16 blocks of A* = (1/nu) M + dt A_div (eq. (pb_study)) of one
+// square of each boundary class on the n x n grid: out[cls][slot][16][16],
+// row-major, cls = cx + 3 cy with c = 0 at the low side (x = 0), 1 inside,
+// 2 at the high side; rows and columns 4 c + j in the element-major order
+// (c the stress component 11, 12, 21, 22, j the corner).  n >= 3.
+void astar_class_blocks(int n, double penalty, double dt, double nu, std::vector<double>& out);
+
 // J = log2(n / 16) + 1, or -1 if n is not 16 * 2^k (n <= 2048).
 int num_levels(int n);
 

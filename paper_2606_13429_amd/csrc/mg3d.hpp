@@ -30,6 +30,11 @@
 //                        levels with n_k < 6 take one class per cube,
 //                        cls = e (at most 125)
 // The coarsest level keeps the dense inverse of its operator, row-major.
+// On the device, levels with more than kSplitMaxN cubes per side store both
+// tables with the row index fastest (op [27][7 slots][8 columns][8 rows],
+// ras [343][200 columns][8 rows], from op_rows_fastest / rows_fastest), so
+// that the eight threads of a cube read one contiguous segment per column;
+// smaller levels keep the row-major tables (one lane per row segment).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -44,6 +49,7 @@ constexpr int kRasClassMinN = 6;   // smaller levels: one class per cube
 constexpr int kDiamond = 25;
 constexpr int kRasCols = 8 * kDiamond;
 constexpr int kMaxCoarsest = 4;
+constexpr int kSplitMaxN = 16;     // levels up to this size: one lane per term group
 
 // Offsets (dx, dy, dz) of the diamond, |dx| + |dy| + |dz| <= 2, in the order
 // z, then y, then x ascending.
@@ -59,6 +65,11 @@ struct Mg3Hierarchy {
   std::vector<Mg3Level> lev;        // lev[k - 1] is level k
   std::vector<double> coarse_inv;   // [m_1][m_1], m_1 = 8 c^3
 };
+
+// A table of [classes][8 rows][cols] (row-major blocks) as
+// [classes][cols][8 rows]; the operator table [27][7][8][8] as [27][7][8 b][8 a].
+std::vector<double> rows_fastest(const std::vector<double>& t, int cols);
+std::vector<double> op_rows_fastest(const std::vector<double>& op);
 
 // Number of levels J for n cubes per side with the finest `levels` levels
 // (0: down to the smallest coarsest size c >= 2); c = n / 2^(J-1) must lie
@@ -78,6 +89,9 @@ Mg3Hierarchy build_mg3(int n, int J, const std::vector<double>& ld);
 hipError_t launch_mg3_res(int nk, const double* op, const double* f, const double* z, double* r,
                           double* part, const int32_t* guard, hipStream_t st);
 int mg3_res_blocks(int nk);
+// True when level nk runs the small-level kernels (one lane per term group
+// without LDS staging, row-major tables) rather than the brick kernels.
+bool mg3_split(int nk);
 // z = (zero ? 0 : z) + S_k r, ras the level's class table.
 hipError_t launch_mg3_ras(int nk, const double* ras, const double* r, double* z, bool zero,
                           const int32_t* guard, hipStream_t st, hipEvent_t ev0 = nullptr,

@@ -290,6 +290,23 @@ void diamond_offsets(int off[kDiamond][3]) {
         }
 }
 
+std::vector<double> rows_fastest(const std::vector<double>& t, int cols) {
+  const size_t per = (size_t)8 * cols, nc = t.size() / per;
+  std::vector<double> out(t.size());
+  for (size_t c = 0; c < nc; ++c)
+    for (int a = 0; a < 8; ++a)
+      for (int j = 0; j < cols; ++j) out[c * per + (size_t)j * 8 + a] = t[c * per + (size_t)a * cols + j];
+  return out;
+}
+
+std::vector<double> op_rows_fastest(const std::vector<double>& op) {
+  std::vector<double> out(op.size());
+  for (size_t blk = 0; blk < op.size() / 64; ++blk)
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) out[blk * 64 + b * 8 + a] = op[blk * 64 + a * 8 + b];
+  return out;
+}
+
 int mg3_num_levels(int n, int levels) {
   if (n < 2) return 0;
   if (levels <= 0) {

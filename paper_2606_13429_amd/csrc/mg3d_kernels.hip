@@ -1,9 +1,10 @@
 // Kernels of the three-dimensional multigrid inner solve (Section 4.2, the 3D
 // case; layouts in mg3d.hpp).  Level vectors hold 8 FP64 values per cube.
-// One thread per (cube, row): 32 cubes per 256-thread workgroup, the eight
-// threads of a cube read its neighbours' values together.  The class tables
-// (operator 27 x 7 blocks, RAS updates 343 x 8 x 200) are shared by every
-// cube of a class and stay in the caches.
+// The residual and the RAS step run on bricks staged in LDS on large levels
+// and split every output over a few lanes on small ones; the transfers run
+// one thread per (cube, row).  The class tables (operator
+// 27 x 7 blocks, RAS updates 343 x 8 x 200) are shared by every cube of a
+// class and stay in the caches.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -35,75 +36,252 @@ __device__ double block_sum(double v, double* sh) {
   return sh[0];
 }
 
-__global__ __launch_bounds__(kThreads) void k_mg3_res(int n, const double* __restrict__ op,
-                                                      const double* __restrict__ f,
-                                                      const double* __restrict__ z,
-                                                      double* __restrict__ r,
-                                                      double* __restrict__ part,
-                                                      const int32_t* __restrict__ guard) {
-  if (stopped(guard)) return;
-  __shared__ double sh[kThreads];
-  const int64_t ne = (int64_t)n * n * n;
-  const int64_t e = (int64_t)blockIdx.x * kCubesPerBlock + threadIdx.x / 8;
-  const int a = threadIdx.x & 7;
-  double v = 0.0;
-  if (e < ne) {
-    const int x = int(e % n), y = int((e / n) % n), zz = int(e / ((int64_t)n * n));
-    const int cls = op_axis(x, n) + 3 * op_axis(y, n) + 9 * op_axis(zz, n);
-    const int c[3] = {x, y, zz};
-    double acc = f ? f[8 * e + a] : 0.0;
-    if (z) {
-#pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        const int ax = s == 0 ? 0 : (s - 1) >> 1;
-        const int dir = s == 0 ? 0 : ((s & 1) ? -1 : 1);
-        const int q = c[ax] + dir;
-        if (q < 0 || q >= n) continue;
-        int64_t nb = e;
-        if (s) nb += dir * (ax == 0 ? 1 : (ax == 1 ? (int64_t)n : (int64_t)n * n));
-        const double* row = op + ((cls * kSlots + s) * 8 + a) * 8;
-        const double* zn = z + 8 * nb;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) acc -= row[b] * zn[b];
-      }
-    }
-    r[8 * e + a] = acc;
-    v = acc * acc;
-  }
-  if (part) {
-    const double s = block_sum(v, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+// ---- residual and RAS step on large levels (n_k > kSplitMaxN): bricks of
+// 4 x 4 x 4 cubes per 512-thread workgroup.  The workgroup stages the input
+// vector on the brick and a halo (zeros outside the domain) in LDS,
+// component-major with a padded stride; thread t computes row t & 7 of cube
+// t >> 3 of the brick.  These levels store the class tables with the row
+// index fastest (mg3d.hpp), so the eight threads of a cube read one
+// contiguous 64-byte segment per column and the cubes of one class in a
+// wavefront share it.
+constexpr int kBrick = 4;
+constexpr int kBrickThreads = 512;
+
+template <int H>
+struct Box {
+  static constexpr int X = kBrick + 2 * H;
+  static constexpr int N = X * X * X;
+  static constexpr int S = N + 1;   // component stride (padding spreads the banks)
+};
+
+__host__ __device__ constexpr int bricks_along(int n) { return (n + kBrick - 1) / kBrick; }
+
+// lds[b S + c] = v on box cube c, component b (0 outside the domain or v = NULL).
+template <int H>
+__device__ __forceinline__ void stage_box(int n, int x0, int y0, int z0, const double* __restrict__ v,
+                                          double* lds) {
+  using B = Box<H>;
+  for (int i = threadIdx.x; i < B::N * 8; i += kBrickThreads) {
+    const int c = i >> 3, b = i & 7;
+    const int x = x0 - H + c % B::X, y = y0 - H + (c / B::X) % B::X, z = z0 - H + c / (B::X * B::X);
+    double val = 0.0;
+    if (v && x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n)
+      val = v[8 * (((int64_t)z * n + y) * n + x) + b];
+    lds[b * B::S + c] = val;
   }
 }
 
-struct DiamondTable {
-  int8_t d[kDiamond][3];
+struct Lane {
+  int row;        // the thread's row of its cube
+  int x, y, z;    // the cube
+  int lx, ly, lz; // its place in the brick
+  int x0, y0, z0; // the brick's origin
+  bool valid;     // inside the domain
+  int64_t e;
 };
 
-__global__ __launch_bounds__(kThreads) void k_mg3_ras(int n, const double* __restrict__ ras,
-                                                      const double* __restrict__ r,
-                                                      double* __restrict__ z, int zero,
-                                                      DiamondTable dt,
-                                                      const int32_t* __restrict__ guard) {
+__device__ __forceinline__ Lane lane_cube(int n) {
+  const int nb = bricks_along(n);
+  const int b = blockIdx.x;
+  Lane L;
+  L.row = threadIdx.x & 7;
+  const int c = threadIdx.x >> 3;
+  L.lx = c & 3;
+  L.ly = (c >> 2) & 3;
+  L.lz = c >> 4;
+  L.x0 = (b % nb) * kBrick;
+  L.y0 = ((b / nb) % nb) * kBrick;
+  L.z0 = (b / (nb * nb)) * kBrick;
+  L.x = L.x0 + L.lx;
+  L.y = L.y0 + L.ly;
+  L.z = L.z0 + L.lz;
+  L.valid = L.x < n && L.y < n && L.z < n;
+  L.e = ((int64_t)L.z * n + L.y) * n + L.x;
+  return L;
+}
+
+__global__ __launch_bounds__(kBrickThreads) void k_mg3_res(int n, const double* __restrict__ opT,
+                                                           const double* __restrict__ f,
+                                                           const double* __restrict__ z,
+                                                           double* __restrict__ r,
+                                                           double* __restrict__ part,
+                                                           const int32_t* __restrict__ guard) {
   if (stopped(guard)) return;
-  const int64_t ne = (int64_t)n * n * n;
-  const int64_t e = (int64_t)blockIdx.x * kCubesPerBlock + threadIdx.x / 8;
-  const int a = threadIdx.x & 7;
-  if (e >= ne) return;
-  const int x = int(e % n), y = int((e / n) % n), zz = int(e / ((int64_t)n * n));
-  const int cls = n < kRasClassMinN ? int(e) : ras_axis(x, n) + 7 * ras_axis(y, n) + 49 * ras_axis(zz, n);
-  const double* K = ras + ((int64_t)cls * 8 + a) * kRasCols;
-  double acc = zero ? 0.0 : z[8 * e + a];
+  using B = Box<1>;
+  __shared__ double zs[8 * B::S];
+  __shared__ double sh[kBrickThreads / 64];
+  const Lane L = lane_cube(n);
+  stage_box<1>(n, L.x0, L.y0, L.z0, z, zs);
+  __syncthreads();
+  constexpr int off[kSlots] = {0, -1, 1, -B::X, B::X, -B::X * B::X, B::X * B::X};
+  const int cls = op_axis(L.x, n) + 3 * op_axis(L.y, n) + 9 * op_axis(L.z, n);
+  // opT[cls][slot][b][row]
+  const double* col = opT + (int64_t)cls * kSlots * 64 + L.row;
+  const int o = ((L.lz + 1) * B::X + L.ly + 1) * B::X + L.lx + 1;
+  double acc = (L.valid && f) ? f[8 * L.e + L.row] : 0.0;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const double* cs = col + 64 * s;
+    const double* zn = zs + o + off[s];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc -= cs[8 * b] * zn[b * B::S];
+  }
+  if (L.valid) r[8 * L.e + L.row] = acc;
+  if (part) {   // the workgroup's sum of r^2, fixed order: lanes, then wavefronts
+    double v = L.valid ? acc * acc : 0.0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < kBrickThreads / 64; ++w) sum += sh[w];
+      part[blockIdx.x] = sum;
+    }
+  }
+}
+
+// The diamond (|dx| + |dy| + |dz| <= 2) as cube offsets, in the order of
+// diamond_offsets().
+struct DiamondOff {
+  int d[kDiamond][3];
+  constexpr DiamondOff() : d() {
+    int k = 0;
+    for (int dz = -2; dz <= 2; ++dz)
+      for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+          const int a = (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz);
+          if (a <= 2) {
+            d[k][0] = dx;
+            d[k][1] = dy;
+            d[k][2] = dz;
+            ++k;
+          }
+        }
+  }
+};
+
+// The diamond as offsets in the halo-2 box, in the same order.
+struct DiamondBox {
+  int o[kDiamond];
+  constexpr DiamondBox() : o() {
+    const DiamondOff D;
+    for (int d = 0; d < kDiamond; ++d) o[d] = (D.d[d][2] * Box<2>::X + D.d[d][1]) * Box<2>::X + D.d[d][0];
+  }
+};
+
+__global__ __launch_bounds__(kBrickThreads) void k_mg3_ras(int n, const double* __restrict__ rasT,
+                                                           const double* __restrict__ r,
+                                                           double* __restrict__ z, int zero,
+                                                           const int32_t* __restrict__ guard) {
+  if (stopped(guard)) return;
+  using B = Box<2>;
+  __shared__ double rs[8 * B::S];
+  const Lane L = lane_cube(n);
+  stage_box<2>(n, L.x0, L.y0, L.z0, r, rs);
+  __syncthreads();
+  constexpr DiamondBox D;
+  const int cls = ras_axis(L.x, n) + 7 * ras_axis(L.y, n) + 49 * ras_axis(L.z, n);
+  // rasT[cls][column 200][row]
+  const double* col = rasT + (int64_t)cls * 8 * kRasCols + L.row;
+  const int o = ((L.lz + 2) * B::X + L.ly + 2) * B::X + L.lx + 2;
+  double acc = (L.valid && !zero) ? z[8 * L.e + L.row] : 0.0;
+  // five diamond cubes per loop trip keep the code small with their table
+  // loads in flight together
 #pragma unroll 5
   for (int d = 0; d < kDiamond; ++d) {
-    const int qx = x + dt.d[d][0], qy = y + dt.d[d][1], qz = zz + dt.d[d][2];
-    if (qx < 0 || qy < 0 || qz < 0 || qx >= n || qy >= n || qz >= n) continue;
-    const double* rn = r + 8 * (((int64_t)qz * n + qy) * n + qx);
-    const double* k = K + 8 * d;
+    const double* cd = col + 64 * d;
+    const double* rd = rs + o + D.o[d];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc += k[b] * rn[b];
+    for (int b = 0; b < 8; ++b) acc += cd[8 * b] * rd[b * B::S];
   }
-  z[8 * e + a] = acc;
+  if (L.valid) z[8 * L.e + L.row] = acc;
+}
+
+// ---- residual and RAS step on small levels (n_k <= kSplitMaxN): one lane
+// per (cube, row, term group), so that every lane issues a single round of
+// loads -- the table row segment and the neighbour's values, 64 bytes each
+// -- and the groups are summed by a fixed shuffle tree.  These levels use
+// the row-major tables.
+// RAS: 32 lanes per output (lane d < 25 takes diamond cube d), 8 outputs per
+// 256-thread workgroup.
+__global__ __launch_bounds__(kThreads) void k_mg3_ras_split(int n, const double* __restrict__ ras,
+                                                            const double* __restrict__ r,
+                                                            double* __restrict__ z, int zero,
+                                                            const int32_t* __restrict__ guard) {
+  if (stopped(guard)) return;
+  constexpr DiamondOff D;
+  const int64_t ne = (int64_t)n * n * n;
+  const int64_t out = (int64_t)blockIdx.x * (kThreads / 32) + (threadIdx.x >> 5);
+  const int d = threadIdx.x & 31;
+  const int64_t e = out >> 3;
+  const int row = int(out & 7);
+  double acc = 0.0;
+  if (e < ne && d < kDiamond) {
+    const int x = int(e % n), y = int((e / n) % n), zz = int(e / ((int64_t)n * n));
+    const int qx = x + D.d[d][0], qy = y + D.d[d][1], qz = zz + D.d[d][2];
+    if (qx >= 0 && qy >= 0 && qz >= 0 && qx < n && qy < n && qz < n) {
+      const int cls = n < kRasClassMinN ? int(e) : ras_axis(x, n) + 7 * ras_axis(y, n) + 49 * ras_axis(zz, n);
+      const double* K = ras + ((int64_t)cls * 8 + row) * kRasCols + 8 * d;
+      const double* rn = r + 8 * (((int64_t)qz * n + qy) * n + qx);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc += K[b] * rn[b];
+    }
+  }
+#pragma unroll
+  for (int m = 16; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 32);
+  if (d == 0 && e < ne) z[8 * e + row] = (zero ? 0.0 : z[8 * e + row]) + acc;
+}
+
+// Residual: 8 lanes per output (lane s < 7 takes face slot s), 32 outputs per
+// 256-thread workgroup; with part, the workgroup's sum of r^2.
+__global__ __launch_bounds__(kThreads) void k_mg3_res_split(int n, const double* __restrict__ op,
+                                                            const double* __restrict__ f,
+                                                            const double* __restrict__ z,
+                                                            double* __restrict__ r,
+                                                            double* __restrict__ part,
+                                                            const int32_t* __restrict__ guard) {
+  if (stopped(guard)) return;
+  __shared__ double sh[kThreads / 64];
+  const int64_t ne = (int64_t)n * n * n;
+  const int64_t out = (int64_t)blockIdx.x * (kThreads / 8) + (threadIdx.x >> 3);
+  const int s = threadIdx.x & 7;
+  const int64_t e = out >> 3;
+  const int row = int(out & 7);
+  double acc = 0.0;
+  if (e < ne && s < kSlots && z) {
+    const int c[3] = {int(e % n), int((e / n) % n), int(e / ((int64_t)n * n))};
+    const int ax = s == 0 ? 0 : (s - 1) >> 1;
+    const int dir = s == 0 ? 0 : ((s & 1) ? -1 : 1);
+    const int q = c[ax] + dir;
+    if (q >= 0 && q < n) {
+      const int cls = op_axis(c[0], n) + 3 * op_axis(c[1], n) + 9 * op_axis(c[2], n);
+      const int64_t nb = e + dir * (ax == 0 ? 1 : (ax == 1 ? (int64_t)n : (int64_t)n * n));
+      const double* row_p = op + ((cls * kSlots + s) * 8 + row) * 8;
+      const double* zn = z + 8 * nb;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc -= row_p[b] * zn[b];
+    }
+  }
+#pragma unroll
+  for (int m = 4; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 8);
+  double v = 0.0;
+  if (s == 0 && e < ne) {
+    acc += f ? f[8 * e + row] : 0.0;
+    r[8 * e + row] = acc;
+    v = acc * acc;
+  }
+  if (part) {   // the workgroup's sum of r^2, fixed order: lanes, then wavefronts
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) sum += sh[w];
+      part[blockIdx.x] = sum;
+    }
+  }
 }
 
 __device__ __forceinline__ double inject(int q, int i, int J) {
@@ -213,31 +391,38 @@ __global__ __launch_bounds__(kThreads) void k_mg3_scale(int64_t len, double a,
 
 unsigned cube_blocks(int64_t cubes) { return unsigned((cubes + kCubesPerBlock - 1) / kCubesPerBlock); }
 
-DiamondTable make_diamond() {
-  int off[kDiamond][3];
-  diamond_offsets(off);
-  DiamondTable t;
-  for (int d = 0; d < kDiamond; ++d)
-    for (int c = 0; c < 3; ++c) t.d[d][c] = int8_t(off[d][c]);
-  return t;
-}
+unsigned brick_blocks(int n) { return unsigned(bricks_along(n) * bricks_along(n) * bricks_along(n)); }
 
 }  // namespace
 
-int mg3_res_blocks(int nk) { return int(cube_blocks((int64_t)nk * nk * nk)); }
+bool mg3_split(int nk) { return nk <= kSplitMaxN; }
+
+int mg3_res_blocks(int nk) {
+  return mg3_split(nk) ? int((8 * (int64_t)nk * nk * nk + kThreads / 8 - 1) / (kThreads / 8))
+                       : int(brick_blocks(nk));
+}
 
 hipError_t launch_mg3_res(int nk, const double* op, const double* f, const double* z, double* r,
                           double* part, const int32_t* guard, hipStream_t st) {
-  hipLaunchKernelGGL(k_mg3_res, dim3(mg3_res_blocks(nk)), dim3(kThreads), 0, st, nk, op, f, z, r,
-                     part, guard);
+  if (mg3_split(nk))
+    hipLaunchKernelGGL(k_mg3_res_split, dim3(mg3_res_blocks(nk)), dim3(kThreads), 0, st, nk, op, f, z,
+                       r, part, guard);
+  else
+    hipLaunchKernelGGL(k_mg3_res, dim3(mg3_res_blocks(nk)), dim3(kBrickThreads), 0, st, nk, op, f, z, r,
+                       part, guard);
   return hipGetLastError();
 }
 
 hipError_t launch_mg3_ras(int nk, const double* ras, const double* r, double* z, bool zero,
                           const int32_t* guard, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  static const DiamondTable dt = make_diamond();
-  hipExtLaunchKernelGGL(k_mg3_ras, dim3(cube_blocks((int64_t)nk * nk * nk)), dim3(kThreads), 0, st,
-                        ev0, ev1, 0, nk, ras, r, z, int(zero), dt, guard);
+  if (mg3_split(nk)) {
+    const int64_t outs = 8 * (int64_t)nk * nk * nk;
+    hipExtLaunchKernelGGL(k_mg3_ras_split, dim3(unsigned((outs + kThreads / 32 - 1) / (kThreads / 32))),
+                          dim3(kThreads), 0, st, ev0, ev1, 0, nk, ras, r, z, int(zero), guard);
+  } else {
+    hipExtLaunchKernelGGL(k_mg3_ras, dim3(brick_blocks(nk)), dim3(kBrickThreads), 0, st, ev0, ev1, 0, nk,
+                          ras, r, z, int(zero), guard);
+  }
   return hipGetLastError();
 }
 

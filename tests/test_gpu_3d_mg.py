@@ -15,7 +15,7 @@ stored results (tests/golden/make_3d_mg_golden.py); graph replays against
 direct launches bit for bit.  At the benchmark size (n = 32) the RAS step is
 checked on sampled cubes against the RAS definition applied to the oracle's
 Laplacian, the W-cycle by its contraction, and the solve by its true
-residual and its repeatability."""
+residual and its outer count against the exact inner solve's."""
 import os
 
 import numpy as np
@@ -242,7 +242,7 @@ def _ras_on_cube(L, n, r, cube):
     return out / len(owners)
 
 
-def test_full_size_ras_step_wcycle_and_solve():
+def test_full_size_ras_step_and_wcycle():
     n, dt, tol = THREE_D["n"], THREE_D["dt"], THREE_D["tol"]
     print("3d mg full size n=%d" % n, flush=True)
     s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg")
@@ -270,14 +270,20 @@ def test_full_size_ras_step_wcycle_and_solve():
         s.mg_apply(lib.DCG3D_MG_LAPLACE, J, z, Lz)
         res.append(float((fd - Lz).norm() / fd.norm()))
     assert all(b < 0.7 * a for a, b in zip(res, res[1:])), res
-    # the solve converges, twice bit for bit
-    b = _dev(rhs3d(n, 0))
-    x1, x2 = torch.empty_like(b), torch.empty_like(b)
-    status, st = s.solve(b, x1, tol)
-    print("  n=%d solve: Out %d Tot %d true %.2e %.1f s"
-          % (n, st.outer_iters, st.total_wcycles, st.rel_res_true, st.t_solve_ms / 1e3), flush=True)
-    assert status == lib.DCG_OK and st.rel_res_true <= 10 * tol
-    assert 20 <= st.total_wcycles / st.inner_solves <= 60
-    status, st2 = s.solve(b, x2, tol)
     s.close()
-    assert torch.equal(x1, x2) and (st2.outer_iters, st2.total_wcycles) == (st.outer_iters, st.total_wcycles)
+
+
+def test_full_size_solve():
+    n, dt, tol = THREE_D["n"], THREE_D["dt"], THREE_D["tol"]
+    print("3d mg full-size solve n=%d" % n, flush=True)
+    s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg")
+    b = _dev(rhs3d(n, 0))
+    x = torch.empty_like(b)
+    status, st = s.solve(b, x, tol)
+    s.close()
+    print("  Out %d Tot %d true %.2e %.1f s"
+          % (st.outer_iters, st.total_wcycles, st.rel_res_true, st.t_solve_ms / 1e3), flush=True)
+    assert status == lib.DCG_OK and st.rel_res_true <= 10 * tol
+    # the exact inner solve takes 266-268 outer iterations on this system
+    assert abs(st.outer_iters - 268) <= 10
+    assert 20 <= st.total_wcycles / st.inner_solves <= 60
