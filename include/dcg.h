@@ -135,6 +135,18 @@ typedef struct {
                           smoothing RAS steps per level visit of the W-cycle
                           (the 3D runs of Section 4.2 use m = 10).  Ignored
                           elsewhere. [10]                                    */
+  int32_t outer_mg;    /* DCG_OUTER_FCG, dcg_solve / dcg_apply only: > 0
+                          preconditions the flexible outer iteration with B =
+                          one W-cycle (Algorithm 4, outer_mg pre- and post-
+                          smoothing RAS steps, gamma = 2) on the Galerkin
+                          hierarchy of A* itself down to 8 x 8 squares, RAS
+                          blocks of a square and its edge neighbours over all
+                          four stress components, the coarsest level solved
+                          by a dense FP64 inverse; the direction of Algorithm
+                          1 is built from B r_i (the multigrid outer
+                          preconditioner the paper's conclusions leave to
+                          future work).  FP64, built per handle (A* depends
+                          on dt).  0 = off. [0]                              */
 } dcg_options;
 
 /* Inner solver of dcg_solve.  DCG_INNER_MG is the paper's method: the
@@ -232,7 +244,19 @@ typedef enum {
   DCG_OP_ASTAR = 0, DCG_OP_ZT = 1, DCG_OP_Z = 2, DCG_OP_ADIVZ = 3,
   DCG_OP_DEFLATED = 4, DCG_OP_INNER = 5, DCG_OP_LAPLACE = 6, DCG_OP_RAS = 7,
   DCG_OP_RESTRICT = 8, DCG_OP_PROLONG = 9, DCG_OP_COARSE = 10, DCG_OP_WCYCLE = 11,
-  DCG_OP_RAS_BATCH = 12, DCG_OP_WCYCLE_BATCH = 13
+  DCG_OP_RAS_BATCH = 12, DCG_OP_WCYCLE_BATCH = 13,
+  /* the outer multigrid preconditioner (opt.outer_mg > 0), FP64 tensor level
+   * vectors of 16 n_k^2 values in the element-major layout, levels k = 1
+   * (8 x 8 squares) .. J = log2(n/8) + 1:
+   *  DCG_OP_OMG_APPLY    r (J)       -          z (J)       B r, one W-cycle from zero
+   *  DCG_OP_OMG_LEVEL    z (k)       -          v (k)       A*_k z (A*_J = A*)
+   *  DCG_OP_OMG_RAS      f (k)       z or NULL  z' (k)      z + S_k (f - A*_k z), k >= 2
+   *  DCG_OP_OMG_RESTRICT r (k)       -          rc (k - 1)  P_k^T r, k >= 2
+   *  DCG_OP_OMG_PROLONG  e (k - 1)   -          v (k)       P_k e, k >= 2
+   *  DCG_OP_OMG_COARSE   f (1)       -          z (1)       (A*_1)^{-1} f
+   *  DCG_OP_OMG_WCYCLE   f (k)       z0 or NULL z (k)       Wcycle_k(f, z0) */
+  DCG_OP_OMG_APPLY = 14, DCG_OP_OMG_LEVEL = 15, DCG_OP_OMG_RAS = 16, DCG_OP_OMG_RESTRICT = 17,
+  DCG_OP_OMG_PROLONG = 18, DCG_OP_OMG_COARSE = 19, DCG_OP_OMG_WCYCLE = 20
 } dcg_op;
 
 dcg_status dcg_apply(dcg_handle h, dcg_op op, int32_t level, const void* in,
@@ -284,6 +308,24 @@ int32_t dcg_num_levels(int32_t n);
 dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
                              double* dst, int64_t dst_len, int32_t* cols,
                              int64_t cols_len, int64_t* needed);
+
+/* Host only (no device call): the class tables of the outer multigrid
+ * preconditioner (opt.outer_mg) for n = 16 2^k <= 64, penalty, dt, nu, on
+ * level `level` (1 = 8 x 8 squares .. J = log2(n/8) + 1), into the HOST
+ * buffer dst of dst_len doubles.  On the uniform grid a square's rows of A*_k
+ * depend only on the domain sides it touches and its RAS update only on its
+ * distance 0, 1, 2 or >= 3 from each side.  which = 0: the operator table
+ * [9][5][16][16], entry (cls, slot, a, b) = A*_k(row a of a square of class
+ * cls = cx + 3 cy -- c_axis 0 at the low side, 2 at the high side, 1 inside --
+ * column b of its slot neighbour: 0 itself, 1/2 x-1/x+1, 3/4 y-1/y+1), rows
+ * and columns 4 c + j (element-major); 1 (level >= 2): the RAS update table
+ * [49][16][208], (S_k r) on a square of class px + 7 py (p = x for x < 3,
+ * 6 - (n_k - 1 - x) for n_k - 1 - x < 3, else 3) equals table[cls] times r on
+ * the 13 squares (dx, dy) with |dx| + |dy| <= 2 (by dy, then dx; column
+ * 16 d + b); 2 (level 1): the inverse of A*_1, [1024][1024] row-major.
+ * DCG_EINVAL for bad arguments or a short buffer. */
+dcg_status dcg_host_outer_mg(int32_t n, double penalty, double dt, double nu, int32_t level,
+                             int32_t which, double* dst, int64_t dst_len);
 
 /* BDF2 time stepping (Section 2.3, implicit multistep family; BDF2 reading):
  * for M d(sigma)/dt + A sigma = F the step n solves (M + alpha A) sigma^n = f

@@ -80,7 +80,7 @@ class Solver:
 
     def __init__(self, n, dt, nu=1.0, prec="mixed", outer="cg", penalty=10.0, pre=2, post=2,
                  c_F=0.01, max_outer=50000, max_inner=100, x0_given=False, use_graph=True,
-                 c_A=0.0, m_max=8, inner="mg", levels=0, restarts=0, ras_group=0):
+                 c_A=0.0, m_max=8, inner="mg", levels=0, restarts=0, ras_group=0, outer_mg=0):
         """outer: "cg", "fcg1", "fcg" (truncated FCG with m_max, FCG(inf) for
         m_max = 0) or "gmres"; c_A > 0 selects the adaptive inner tolerance of
         eq. (tol); inner="exact" solves the inner system exactly by fast
@@ -91,7 +91,8 @@ class Solver:
         reruns Algorithm 2 from the returned x while its true residual misses
         tol (at most that many times); ras_group selects the RAS step kernel
         (0 automatic, 1 / 2 / 4 grouped MFMA tiles, -1 one tile per wavefront
-        group)."""
+        group); outer_mg = m > 0 (with outer="fcg") preconditions the outer
+        iteration with one W-cycle on A* with m smoothing steps."""
         mesh, opt = dcg_defaults()
         mesh.n, mesh.penalty, mesh.pre, mesh.post = n, penalty, pre, post
         opt.prec = {"mixed": DCG_MIXED, "fp64": DCG_FP64}[prec]
@@ -101,6 +102,7 @@ class Solver:
         opt.inner = {"mg": DCG_INNER_MG, "exact": DCG_INNER_EXACT, "none": DCG_INNER_NONE}[inner]
         opt.x0_given, opt.use_graph = int(x0_given), int(use_graph)
         opt.levels, opt.restarts, opt.ras_group = levels, restarts, ras_group
+        opt.outer_mg = outer_mg
         self.n, self.dt, self.nu, self.mesh, self.opt = n, dt, nu, mesh, opt
         self.handle = dcg_setup(mesh, dt, nu, opt)
 

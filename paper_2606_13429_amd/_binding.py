@@ -25,7 +25,8 @@ DCG_OUTER_CG, DCG_OUTER_FCG1, DCG_OUTER_FCG, DCG_OUTER_GMRES = 0, 1, 2, 3
 DCG_INNER_MG, DCG_INNER_EXACT, DCG_INNER_NONE = 0, 1, 2
 (DCG_OP_ASTAR, DCG_OP_ZT, DCG_OP_Z, DCG_OP_ADIVZ, DCG_OP_DEFLATED, DCG_OP_INNER, DCG_OP_LAPLACE,
  DCG_OP_RAS, DCG_OP_RESTRICT, DCG_OP_PROLONG, DCG_OP_COARSE, DCG_OP_WCYCLE, DCG_OP_RAS_BATCH,
- DCG_OP_WCYCLE_BATCH) = range(14)
+ DCG_OP_WCYCLE_BATCH, DCG_OP_OMG_APPLY, DCG_OP_OMG_LEVEL, DCG_OP_OMG_RAS, DCG_OP_OMG_RESTRICT,
+ DCG_OP_OMG_PROLONG, DCG_OP_OMG_COARSE, DCG_OP_OMG_WCYCLE) = range(21)
 BATCH = 16   # vectors of the _BATCH operators and requests per serving batch
 (DCG3D_OP_ASTAR, DCG3D_OP_ZT, DCG3D_OP_Z, DCG3D_OP_DEFLATED, DCG3D_OP_REDUCED, DCG3D_OP_INNER,
  DCG3D_OP_ADIVZ) = range(7)
@@ -47,7 +48,8 @@ class dcg_options(ctypes.Structure):
                 ("hbm_budget_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int32),
                 ("c_A", ctypes.c_double), ("m_max", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("ras_group", ctypes.c_int32), ("smooth3d", ctypes.c_int32)]
+                ("ras_group", ctypes.c_int32), ("smooth3d", ctypes.c_int32),
+                ("outer_mg", ctypes.c_int32)]
 
 
 class dcg_stats(ctypes.Structure):
@@ -103,6 +105,8 @@ _SIGS = {
     "dcg3d_host_blocks": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                          _P(ctypes.c_double)]),
     "dcg3d_mg_apply": (ctypes.c_int, [_h, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
+    "dcg_host_outer_mg": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int64]),
     "dcg3d_mg_levels": (ctypes.c_int, [_h, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     "dcg3d_host_mg": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, _P(ctypes.c_double)]),
@@ -201,6 +205,18 @@ def dcg_apply_noalloc(handle, op, inp, out, stream=None):
 
 def dcg_noalloc_bytes():
     return _lib.dcg_noalloc_bytes()
+
+
+def dcg_host_outer_mg(n, penalty, dt, nu, level, which):
+    """Host copy of a class table of the outer multigrid (no device call):
+    which 0 the operator table (9, 5, 16, 16), 1 the RAS update table
+    (49, 16, 208), 2 the coarsest inverse (1024, 1024)."""
+    import numpy as np
+    shape = {0: (9, 5, 16, 16), 1: (49, 16, 208), 2: (1024, 1024)}[which]
+    out = np.empty(shape, dtype=np.float64)
+    _check(_lib.dcg_host_outer_mg(n, penalty, dt, nu, level, which, out.ctypes.data_as(_P(ctypes.c_double)),
+                                  out.size))
+    return out
 
 
 def dcg_host_assemble(mesh, which, level=0):

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("DCG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "mg_kernels.hip", "mg_batch.hip", "host_setup.cpp", "context.cpp", "solver.cpp", "server.cpp", "capi.cpp", "dcg3d_kernels.hip", "dcg3d.cpp", "mg3d_host.cpp", "mg3d_kernels.hip", "fdm_host.cpp", "fdm_kernels.hip"]
+SOURCES = ["kernels.hip", "mg_kernels.hip", "mg_batch.hip", "host_setup.cpp", "context.cpp", "solver.cpp", "server.cpp", "capi.cpp", "dcg3d_kernels.hip", "dcg3d.cpp", "mg3d_host.cpp", "mg3d_kernels.hip", "omg_host.cpp", "omg_kernels.hip", "omg_driver.cpp", "fdm_host.cpp", "fdm_kernels.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I" + os.path.join(HERE, "..", "include")]

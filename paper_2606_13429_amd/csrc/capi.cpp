@@ -7,6 +7,7 @@
 #include <string>
 
 #include "fdm_host.hpp"
+#include "omg.hpp"
 #include "server.hpp"
 
 namespace {
@@ -64,6 +65,9 @@ dcg_status check_options(const dcg_options& o) {
   if (o.ras_group != 0 && o.ras_group != -1 && o.ras_group != 1 && o.ras_group != 2 &&
       o.ras_group != 4)
     return fail(nullptr, DCG_EINVAL, "ras_group must be 0, -1, 1, 2 or 4");
+  if (o.outer_mg < 0) return fail(nullptr, DCG_EINVAL, "outer_mg must be >= 0");
+  if (o.outer_mg > 0 && o.outer != DCG_OUTER_FCG)
+    return fail(nullptr, DCG_EINVAL, "outer_mg needs the flexible outer iteration (DCG_OUTER_FCG)");
   return DCG_OK;
 }
 
@@ -127,6 +131,7 @@ dcg_status dcg_setup(const dcg_mesh* mesh, double dt, double nu, const dcg_optio
     h->fp32 = o.prec == DCG_MIXED;
     h->mesh = dcg::get_context(mesh->n, mesh->penalty, h->fp32);
     dcg::handle_init(h);
+    if (o.outer_mg > 0) dcg::omg_setup(h);
     h->t_setup_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return DCG_OK;
@@ -174,6 +179,26 @@ dcg_status dcg_apply_noalloc(dcg_handle h, dcg_op op, const double* in, double* 
 }
 
 int64_t dcg_noalloc_bytes(void) { return int64_t(dcg::noalloc_capacity()); }
+
+dcg_status dcg_host_outer_mg(int32_t n, double penalty, double dt, double nu, int32_t level,
+                             int32_t which, double* dst, int64_t dst_len) {
+  if (!dst) return fail(nullptr, DCG_EINVAL, "dst is NULL");
+  const int J = dcg::omg_num_levels(n);
+  if (J < 2 || n > 64) return fail(nullptr, DCG_EINVAL, "n must be 16 2^k <= 64");
+  if (!(penalty > 0.0) || !(dt > 0.0) || !(nu > 0.0))
+    return fail(nullptr, DCG_EINVAL, "penalty, dt and nu must be positive");
+  if (level < 1 || level > J) return fail(nullptr, DCG_EINVAL, "level out of range");
+  if (which < 0 || which > 2 || (which == 1 && level < 2) || (which == 2 && level != 1))
+    return fail(nullptr, DCG_EINVAL, "which must be 0, 1 (level >= 2) or 2 (level 1)");
+  return guarded(nullptr, [&]() -> dcg_status {
+    const dcg::OmgHierarchy H = dcg::build_omg(n, penalty, dt, nu);
+    const std::vector<double>& src =
+        which == 0 ? H.lev[level - 1].op : (which == 1 ? H.lev[level - 1].ras : H.coarse_inv);
+    if (dst_len < (int64_t)src.size()) return fail(nullptr, DCG_EINVAL, "dst too small");
+    std::copy(src.begin(), src.end(), dst);
+    return DCG_OK;
+  });
+}
 
 dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level, double* dst,
                              int64_t dst_len, int32_t* cols, int64_t cols_len, int64_t* needed) {
@@ -304,6 +329,7 @@ dcg_status dcg_server_create(const dcg_options* opt, dcg_server* out) {
   dcg_defaults(nullptr, &o);
   if (opt) o = *opt;
   if (const dcg_status cs = check_options(o); cs != DCG_OK) return cs;
+  if (o.outer_mg > 0) return fail(nullptr, DCG_EINVAL, "the server runs no outer multigrid (outer_mg = 0)");
   if (o.max_pending < 1) return fail(nullptr, DCG_EINVAL, "max_pending must be >= 1");
   if (o.outer == DCG_OUTER_FCG || o.outer == DCG_OUTER_GMRES)
     return fail(nullptr, DCG_EINVAL, "the server runs DCG_OUTER_CG or DCG_OUTER_FCG1");

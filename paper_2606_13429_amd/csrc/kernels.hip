@@ -391,8 +391,8 @@ __global__ __launch_bounds__(kThreads) void k_fcg_coef(const double* __restrict_
 // d may alias r (in-place Gram-Schmidt update): element i is read before it is
 // written by the same thread.
 __global__ __launch_bounds__(kThreads) void k_fcg_direction(
-    int64_t n, const double* r, const double* const* __restrict__ dptr, int first, int m, int R,
-    const double* __restrict__ coef, double* d, double* __restrict__ part) {
+    int64_t n, const double* r, const double* rdot, const double* const* __restrict__ dptr, int first,
+    int m, int R, const double* __restrict__ coef, double* d, double* __restrict__ part) {
   __shared__ double lds[4];
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kThreads) void k_fcg_direction(
     double di = ri;
     for (int k = 0; k < m; ++k) di += coef[k] * dptr[(first + k) % R][i];
     d[i] = di;
-    acc += di * ri;
+    acc += di * (rdot ? rdot[i] : ri);
   }
   const double t = block_sum(acc, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -715,12 +715,12 @@ hipError_t launch_fcg_coef(int64_t n, const double* r, const double* const* qptr
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_direction(int64_t n, const double* r, const double* const* dptr, int first,
+hipError_t launch_fcg_direction(int64_t n, const double* r, const double* rdot, const double* const* dptr, int first,
                                 int m, int R, const double* coef, double* d, double* part,
                                 int* nblocks, hipStream_t st) {
   const int grid = grid_for(n, kThreads * 4, 8192);
   *nblocks = grid;
-  k_fcg_direction<<<grid, kThreads, 0, st>>>(n, r, dptr, first, m, R, coef, d, part);
+  k_fcg_direction<<<grid, kThreads, 0, st>>>(n, r, rdot, dptr, first, m, R, coef, d, part);
   return hipGetLastError();
 }
 

@@ -152,11 +152,13 @@ hipError_t launch_bdf2_rhs(int ne, const double* M1, double inv_nu, const double
 //                         nullptr (the Gram-Schmidt coefficients of GMRES) (partials in part, then a
 //                         fixed-order reduction per k; ``part`` holds m x
 //                         fcg_coef_blocks(n) doubles)
-//   launch_fcg_direction: d = r + sum_k coef[k] d_k (k ascending), partial (d, r)
+//   launch_fcg_direction: d = r + sum_k coef[k] d_k (k ascending), partial (d, rdot)
+//                         with rdot = r when NULL (the preconditioned FCG builds d
+//                         from z = B r and takes (d, r))
 int fcg_coef_blocks(int64_t n);
 hipError_t launch_fcg_coef(int64_t n, const double* r, const double* const* qptr, const double* dq,
                            int first, int m, int R, double* part, double* coef, hipStream_t st);
-hipError_t launch_fcg_direction(int64_t n, const double* r, const double* const* dptr, int first,
+hipError_t launch_fcg_direction(int64_t n, const double* r, const double* rdot, const double* const* dptr, int first,
                                 int m, int R, const double* coef, double* d, double* part,
                                 int* nblocks, hipStream_t st);
 

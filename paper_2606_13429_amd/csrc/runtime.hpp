@@ -150,6 +150,23 @@ struct Workspace {
 }  // namespace dcg
 
 // Solver handle (the opaque dcg_handle of the C ABI).
+namespace dcg {
+// The outer multigrid preconditioner of a handle (omg.hpp, omg_driver.cpp):
+// the A* hierarchy (level k at index k - 1; device arrays in the handle's
+// workspace) and the graph of B(r) with the pointers it was captured for.
+struct OuterMg {
+  int J = 0, m = 2;
+  std::vector<int> n;
+  std::vector<double*> op, ras, f, z, r;
+  double* cinv = nullptr;
+  double* zp = nullptr;            // B r of the current outer iteration (16 n^2)
+  hipGraphExec_t graph = nullptr;
+  const double* g_in = nullptr;
+  double* g_out = nullptr;
+  ~OuterMg();
+};
+}  // namespace dcg
+
 struct dcg_ctx {
   std::shared_ptr<dcg::MeshContext> mesh;
   dcg_mesh mp{};
@@ -193,6 +210,8 @@ struct dcg_ctx {
   // level-buffer view of dcg_apply_noalloc (pointers into the static scratch
   // array; the tables are sized at setup so that the call allocates nothing)
   dcg::LevelBuffers noalloc_lvb;
+  // outer multigrid preconditioner (opt.outer_mg > 0)
+  std::unique_ptr<dcg::OuterMg> omg;
   ~dcg_ctx();
 };
 
@@ -207,4 +226,10 @@ dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* i
 // array (no device allocation); noalloc_capacity() is its size in bytes.
 dcg_status apply_noalloc(dcg_ctx* h, dcg_op op, const double* in, double* out, hipStream_t stream);
 size_t noalloc_capacity();
+// The outer multigrid preconditioner: set-up (after handle_init), z = B r on
+// the stream, and its level operators (DCG_OP_OMG_*).
+void omg_setup(dcg_ctx* h);
+void omg_apply(dcg_ctx* h, const double* r, double* z, hipStream_t st);
+void omg_apply_level(dcg_ctx* h, dcg_op op, int k, const double* in, const double* in2, double* out,
+                     hipStream_t st);
 }  // namespace dcg

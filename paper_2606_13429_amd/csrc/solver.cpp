@@ -87,6 +87,7 @@ dcg_ctx::~dcg_ctx() {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t& e : aev)
     if (e) (void)hipEventDestroy(e);
+  omg.reset();
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   ws.release();
   (void)hipSetDevice(cur);
@@ -407,9 +408,15 @@ dcg_status outer_fcg(dcg_ctx* h, double lim, double& rho, int& it, int& cycles_t
     const int slot = i % R;
     store_slot(fs, slot, N, true);
     const int first = ((i - mi) % R + R) % R;
-    DCG_HIP(launch_fcg_coef(N, ws.r, fs.qptr, fs.dq, first, mi, R, fs.part, fs.coef, st));
+    // with the outer multigrid the direction is built from z_i = B r_i
+    const double* base = ws.r;
+    if (h->omg) {
+      omg_apply(h, ws.r, h->omg->zp, st);
+      base = h->omg->zp;
+    }
+    DCG_HIP(launch_fcg_coef(N, base, fs.qptr, fs.dq, first, mi, R, fs.part, fs.coef, st));
     int nbd = 0;
-    DCG_HIP(launch_fcg_direction(N, ws.r, fs.dptr, first, mi, R, fs.coef, fs.d[slot], ws.part,
+    DCG_HIP(launch_fcg_direction(N, base, ws.r, fs.dptr, first, mi, R, fs.coef, fs.d[slot], ws.part,
                                  &nbd, st));
     DCG_HIP(launch_reduce(ws.part, nbd, kRedDr, ws.sc, st));
     DCG_HIP(launch_astar(kAstarPlain, m.Cdiv, m.cols, m.M1, ne, fs.d[slot], nullptr, nullptr,
@@ -483,9 +490,9 @@ dcg_status outer_gmres(dcg_ctx* h, double lim, double& rho, int& it, int& cycles
     // two Gram-Schmidt passes in place on q, then ||q||^2
     int nbd = 0;
     DCG_HIP(launch_fcg_coef(N, ws.q, fs.dptr, nullptr, 0, j + 1, R, fs.part, fs.coef, st));
-    DCG_HIP(launch_fcg_direction(N, ws.q, fs.dptr, 0, j + 1, R, fs.coef, ws.q, ws.part, &nbd, st));
+    DCG_HIP(launch_fcg_direction(N, ws.q, nullptr, fs.dptr, 0, j + 1, R, fs.coef, ws.q, ws.part, &nbd, st));
     DCG_HIP(launch_fcg_coef(N, ws.q, fs.dptr, nullptr, 0, j + 1, R, fs.part, fs.coef2, st));
-    DCG_HIP(launch_fcg_direction(N, ws.q, fs.dptr, 0, j + 1, R, fs.coef2, ws.q, ws.part, &nbd, st));
+    DCG_HIP(launch_fcg_direction(N, ws.q, nullptr, fs.dptr, 0, j + 1, R, fs.coef2, ws.q, ws.part, &nbd, st));
     int nbu = 0;
     DCG_HIP(launch_axpy_dot(N, 0.0, ws.q, ws.q, ws.part, &nbu, st));
     DCG_HIP(launch_reduce(ws.part, nbu, kRedRho, ws.sc, st));
@@ -531,7 +538,7 @@ dcg_status outer_gmres(dcg_ctx* h, double lim, double& rho, int& it, int& cycles
     }
     DCG_HIP(hipMemcpy(fs.coef, y.data(), sizeof(double) * k, hipMemcpyHostToDevice));
     int nbd = 0;
-    DCG_HIP(launch_fcg_direction(N, ws.xh, fs.dptr, 0, k, R, fs.coef, ws.xh, ws.part, &nbd, st));
+    DCG_HIP(launch_fcg_direction(N, ws.xh, nullptr, fs.dptr, 0, k, R, fs.coef, ws.xh, ws.part, &nbd, st));
   }
   return status;
 }
@@ -848,6 +855,15 @@ dcg_status apply(dcg_ctx* h, dcg_op op, int level, const void* in, const void* i
                              h->ws.part, st));
       break;
     }
+    case DCG_OP_OMG_APPLY:
+    case DCG_OP_OMG_LEVEL:
+    case DCG_OP_OMG_RAS:
+    case DCG_OP_OMG_RESTRICT:
+    case DCG_OP_OMG_PROLONG:
+    case DCG_OP_OMG_COARSE:
+    case DCG_OP_OMG_WCYCLE:
+      omg_apply_level(h, op, level, x, static_cast<const double*>(in2), y, st);
+      break;
     default:
       if (h->fp32)
         apply_level<float>(h, op, level, in, in2, out, st);
