@@ -697,6 +697,44 @@ def three_d_sweep(args):
                       "unit": "iterations", "tol": THREE_D["tol"], "rows": rows}), flush=True)
 
 
+def outer_mg_sweep(args):
+    """The outer multigrid preconditioner against mesh size: per (n, dt) the
+    paper's deflated CG (fixed inner tolerance), FCG(8) and FCG(8) with B =
+    one W-cycle on A* (m = --omg-m), mixed form, b = rhs(n, 0), tol 1e-8:
+    outer iterations, W-cycles, wall time and the true residual."""
+    import torch
+    import paper_2606_13429_amd as dcg
+    from dcg_workloads import rhs
+    torch.cuda.set_device(0)
+    rows = []
+    cases = [(n, 1e-4) for n in (64, 128, 256, 512)] + [(n, 1e-2) for n in (64, 128, 256)]
+    methods = (("dcg", dict(outer="cg")), ("fcg8", dict(outer="fcg", m_max=8)),
+               ("fcg8+omg", dict(outer="fcg", m_max=8, outer_mg=args.omg_m)))
+    if args.omg_profile:   # one capped preconditioned solve at the headline size (profiling runs)
+        cases, methods = [(args.n, args.dt)], methods[2:]
+    for n, dt in cases:
+        b = torch.from_numpy(rhs(n, 0)).cuda()
+        x = torch.empty_like(b)
+        for name, kw in methods:
+            s = dcg.Solver(n, dt, prec="mixed",
+                           max_outer=args.max_outer if args.omg_profile else args.sweep_max_outer,
+                           levels=levels_option(n, args.levels), **kw)
+            s.solve(b, x, args.tol)                       # graph capture, caches
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status, st = s.solve(b, x, args.tol)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            s.close()
+            rows.append({"n": n, "dt": dt, "method": name, "status": status, "outer": st.outer_iters,
+                         "tot": st.total_wcycles, "solve_s": round(t, 3), "rel_res_true": st.rel_res_true})
+            log("omg sweep n=%d dt=%g %s: status %d Out %d Tot %d %.2f s res %.2e"
+                % (n, dt, name, status, st.outer_iters, st.total_wcycles, t, st.rel_res_true))
+    print(json.dumps({"metric": "outer iterations and solve time against n: DCG, FCG(8), FCG(8) with "
+                                "the outer multigrid preconditioner", "m": args.omg_m, "tol": args.tol,
+                      "rows": rows}), flush=True)
+
+
 def three_d_table5(args):
     """The analogue of Table 5 (right): deflated CG with the multigrid inner
     solve (W-cycles, RAS, m = 10) at --n3 cubes per side, Out / Tot / Inn for
@@ -823,6 +861,12 @@ def main():
                          "tolerance rule at --n3 (the analogue of Table 5, right)")
     ap.add_argument("--3d-sweep", dest="three_d_sweep", action="store_true",
                     help="outer iterations of the 3D solver against dt at n = 8, 16, 32")
+    ap.add_argument("--outer-mg-sweep", action="store_true",
+                    help="DCG, FCG(8) and FCG(8) with the outer multigrid preconditioner against n")
+    ap.add_argument("--omg-m", type=int, default=2, help="outer multigrid: smoothing steps")
+    ap.add_argument("--omg-profile", action="store_true",
+                    help="with --outer-mg-sweep: only the preconditioned solve at --n / --dt, "
+                         "capped at --max-outer")
     ap.add_argument("--variants", action="store_true",
                     help="compare the fixed and adaptive inner tolerance at --n/--dt")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -861,6 +905,9 @@ def main():
         return
     if args.three_d_table5:
         three_d_table5(args)
+        return
+    if args.outer_mg_sweep:
+        outer_mg_sweep(args)
         return
 
     import numpy as np

@@ -6,9 +6,10 @@
 // diamond square resp. face slot, one round of 128-byte loads each, a fixed
 // shuffle sum), where a launch has few workgroups and its time is one
 // thread's chain of loads.  Larger levels stage the input on 8 x 8 bricks in
-// LDS and give each wavefront one row of the brick's 64 squares; a
-// wavefront whose squares share one class (all but the boundary bricks)
-// reads its table row at wave-uniform addresses through scalar loads.
+// LDS: up to kOmgBrick1MaxN squares per side every wavefront computes one row
+// of the brick's 64 squares with the table rows read per lane; above, every
+// wavefront computes four rows with the table rows read at wave-uniform
+// addresses through scalar loads (the fastest form measured at each size).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -21,7 +22,8 @@ namespace {
 
 constexpr int D = kOmgDofs;
 constexpr int kThreads = 256;
-constexpr int kOmgSplitMaxN = 32;
+constexpr int kOmgSplitMaxN = 64;
+constexpr int kOmgBrick1MaxN = 256;
 
 __device__ __forceinline__ int op_axis(int x, int n) { return x == 0 ? 0 : (x == n - 1 ? 2 : 1); }
 __device__ __forceinline__ int ras_axis(int x, int n) {
@@ -104,7 +106,9 @@ __global__ __launch_bounds__(kThreads) void k_omg_res_split(int n, const double*
   if (s == 0 && e < ne) r[D * e + row] = (f ? f[D * e + row] : 0.0) + acc;
 }
 
-// ---- large levels: bricks of 8 x 8 squares, 16 wavefronts (one per row)
+// ---- large levels (kOmgSplitMaxN < n_k <= kOmgBrick1MaxN): bricks of 8 x 8
+// squares per 1024-thread workgroup, 16 wavefronts (one per row), the
+// table rows read per lane
 constexpr int kBrick = 8;
 constexpr int kBrickThreads = 64 * D;
 
@@ -119,7 +123,7 @@ template <int H>
 __device__ __forceinline__ void stage_box(int n, int x0, int y0, const double* __restrict__ v,
                                           double* lds) {
   using B = Box2<H>;
-  for (int i = threadIdx.x; i < B::N * D; i += kBrickThreads) {
+  for (int i = threadIdx.x; i < B::N * D; i += blockDim.x) {
     const int c = i / D, b = i % D;
     const int x = x0 - H + c % B::X, y = y0 - H + c / B::X;
     double val = 0.0;
@@ -219,6 +223,122 @@ __global__ __launch_bounds__(kBrickThreads) void k_omg_res(int n, const double* 
   if (L.valid) r[D * L.e + L.row] = acc;
 }
 
+// ---- the largest levels (n_k > kOmgBrick1MaxN): bricks of 8 x 8 squares per
+// 256-thread workgroup, wavefront w computing rows 4w .. 4w + 3 of the
+// brick's 64 squares (one square per lane), so that every value staged in
+// LDS serves four rows.
+// The table rows come through scalar loads at wave-uniform addresses: a
+// wavefront whose squares share one class reads its four rows once; a
+// boundary wavefront takes its few distinct classes one after the other,
+// every lane computing with each and keeping the result of its own.
+constexpr int kRowsPerWave = 4;
+constexpr int kBrick4Threads = 64 * D / kRowsPerWave;
+
+// acc[j] += sum over the diamond of K(row j, 16 d + b) r_d[b] (K =
+// kRowsPerWave consecutive rows of a class, row-major [row][208], at a
+// wave-uniform address).
+__device__ __forceinline__ void ras_rows4(ConstPtr K, const double* rs, int o, double acc[kRowsPerWave]) {
+  using B = Box2<2>;
+  constexpr Diamond2 DM;
+  // one diamond square per trip keeps the registers of the four rows free
+  // of spills
+#pragma unroll 1
+  for (int d = 0; d < kOmgDiamond; ++d) {
+    const int od = DM.d[d][1] * B::X + DM.d[d][0];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const double rv = rs[b * B::S + o + od];
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; ++j) acc[j] += K[j * kOmgRasCols + D * d + b] * rv;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBrick4Threads) void k_omg_ras4(int n, const double* __restrict__ ras,
+                                                           const double* __restrict__ r,
+                                                           double* __restrict__ z, int zero) {
+  using B = Box2<2>;
+  __shared__ double rs[D * B::S];
+  const BrickLane L = brick_lane(n);
+  stage_box<2>(n, L.x0, L.y0, r, rs);
+  __syncthreads();
+  const int row0 = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * kRowsPerWave);
+  const int cls = L.valid ? ras_class(L.x, L.y, n) : -1;
+  const int o = (L.ly + 2) * B::X + L.lx + 2;
+  double acc[kRowsPerWave];
+#pragma unroll
+  for (int j = 0; j < kRowsPerWave; ++j) acc[j] = (L.valid && !zero) ? z[D * L.e + row0 + j] : 0.0;
+  uint64_t pending = __ballot(L.valid);
+  while (pending) {   // the wavefront's distinct classes, one per trip (one trip inside)
+    const int c = __builtin_amdgcn_readfirstlane(__shfl(cls, __builtin_ctzll(pending), 64));
+    double t[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) t[j] = acc[j];
+    ras_rows4((ConstPtr)ras + ((int64_t)c * D + row0) * kOmgRasCols, rs, o, t);
+    const bool mine = cls == c;
+    if (mine) {
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; ++j) acc[j] = t[j];
+    }
+    pending &= ~__ballot(mine);
+  }
+  if (L.valid) {
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) z[D * L.e + row0 + j] = acc[j];
+  }
+}
+
+// acc[j] -= sum over the 5 slots of A(row j, neighbour column b) z_nb[b]
+// (A = kRowsPerWave consecutive rows of a class's blocks, [slot][row][16]).
+__device__ __forceinline__ void res_rows4(ConstPtr A, const double* zs, int o, double acc[kRowsPerWave]) {
+  using B = Box2<1>;
+#pragma unroll 1
+  for (int s = 0; s < kSlots; ++s) {
+    const int os = kSlotOff[s][1] * B::X + kSlotOff[s][0];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const double zv = zs[b * B::S + o + os];
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; ++j) acc[j] -= A[s * D * D + j * D + b] * zv;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBrick4Threads) void k_omg_res4(int n, const double* __restrict__ op,
+                                                           const double* __restrict__ f,
+                                                           const double* __restrict__ z,
+                                                           double* __restrict__ r) {
+  using B = Box2<1>;
+  __shared__ double zs[D * B::S];
+  const BrickLane L = brick_lane(n);
+  stage_box<1>(n, L.x0, L.y0, z, zs);
+  __syncthreads();
+  const int row0 = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * kRowsPerWave);
+  const int cls = L.valid ? op_axis(L.x, n) + 3 * op_axis(L.y, n) : -1;
+  const int o = (L.ly + 1) * B::X + L.lx + 1;
+  double acc[kRowsPerWave];
+#pragma unroll
+  for (int j = 0; j < kRowsPerWave; ++j) acc[j] = (L.valid && f) ? f[D * L.e + row0 + j] : 0.0;
+  uint64_t pending = __ballot(L.valid);
+  while (pending) {
+    const int c = __builtin_amdgcn_readfirstlane(__shfl(cls, __builtin_ctzll(pending), 64));
+    double t[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) t[j] = acc[j];
+    res_rows4((ConstPtr)op + ((int64_t)c * kSlots * D + row0) * D, zs, o, t);
+    const bool mine = cls == c;
+    if (mine) {
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; ++j) acc[j] = t[j];
+    }
+    pending &= ~__ballot(mine);
+  }
+  if (L.valid) {
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) r[D * L.e + row0 + j] = acc[j];
+  }
+}
+
 // ---- transfers: one thread per (square, dof); every component injected alike
 __device__ __forceinline__ double inject(int q, int i, int J) {
   double v = 1.0;
@@ -289,9 +409,12 @@ hipError_t launch_omg_res(int nk, const double* op, const double* f, const doubl
   if (nk <= kOmgSplitMaxN)
     hipLaunchKernelGGL(k_omg_res_split, dim3(blocks_for(8 * (int64_t)D * nk * nk)), dim3(kThreads), 0, st,
                        nk, op, f, z, r);
-  else
+  else if (nk <= kOmgBrick1MaxN)
     hipLaunchKernelGGL(k_omg_res, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
                        dim3(kBrickThreads), 0, st, nk, op, f, z, r);
+  else
+    hipLaunchKernelGGL(k_omg_res4, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
+                       dim3(kBrick4Threads), 0, st, nk, op, f, z, r);
   return hipGetLastError();
 }
 
@@ -300,9 +423,12 @@ hipError_t launch_omg_ras(int nk, const double* ras, const double* r, double* z,
   if (nk <= kOmgSplitMaxN)
     hipExtLaunchKernelGGL(k_omg_ras_split, dim3(blocks_for(16 * (int64_t)D * nk * nk)), dim3(kThreads), 0,
                           st, ev0, ev1, 0, nk, ras, r, z, int(zero));
-  else
+  else if (nk <= kOmgBrick1MaxN)
     hipExtLaunchKernelGGL(k_omg_ras, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
                           dim3(kBrickThreads), 0, st, ev0, ev1, 0, nk, ras, r, z, int(zero));
+  else
+    hipExtLaunchKernelGGL(k_omg_ras4, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
+                          dim3(kBrick4Threads), 0, st, ev0, ev1, 0, nk, ras, r, z, int(zero));
   return hipGetLastError();
 }
 
