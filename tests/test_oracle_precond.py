@@ -116,3 +116,31 @@ def test_multigrid_preconditioned_solve():
     assert res.rel_res_true <= 2 * tol
     assert np.linalg.norm(res.x - x_direct) <= 1e-6 * np.linalg.norm(x_direct)
     assert 4 * res.iterations < plain.iterations
+
+
+@pytest.mark.parametrize("dt", [1e-4, 1e-1])
+def test_window_rows_reproduce_the_hierarchy_levels(dt):
+    # the test-side window (tests/window2d.py) that evaluates the level
+    # operators of large grids square by square rests on the exact h-scaling
+    # of the forms and on the Galerkin levels keeping the fine penalty; both
+    # are checked here against the oracle's own hierarchy at n = 32 (levels
+    # 32 and 16, every distance class from the sides)
+    from layout import comp_to_elem, tensor_perm
+    from window2d import Window, sample_squares
+    n = 32
+    H = pc.Hierarchy(d.operator(n, dt), n)
+    rng = np.random.default_rng(3)
+    for k in (H.J, H.J - 1):
+        nk = H.n[k]
+        W = Window(nk, n, dt)
+        pe = tensor_perm(nk)
+        f, z = rng.standard_normal(16 * nk * nk), rng.standard_normal(16 * nk * nk)
+        Az = comp_to_elem(H.A[k] @ z[pe], nk)
+        Sf = comp_to_elem(H.S[k].apply(f[pe]), nk)
+        Sz = comp_to_elem(z[pe] + H.S[k].apply(f[pe] - H.A[k] @ z[pe]), nk)
+        for x, y in sample_squares(nk, count=30, seed=k):
+            e = y * nk + x
+            sl = slice(16 * e, 16 * e + 16)
+            assert np.abs(W.rows(z, x, y) - Az[sl]).max() <= 1e-12 * np.abs(Az).max(), (k, x, y)
+            assert np.abs(W.ras(f, x, y) - Sf[sl]).max() <= 1e-11 * np.abs(Sf).max(), (k, x, y)
+            assert np.abs(W.ras(f, x, y, z) - Sz[sl]).max() <= 1e-11 * np.abs(Sz).max(), (k, x, y)
