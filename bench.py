@@ -573,7 +573,7 @@ def three_d(args):
     torch.cuda.set_device(0)
     t0 = time.time()
     s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], inner=args.inner3,
-                     c_A=args.cA3, max_outer=args.max_outer3)
+                     c_A=args.cA3, max_outer=args.max_outer3, levels=args.levels3)
     log("3d setup n=%d (%d elements) %.1f s" % (n, n ** 3, time.time() - t0))
     bs = [torch.from_numpy(rhs3d(n, i)).cuda() for i in range(max(args.steps, 1))]
     x = torch.empty_like(bs[0])
@@ -629,6 +629,7 @@ def three_d(args):
         "config": {"workload": "3D pseudo-stress A* x = b, n=%d, dt=%g, nu=%g, penalty=%g, tol=%g"
                    % (n, dt, THREE_D["nu"], THREE_D["penalty"], tol)},
         "roofline": roof,
+        "mg_levels": list(s.mg_levels()) if args.inner3 == "mg" else None,
         "rows": rows}), flush=True)
     s.close()
 
@@ -854,6 +855,8 @@ def main():
     ap.add_argument("--3d-inner", dest="inner3", choices=("exact", "cg", "mg"), default="exact")
     ap.add_argument("--3d-max-outer", dest="max_outer3", type=int, default=50000,
                     help="3D: cap on outer iterations (profiling runs only)")
+    ap.add_argument("--3d-levels", dest="levels3", type=int, default=0,
+                    help="3D multigrid: levels kept (0 = all, coarsest 2 cubes per side)")
     ap.add_argument("--3d-cA", dest="cA3", type=float, default=0.0,
                     help="3D: adaptive inner tolerance constant (0 = fixed c_F = 0.01)")
     ap.add_argument("--3d-table5", dest="three_d_table5", action="store_true",
@@ -1093,6 +1096,26 @@ def main():
                                  "speedup_vs_headline_same_seed":
                                      round(stats[0]["t_solve_ms"] * 1e-3 / te, 2)}
         se.close()
+        # the multigrid outer preconditioner (the paper's future work, not its
+        # method): FCG(8) with B = one W-cycle on A*, the same right-hand side
+        log("outer multigrid preconditioner: setup + one solve")
+        t0 = time.time()
+        so = dcg.Solver(n, dt, prec="mixed", outer="fcg", m_max=8, outer_mg=2,
+                        max_outer=args.max_outer, levels=args.levels)
+        to_setup = time.time() - t0
+        so.solve(bs[0], x, tol)                       # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, sto = so.solve(bs[0], x, tol)
+        torch.cuda.synchronize()
+        to = time.time() - t0
+        result["outer_mg_preconditioner_seed0"] = {
+            "method": "FCG(8), directions from B r_i, B = one W-cycle on A* (m = 2), mixed form",
+            "solves_per_s": round(1.0 / to, 4), "outer_iters": sto.outer_iters,
+            "total_wcycles": sto.total_wcycles, "rel_res_true": sto.rel_res_true,
+            "setup_s": round(to_setup, 1),
+            "speedup_vs_headline_same_seed": round(stats[0]["t_solve_ms"] * 1e-3 / to, 2)}
+        so.close()
 
     if not args.skip_cpu:
         log("CPU oracle baseline (setup is not counted)")

@@ -4,19 +4,26 @@ A* as B in the flexible outer iteration) against the oracle
 
 Level operators: every DCG_OP_OMG_* operator element by element against the
 oracle's hierarchy of A* (layout converted element-major <-> component-major),
-at n = 16 (two levels) and n = 64 (four levels; the finest runs the brick
-kernels, the others the small-level kernels).  Bar: max abs difference <=
-1e-12 x max |oracle| for the single operators, 1e-11 for the W-cycle and B
-(FP64, different summation order).  Solves: the preconditioned flexible
-iteration against the oracle's at n = 16 and 32 (FP64 form: outer counts
-within +-2, W-cycles within +-2 %, x within 1e-7; mixed form: counts within
-+-2); graph replays of B equal direct launches bit for bit."""
+at n = 16 (two levels) and n = 64 (four levels), where every level runs the
+small-level (split) kernels.  Bar: max abs difference <= 1e-12 x max |oracle|
+for the single operators, 1e-11 for the W-cycle and B (FP64, different
+summation order).  The brick kernels of the levels above 64 squares per side
+(1024-thread bricks up to 256, the four-rows-per-wavefront bricks above) on
+sampled squares of the levels 128 (n = 128) and 512, 256, 128 (n = 512),
+against the oracle's rows evaluated square by square on a 16 x 16 window
+(tests/window2d.py): A*_k z 1e-12, the RAS step from zero and from a start
+1e-11.  Solves: the preconditioned flexible iteration against the oracle's at
+n = 16 and 32 (FP64 form: outer counts within +-2, W-cycles within +-2 %, x
+within 1e-7; mixed form: counts within +-2); at n = 512, dt = 1e-4 (the
+benchmark's size, four inner levels) the solve converges to the true
+residual; graph replays of B equal direct launches bit for bit."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
 
 from dcg_workloads import rhs
 from layout import comp_to_elem, elem_to_comp, tensor_perm
+from window2d import Window, sample_squares
 from oracle import discretisation as d
 from oracle import krylov as kr
 from oracle import multigrid as mg
@@ -122,6 +129,54 @@ def test_preconditioned_solve_matches_oracle(n, dt):
             assert abs(st.total_wcycles - res.total_cycles) <= max(2, 0.02 * res.total_cycles)
             xg = elem_to_comp(_host(x), n)
             assert np.linalg.norm(xg - res.x) <= 1e-7 * np.linalg.norm(res.x)
+
+
+@pytest.mark.parametrize("n", [128, 512])
+def test_full_size_level_steps_on_sampled_squares(n):
+    dt = 1e-4
+    print("outer mg large levels n=%d" % n, flush=True)
+    s = _solver(n, dt, levels=4)
+    rng = np.random.default_rng(n)
+    J = 1
+    while 8 << (J - 1) < n:
+        J += 1
+    for k in range(J, 0, -1):
+        nk = 8 << (k - 1)
+        if nk <= 64:
+            break
+        f, z = rng.standard_normal(16 * nk * nk), rng.standard_normal(16 * nk * nk)
+        got = []
+        for op, a, b in ((lib.DCG_OP_OMG_LEVEL, z, None), (lib.DCG_OP_OMG_RAS, f, None),
+                         (lib.DCG_OP_OMG_RAS, f, z)):
+            out = torch.empty(16 * nk * nk, dtype=torch.float64, device="cuda")
+            s.apply(op, _dev(a), out, level=k, in2=None if b is None else _dev(b))
+            got.append(_host(out))
+        W = Window(nk, n, dt)
+        ref = {(x, y): (W.rows(z, x, y), W.ras(f, x, y), W.ras(f, x, y, z))
+               for x, y in sample_squares(nk, seed=k)}
+        scale = [max(np.abs(r[i]).max() for r in ref.values()) for i in range(3)]
+        for (x, y), r in ref.items():
+            sl = slice(16 * (y * nk + x), 16 * (y * nk + x) + 16)
+            for i, bar in enumerate((1e-12, 1e-11, 1e-11)):
+                err = np.abs(got[i][sl] - r[i]).max() / scale[i]
+                assert err <= bar, (nk, x, y, i, err)
+        print("  level %d (%d squares per side): %d squares checked" % (k, nk, len(ref)), flush=True)
+    s.close()
+
+
+def test_full_size_preconditioned_solve():
+    n, dt, tol = 512, 1e-4, 1e-8
+    print("outer mg solve n=%d dt=%g" % (n, dt), flush=True)
+    s = dcg.Solver(n, dt, prec="mixed", outer="fcg", m_max=8, outer_mg=2, levels=4, max_outer=400)
+    b = _dev(rhs(n, 0))
+    x = torch.empty_like(b)
+    status, st = s.solve(b, x, tol)
+    s.close()
+    print("  Out %d Tot %d true residual %.3e" % (st.outer_iters, st.total_wcycles, st.rel_res_true),
+          flush=True)
+    # deflated CG without the preconditioner needs 2092 outer iterations here
+    assert status == lib.DCG_OK and st.rel_res_true <= tol
+    assert st.outer_iters <= 100
 
 
 def test_options_are_checked():
