@@ -713,6 +713,8 @@ def outer_mg_sweep(args):
                ("fcg8+omg", dict(outer="fcg", m_max=8, outer_mg=args.omg_m)))
     if args.omg_profile:   # one capped preconditioned solve at the headline size (profiling runs)
         cases, methods = [(args.n, args.dt)], methods[2:]
+    elif args.omg_only:    # the preconditioned column only
+        methods = methods[2:]
     for n, dt in cases:
         b = torch.from_numpy(rhs(n, 0)).cuda()
         x = torch.empty_like(b)
@@ -867,6 +869,8 @@ def main():
     ap.add_argument("--outer-mg-sweep", action="store_true",
                     help="DCG, FCG(8) and FCG(8) with the outer multigrid preconditioner against n")
     ap.add_argument("--omg-m", type=int, default=2, help="outer multigrid: smoothing steps")
+    ap.add_argument("--omg-only", action="store_true",
+                    help="outer multigrid sweep: the preconditioned solves only")
     ap.add_argument("--omg-profile", action="store_true",
                     help="with --outer-mg-sweep: only the preconditioned solve at --n / --dt, "
                          "capped at --max-outer")

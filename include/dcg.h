@@ -322,7 +322,11 @@ dcg_status dcg_host_assemble(const dcg_mesh* mesh, int32_t which, int32_t level,
  * [49][16][208], (S_k r) on a square of class px + 7 py (p = x for x < 3,
  * 6 - (n_k - 1 - x) for n_k - 1 - x < 3, else 3) equals table[cls] times r on
  * the 13 squares (dx, dy) with |dx| + |dy| <= 2 (by dy, then dx; column
- * 16 d + b); 2 (level 1): the inverse of A*_1, [1024][1024] row-major.
+ * 16 d + b); 2 (level 1): the inverse of A*_1, [1024][1024] row-major;
+ * 3 and 4 (level >= 2 for 4): the tables 0 and 1 in the operand order of the
+ * MFMA kernels, [9][20][64] and [49][52][64], entry (cls, s, l) = row l % 16,
+ * column 4 s + l / 16 of the class's matrix (for table 0 the 16 x 80 matrix
+ * with column 16 slot + b).
  * DCG_EINVAL for bad arguments or a short buffer. */
 dcg_status dcg_host_outer_mg(int32_t n, double penalty, double dt, double nu, int32_t level,
                              int32_t which, double* dst, int64_t dst_len);

@@ -210,9 +210,10 @@ def dcg_noalloc_bytes():
 def dcg_host_outer_mg(n, penalty, dt, nu, level, which):
     """Host copy of a class table of the outer multigrid (no device call):
     which 0 the operator table (9, 5, 16, 16), 1 the RAS update table
-    (49, 16, 208), 2 the coarsest inverse (1024, 1024)."""
+    (49, 16, 208), 2 the coarsest inverse (1024, 1024), 3 and 4 tables 0 and
+    1 in the MFMA operand order, (9, 20, 64) and (49, 52, 64)."""
     import numpy as np
-    shape = {0: (9, 5, 16, 16), 1: (49, 16, 208), 2: (1024, 1024)}[which]
+    shape = {0: (9, 5, 16, 16), 1: (49, 16, 208), 2: (1024, 1024), 3: (9, 20, 64), 4: (49, 52, 64)}[which]
     out = np.empty(shape, dtype=np.float64)
     _check(_lib.dcg_host_outer_mg(n, penalty, dt, nu, level, which, out.ctypes.data_as(_P(ctypes.c_double)),
                                   out.size))

@@ -188,12 +188,16 @@ dcg_status dcg_host_outer_mg(int32_t n, double penalty, double dt, double nu, in
   if (!(penalty > 0.0) || !(dt > 0.0) || !(nu > 0.0))
     return fail(nullptr, DCG_EINVAL, "penalty, dt and nu must be positive");
   if (level < 1 || level > J) return fail(nullptr, DCG_EINVAL, "level out of range");
-  if (which < 0 || which > 2 || (which == 1 && level < 2) || (which == 2 && level != 1))
-    return fail(nullptr, DCG_EINVAL, "which must be 0, 1 (level >= 2) or 2 (level 1)");
+  if (which < 0 || which > 4 || ((which == 1 || which == 4) && level < 2) || (which == 2 && level != 1))
+    return fail(nullptr, DCG_EINVAL, "which must be 0, 1 (level >= 2), 2 (level 1), 3 or 4 (level >= 2)");
   return guarded(nullptr, [&]() -> dcg_status {
     const dcg::OmgHierarchy H = dcg::build_omg(n, penalty, dt, nu);
+    const dcg::OmgLevel& L = H.lev[level - 1];
+    std::vector<double> ordered;
+    if (which == 3) ordered = dcg::omg_operand_order(dcg::omg_op_rows(L.op), dcg::kOmgOpClasses, dcg::kOmgOpCols);
+    if (which == 4) ordered = dcg::omg_operand_order(L.ras, dcg::kOmgRasClasses, dcg::kOmgRasCols);
     const std::vector<double>& src =
-        which == 0 ? H.lev[level - 1].op : (which == 1 ? H.lev[level - 1].ras : H.coarse_inv);
+        which == 0 ? L.op : (which == 1 ? L.ras : (which == 2 ? H.coarse_inv : ordered));
     if (dst_len < (int64_t)src.size()) return fail(nullptr, DCG_EINVAL, "dst too small");
     std::copy(src.begin(), src.end(), dst);
     return DCG_OK;

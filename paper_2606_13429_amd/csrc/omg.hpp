@@ -26,7 +26,13 @@
 //                        domain); cls = px + 7 py with p = x (x < 3),
 //                        6 - (n_k - 1 - x) (n_k - 1 - x < 3), else 3; levels
 //                        below 6 squares per side take cls = e
-// and the coarsest level the dense inverse of its operator, row-major.
+// and the coarsest level the dense inverse of its operator, row-major.  The
+// MFMA kernels read both tables in the operand order of v_mfma_f64_16x16x4f64
+// (a 16-row table times 16 squares' gathered inputs, four columns a step):
+//   opm  [9][20][64], rasm [49][52][64]: entry (cls, s, l) = row l % 16,
+//                        column 4 s + l / 16 of the row-major table above
+//                        (column 16 slot + b of op), so that one step's
+//                        operand is one contiguous 512-byte load.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -42,6 +48,9 @@ constexpr int kOmgRasClassMinN = 6;
 constexpr int kOmgDiamond = 13;
 constexpr int kOmgRasCols = kOmgDofs * kOmgDiamond;
 constexpr int kOmgCoarsest = 8;
+constexpr int kOmgOpCols = 5 * kOmgDofs;   // self and the four edge neighbours
+constexpr int kOmgRasSteps = kOmgRasCols / 4;
+constexpr int kOmgOpSteps = kOmgOpCols / 4;
 
 struct OmgLevel {
   int n = 0;
@@ -57,6 +66,13 @@ struct OmgHierarchy {
 // Offsets (dx, dy) of the 2D diamond, |dx| + |dy| <= 2, by dy then dx.
 void omg_diamond(int off[kOmgDiamond][2]);
 
+// The operand order of a table of `classes` row-major 16 x cols class
+// matrices (cols a multiple of 4): [classes][cols / 4][64].
+std::vector<double> omg_operand_order(const std::vector<double>& tab, int classes, int cols);
+
+// The operator table as 9 row-major 16 x 80 matrices (column 16 slot + b).
+std::vector<double> omg_op_rows(const std::vector<double>& op);
+
 // J = log2(n / 8) + 1 for n = 8 2^k >= 16, else 0.
 int omg_num_levels(int n);
 
@@ -66,12 +82,13 @@ int omg_num_levels(int n);
 OmgHierarchy build_omg(int n, double penalty, double dt, double nu);
 
 // ---- launchers (FP64; level vectors as above)
-// r = f - A*_k z (f may be NULL: r = -A*_k z).
-hipError_t launch_omg_res(int nk, const double* op, const double* f, const double* z, double* r,
-                          hipStream_t st);
-// z = (zero ? 0 : z) + S_k r.
-hipError_t launch_omg_ras(int nk, const double* ras, const double* r, double* z, bool zero,
-                          hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// r = f - A*_k z (f may be NULL: r = -A*_k z); op and opm the level's
+// operator table in both orders.
+hipError_t launch_omg_res(int nk, const double* op, const double* opm, const double* f, const double* z,
+                          double* r, hipStream_t st);
+// z = (zero ? 0 : z) + S_k r; ras and rasm the level's RAS table in both orders.
+hipError_t launch_omg_ras(int nk, const double* ras, const double* rasm, const double* r, double* z,
+                          bool zero, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // fc = P_k^T r (nf fine squares per side).
 hipError_t launch_omg_restrict(int nf, const double* r, double* fc, hipStream_t st);
 // z += P_k zc, or z = P_k zc with assign.

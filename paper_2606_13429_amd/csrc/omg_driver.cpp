@@ -41,20 +41,20 @@ void cycle(const OuterMg& g, int k, int mode, hipStream_t st) {
   }
   for (int s = 0; s < g.m; ++s) {
     if (s == 0 && mode == kZero) {
-      DCG_HIP(launch_omg_ras(nk, g.ras[i], g.f[i], g.z[i], true, st));
+      DCG_HIP(launch_omg_ras(nk, g.ras[i], g.rasm[i], g.f[i], g.z[i], true, st));
       continue;
     }
-    DCG_HIP(launch_omg_res(nk, g.op[i], g.f[i], g.z[i], g.r[i], st));
-    DCG_HIP(launch_omg_ras(nk, g.ras[i], g.r[i], g.z[i], false, st));
+    DCG_HIP(launch_omg_res(nk, g.op[i], g.opm[i], g.f[i], g.z[i], g.r[i], st));
+    DCG_HIP(launch_omg_ras(nk, g.ras[i], g.rasm[i], g.r[i], g.z[i], false, st));
   }
-  DCG_HIP(launch_omg_res(nk, g.op[i], g.f[i], g.z[i], g.r[i], st));
+  DCG_HIP(launch_omg_res(nk, g.op[i], g.opm[i], g.f[i], g.z[i], g.r[i], st));
   DCG_HIP(launch_omg_restrict(nk, g.r[i], g.f[i - 1], st));
   cycle(g, k - 1, kZero, st);                 // gamma = 2 coarse cycles,
   if (k - 1 > 1) cycle(g, k - 1, kWarm, st);  // the exact solve once
   DCG_HIP(launch_omg_prolong(nk, g.z[i - 1], g.z[i], false, st));
   for (int s = 0; s < g.m; ++s) {
-    DCG_HIP(launch_omg_res(nk, g.op[i], g.f[i], g.z[i], g.r[i], st));
-    DCG_HIP(launch_omg_ras(nk, g.ras[i], g.r[i], g.z[i], false, st));
+    DCG_HIP(launch_omg_res(nk, g.op[i], g.opm[i], g.f[i], g.z[i], g.r[i], st));
+    DCG_HIP(launch_omg_ras(nk, g.ras[i], g.rasm[i], g.r[i], g.z[i], false, st));
   }
 }
 
@@ -76,6 +76,8 @@ void omg_setup(dcg_ctx* h) {
     g->n.push_back(L.n);
     g->op.push_back(upload(ws, L.op));
     g->ras.push_back(k >= 2 ? upload(ws, L.ras) : nullptr);
+    g->opm.push_back(upload(ws, omg_operand_order(omg_op_rows(L.op), kOmgOpClasses, kOmgOpCols)));
+    g->rasm.push_back(k >= 2 ? upload(ws, omg_operand_order(L.ras, kOmgRasClasses, kOmgRasCols)) : nullptr);
     g->f.push_back(static_cast<double*>(ws.alloc(len * sizeof(double))));
     g->z.push_back(static_cast<double*>(ws.alloc(len * sizeof(double))));
     g->r.push_back(static_cast<double*>(ws.alloc(len * sizeof(double))));
@@ -135,17 +137,17 @@ void omg_apply_level(dcg_ctx* h, dcg_op op, int k, const double* in, const doubl
       omg_apply(h, in, out, st);
       break;
     case DCG_OP_OMG_LEVEL:   // out = -(0 - A*_k in)
-      DCG_HIP(launch_omg_res(nk, g.op[i], nullptr, in, g.r[i], st));
+      DCG_HIP(launch_omg_res(nk, g.op[i], g.opm[i], nullptr, in, g.r[i], st));
       DCG_HIP(launch_scale(len, -1.0, g.r[i], out, st));
       break;
     case DCG_OP_OMG_RAS:
       if (k < 2) throw Error(DCG_EINVAL, "the coarsest level has no smoother");
       if (!in2) {
-        DCG_HIP(launch_omg_ras(nk, g.ras[i], in, out, true, st));
+        DCG_HIP(launch_omg_ras(nk, g.ras[i], g.rasm[i], in, out, true, st));
       } else {
         copy(in2, out, len, st);
-        DCG_HIP(launch_omg_res(nk, g.op[i], in, in2, g.r[i], st));
-        DCG_HIP(launch_omg_ras(nk, g.ras[i], g.r[i], out, false, st));
+        DCG_HIP(launch_omg_res(nk, g.op[i], g.opm[i], in, in2, g.r[i], st));
+        DCG_HIP(launch_omg_ras(nk, g.ras[i], g.rasm[i], g.r[i], out, false, st));
       }
       break;
     case DCG_OP_OMG_RESTRICT:

@@ -233,6 +233,30 @@ void omg_diamond(int off[kOmgDiamond][2]) {
       }
 }
 
+std::vector<double> omg_operand_order(const std::vector<double>& tab, int classes, int cols) {
+  if (cols % 4 || tab.size() != (size_t)classes * D * cols)
+    throw std::runtime_error("outer multigrid: table shape does not fit the operand order");
+  const int steps = cols / 4;
+  std::vector<double> out(tab.size());
+  for (int c = 0; c < classes; ++c)
+    for (int s = 0; s < steps; ++s)
+      for (int l = 0; l < 64; ++l)
+        out[((size_t)c * steps + s) * 64 + l] = tab[((size_t)c * D + l % 16) * cols + 4 * s + l / 16];
+  return out;
+}
+
+std::vector<double> omg_op_rows(const std::vector<double>& op) {
+  if (op.size() != (size_t)kOmgOpClasses * kSlots * D * D)
+    throw std::runtime_error("outer multigrid: operator table of the wrong size");
+  std::vector<double> out(op.size());
+  for (int c = 0; c < kOmgOpClasses; ++c)
+    for (int s = 0; s < kSlots; ++s)
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b)
+          out[((size_t)c * D + a) * kOmgOpCols + D * s + b] = op[(((size_t)c * kSlots + s) * D + a) * D + b];
+  return out;
+}
+
 int omg_num_levels(int n) {
   if (n < 2 * kOmgCoarsest || n % kOmgCoarsest) return 0;
   int r = n / kOmgCoarsest, J = 1;

@@ -5,11 +5,12 @@
 // lanes on levels of at most kOmgSplitMaxN squares per side (one lane per
 // diamond square resp. face slot, one round of 128-byte loads each, a fixed
 // shuffle sum), where a launch has few workgroups and its time is one
-// thread's chain of loads.  Larger levels stage the input on 8 x 8 bricks in
-// LDS: up to kOmgBrick1MaxN squares per side every wavefront computes one row
-// of the brick's 64 squares with the table rows read per lane; above, every
-// wavefront computes four rows with the table rows read at wave-uniform
-// addresses through scalar loads (the fastest form measured at each size).
+// thread's chain of loads.  Larger levels stage the input of an 8 x 8 brick
+// in LDS and run the step as FP64 MFMA products of the class tables with the
+// brick's gathered inputs (measured against vector-FMA bricks with the table
+// rows read per lane or through scalar loads: 2-5x faster above 64 squares
+// per side, slower below, where a boundary brick's several classes cost one
+// trip each).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -22,8 +23,7 @@ namespace {
 
 constexpr int D = kOmgDofs;
 constexpr int kThreads = 256;
-constexpr int kOmgSplitMaxN = 64;
-constexpr int kOmgBrick1MaxN = 256;
+constexpr int kOmgSplitMaxN = 32;
 
 __device__ __forceinline__ int op_axis(int x, int n) { return x == 0 ? 0 : (x == n - 1 ? 2 : 1); }
 __device__ __forceinline__ int ras_axis(int x, int n) {
@@ -106,11 +106,8 @@ __global__ __launch_bounds__(kThreads) void k_omg_res_split(int n, const double*
   if (s == 0 && e < ne) r[D * e + row] = (f ? f[D * e + row] : 0.0) + acc;
 }
 
-// ---- large levels (kOmgSplitMaxN < n_k <= kOmgBrick1MaxN): bricks of 8 x 8
-// squares per 1024-thread workgroup, 16 wavefronts (one per row), the
-// table rows read per lane
+// ---- large levels: 8 x 8 bricks with their input staged in LDS
 constexpr int kBrick = 8;
-constexpr int kBrickThreads = 64 * D;
 
 template <int H>
 struct Box2 {
@@ -132,211 +129,215 @@ __device__ __forceinline__ void stage_box(int n, int x0, int y0, const double* _
   }
 }
 
-using ConstPtr = const __attribute__((address_space(4))) double*;
-__device__ __forceinline__ ConstPtr as_const(const double* p) { return (ConstPtr)p; }
+// ---- MFMA form: on an 8 x 8 brick the step is a class table (16 rows) times
+// the gathered inputs of the brick's squares, 16 squares per wavefront as the
+// columns of v_mfma_f64_16x16x4f64, four table columns a step.  Lane l
+// supplies row l % 16, column 4 s + l / 16 of the table (the operand-order
+// tables make one step's operand one contiguous 512-byte run) and, for square
+// l % 16 of its wavefront, input value 4 s + l / 16 of that square's window
+// from LDS; it receives rows 4 v + l / 16 (v = 0..3) of square l % 16.
+// Interior bricks (every square of the interior class) stage the one class
+// table in LDS next to the input and run the products from LDS with two
+// accumulators; boundary bricks, dispatched first, take the distinct classes
+// of each wavefront one after the other with the table read from global
+// memory, keeping for each square the product with its own class.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kMfmaThreads = 256;   // 4 wavefronts x 16 squares = one brick
+constexpr int kRasInterior = 3 + 7 * 3;
+constexpr int kOpInterior = 1 + 3 * 1;
 
-struct BrickLane {
-  int row, lx, ly, x, y, x0, y0;
-  bool valid;
+struct MfmaLane {
+  int x0, y0, x, y, q, o1, o2;   // brick, square, output row group, LDS offsets (halo 1 / 2)
+  bool interior;
   int64_t e;
 };
 
-__device__ __forceinline__ BrickLane brick_lane(int n) {
-  const int nb = (n + kBrick - 1) / kBrick;
-  BrickLane L;
-  L.x0 = (blockIdx.x % nb) * kBrick;
-  L.y0 = (blockIdx.x / nb) * kBrick;
-  L.row = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = threadIdx.x & 63;
-  L.lx = c & 7;
-  L.ly = c >> 3;
-  L.x = L.x0 + L.lx;
-  L.y = L.y0 + L.ly;
-  L.valid = L.x < n && L.y < n;
+// Workgroup -> brick: the ring of boundary bricks first, then the interior.
+__device__ __forceinline__ MfmaLane mfma_lane(int n) {
+  const int nb = n / kBrick, ring = nb > 1 ? 4 * (nb - 1) : 1;
+  const int b = blockIdx.x;
+  int bx, by;
+  if (b < ring) {
+    if (b < nb) {
+      bx = b;
+      by = 0;
+    } else if (b < 2 * nb) {
+      bx = b - nb;
+      by = nb - 1;
+    } else {
+      const int t = b - 2 * nb;
+      bx = t < nb - 2 ? 0 : nb - 1;
+      by = 1 + (t < nb - 2 ? t : t - (nb - 2));
+    }
+  } else {
+    const int t = b - ring;
+    bx = 1 + t % (nb - 2);
+    by = 1 + t / (nb - 2);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = lane & 15, lx = j & 7, ly = 2 * w + (j >> 3);
+  MfmaLane L;
+  L.x0 = bx * kBrick;
+  L.y0 = by * kBrick;
+  L.interior = b >= ring;
+  L.x = L.x0 + lx;
+  L.y = L.y0 + ly;
+  L.q = lane >> 4;
+  L.o1 = (ly + 1) * Box2<1>::X + lx + 1;
+  L.o2 = (ly + 2) * Box2<2>::X + lx + 2;
   L.e = (int64_t)L.y * n + L.x;
   return L;
 }
 
-template <typename P>
-__device__ __forceinline__ double ras_row(P K, const double* rs, int o, double acc) {
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Copies one class table (steps x 64 doubles, operand order) into LDS.
+template <int STEPS>
+__device__ __forceinline__ void stage_table(const double* __restrict__ src, double* kt) {
+  for (int i = threadIdx.x; i < STEPS * 64; i += kMfmaThreads) kt[i] = src[i];
+}
+
+// RAS products over the 13-square diamond: Kv(s) is the lane's table operand
+// of step s, the input of step s the LDS plane 4 (s % 4) + q at the square's
+// offset plus the diamond offset of s / 4.
+template <typename KV>
+__device__ __forceinline__ v4d ras_chain(KV Kv, const double* rs, const MfmaLane& L, v4d t) {
   using B = Box2<2>;
   constexpr Diamond2 DM;
+  v4d t1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int d = 0; d < kOmgDiamond; ++d) {
     const int od = DM.d[d][1] * B::X + DM.d[d][0];
-#pragma unroll
-    for (int b = 0; b < D; ++b) acc += K[D * d + b] * rs[b * B::S + o + od];
+    t = mfma64(Kv(4 * d), rs[(0 + L.q) * B::S + L.o2 + od], t);
+    t1 = mfma64(Kv(4 * d + 1), rs[(4 + L.q) * B::S + L.o2 + od], t1);
+    t = mfma64(Kv(4 * d + 2), rs[(8 + L.q) * B::S + L.o2 + od], t);
+    t1 = mfma64(Kv(4 * d + 3), rs[(12 + L.q) * B::S + L.o2 + od], t1);
   }
-  return acc;
+  return t + t1;
 }
 
-__global__ __launch_bounds__(kBrickThreads) void k_omg_ras(int n, const double* __restrict__ ras,
-                                                           const double* __restrict__ r,
-                                                           double* __restrict__ z, int zero) {
+template <typename KV>
+__device__ __forceinline__ v4d res_chain(KV Kv, const double* zs, const MfmaLane& L) {
+  using B = Box2<1>;
+  v4d t = {0.0, 0.0, 0.0, 0.0}, t1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int sl = 0; sl < kSlots; ++sl) {
+    const int os = kSlotOff[sl][1] * B::X + kSlotOff[sl][0];
+    t = mfma64(Kv(4 * sl), zs[(0 + L.q) * B::S + L.o1 + os], t);
+    t1 = mfma64(Kv(4 * sl + 1), zs[(4 + L.q) * B::S + L.o1 + os], t1);
+    t = mfma64(Kv(4 * sl + 2), zs[(8 + L.q) * B::S + L.o1 + os], t);
+    t1 = mfma64(Kv(4 * sl + 3), zs[(12 + L.q) * B::S + L.o1 + os], t1);
+  }
+  return t + t1;
+}
+
+// Boundary bricks: the lanes of a wavefront take squares of as few classes as
+// possible -- square slot i of the brick (wavefront i / 16, lane i % 16) gets
+// the square of rank i in the order (class, position) -- so that an edge brick
+// needs at most two class trips per wavefront.  cls_of(x, y) is the class.
+template <typename CF>
+__device__ __forceinline__ void sort_squares(MfmaLane& L, int n, CF cls_of, int* scls, int* sperm) {
+  if (threadIdx.x < kBrick * kBrick)
+    scls[threadIdx.x] = cls_of(L.x0 + (threadIdx.x & 7), L.y0 + (threadIdx.x >> 3));
+  __syncthreads();
+  if (threadIdx.x < kBrick * kBrick) {
+    const int me = threadIdx.x, c = scls[me];
+    int rank = 0;
+    for (int i = 0; i < kBrick * kBrick; ++i) {
+      const int ci = scls[i];
+      rank += (ci < c) || (ci == c && i < me);
+    }
+    sperm[rank] = me;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, sq = sperm[16 * (threadIdx.x >> 6) + (lane & 15)];
+  const int lx = sq & 7, ly = sq >> 3;
+  L.x = L.x0 + lx;
+  L.y = L.y0 + ly;
+  L.o1 = (ly + 1) * Box2<1>::X + lx + 1;
+  L.o2 = (ly + 2) * Box2<2>::X + lx + 2;
+  L.e = (int64_t)L.y * n + L.x;
+}
+
+// three workgroups fit a compute unit's LDS; registers are kept to match
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_omg_ras_m(int n, const double* __restrict__ rasm,
+                                                            const double* __restrict__ r,
+                                                            double* __restrict__ z, int zero) {
   using B = Box2<2>;
   __shared__ double rs[D * B::S];
-  const BrickLane L = brick_lane(n);
+  __shared__ double kt[kOmgRasSteps * 64];
+  __shared__ int scls[kBrick * kBrick], sperm[kBrick * kBrick];
+  MfmaLane L = mfma_lane(n);
+  const int lane = threadIdx.x & 63;
+  if (L.interior) stage_table<kOmgRasSteps>(rasm + (int64_t)kRasInterior * kOmgRasSteps * 64, kt);
   stage_box<2>(n, L.x0, L.y0, r, rs);
+  if (!L.interior) sort_squares(L, n, [n](int x, int y) { return ras_class(x, y, n); }, scls, sperm);
+  v4d acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = zero ? 0.0 : z[D * L.e + 4 * v + L.q];
   __syncthreads();
-  const int cls = ras_class(L.valid ? L.x : L.x0, L.valid ? L.y : L.y0, n);
-  const int first = __builtin_amdgcn_readfirstlane(cls);
-  const bool uniform = __all(!L.valid || cls == first);
-  const int o = (L.ly + 2) * B::X + L.lx + 2;
-  double acc = (L.valid && !zero) ? z[D * L.e + L.row] : 0.0;
-  if (uniform)
-    acc = ras_row(as_const(ras + ((int64_t)first * D + L.row) * kOmgRasCols), rs, o, acc);
-  else
-    acc = ras_row(ras + ((int64_t)cls * D + L.row) * kOmgRasCols, rs, o, acc);
-  if (L.valid) z[D * L.e + L.row] = acc;
-}
-
-template <typename P>
-__device__ __forceinline__ double res_row(P A, const double* zs, int o, double acc) {
-  using B = Box2<1>;
+  if (L.interior) {
+    acc = ras_chain([&](int st) { return kt[lane + 64 * st]; }, rs, L, acc);
+  } else {
+    const int cls = ras_class(L.x, L.y, n);
+    uint64_t pending = __ballot(true);
+    while (pending) {   // the wavefront's distinct classes, one per trip
+      const int c = __builtin_amdgcn_readfirstlane(__shfl(cls, __builtin_ctzll(pending), 64));
+      const double* K = rasm + (int64_t)c * kOmgRasSteps * 64 + lane;
+      double a[kOmgRasSteps];   // the trip's operands requested ahead of the products
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const int os = kSlotOff[s][1] * B::X + kSlotOff[s][0];
-#pragma unroll
-    for (int b = 0; b < D; ++b) acc -= A[s * D * D + b] * zs[b * B::S + o + os];
+      for (int st = 0; st < kOmgRasSteps; ++st) a[st] = K[64 * st];
+      const v4d t = ras_chain([&](int st) { return a[st]; }, rs, L, acc);
+      const bool mine = cls == c;
+      if (mine) acc = t;
+      pending &= ~__ballot(mine);
+    }
   }
-  return acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) z[D * L.e + 4 * v + L.q] = acc[v];
 }
 
-__global__ __launch_bounds__(kBrickThreads) void k_omg_res(int n, const double* __restrict__ op,
-                                                           const double* __restrict__ f,
-                                                           const double* __restrict__ z,
-                                                           double* __restrict__ r) {
+__global__ __launch_bounds__(kMfmaThreads) void k_omg_res_m(int n, const double* __restrict__ opm,
+                                                            const double* __restrict__ f,
+                                                            const double* __restrict__ z,
+                                                            double* __restrict__ r) {
   using B = Box2<1>;
   __shared__ double zs[D * B::S];
-  const BrickLane L = brick_lane(n);
+  __shared__ double kt[kOmgOpSteps * 64];
+  __shared__ int scls[kBrick * kBrick], sperm[kBrick * kBrick];
+  MfmaLane L = mfma_lane(n);
+  const int lane = threadIdx.x & 63;
+  if (L.interior) stage_table<kOmgOpSteps>(opm + (int64_t)kOpInterior * kOmgOpSteps * 64, kt);
   stage_box<1>(n, L.x0, L.y0, z, zs);
+  if (!L.interior)
+    sort_squares(L, n, [n](int x, int y) { return op_axis(x, n) + 3 * op_axis(y, n); }, scls, sperm);
+  double fv[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) fv[v] = f ? f[D * L.e + 4 * v + L.q] : 0.0;
   __syncthreads();
-  const int cls = L.valid ? op_axis(L.x, n) + 3 * op_axis(L.y, n) : 4;
-  const int first = __builtin_amdgcn_readfirstlane(cls);
-  const bool uniform = __all(!L.valid || cls == first);
-  const int o = (L.ly + 1) * B::X + L.lx + 1;
-  double acc = (L.valid && f) ? f[D * L.e + L.row] : 0.0;
-  if (uniform)
-    acc = res_row(as_const(op + ((int64_t)first * kSlots * D + L.row) * D), zs, o, acc);
-  else
-    acc = res_row(op + ((int64_t)cls * kSlots * D + L.row) * D, zs, o, acc);
-  if (L.valid) r[D * L.e + L.row] = acc;
-}
-
-// ---- the largest levels (n_k > kOmgBrick1MaxN): bricks of 8 x 8 squares per
-// 256-thread workgroup, wavefront w computing rows 4w .. 4w + 3 of the
-// brick's 64 squares (one square per lane), so that every value staged in
-// LDS serves four rows.
-// The table rows come through scalar loads at wave-uniform addresses: a
-// wavefront whose squares share one class reads its four rows once; a
-// boundary wavefront takes its few distinct classes one after the other,
-// every lane computing with each and keeping the result of its own.
-constexpr int kRowsPerWave = 4;
-constexpr int kBrick4Threads = 64 * D / kRowsPerWave;
-
-// acc[j] += sum over the diamond of K(row j, 16 d + b) r_d[b] (K =
-// kRowsPerWave consecutive rows of a class, row-major [row][208], at a
-// wave-uniform address).
-__device__ __forceinline__ void ras_rows4(ConstPtr K, const double* rs, int o, double acc[kRowsPerWave]) {
-  using B = Box2<2>;
-  constexpr Diamond2 DM;
-  // one diamond square per trip keeps the registers of the four rows free
-  // of spills
-#pragma unroll 1
-  for (int d = 0; d < kOmgDiamond; ++d) {
-    const int od = DM.d[d][1] * B::X + DM.d[d][0];
+  v4d acc;
+  if (L.interior) {
+    acc = res_chain([&](int st) { return kt[lane + 64 * st]; }, zs, L);
+  } else {
+    const int cls = op_axis(L.x, n) + 3 * op_axis(L.y, n);
+    acc = v4d{0.0, 0.0, 0.0, 0.0};
+    uint64_t pending = __ballot(true);
+    while (pending) {
+      const int c = __builtin_amdgcn_readfirstlane(__shfl(cls, __builtin_ctzll(pending), 64));
+      const double* K = opm + (int64_t)c * kOmgOpSteps * 64 + lane;
+      double a[kOmgOpSteps];
 #pragma unroll
-    for (int b = 0; b < D; ++b) {
-      const double rv = rs[b * B::S + o + od];
-#pragma unroll
-      for (int j = 0; j < kRowsPerWave; ++j) acc[j] += K[j * kOmgRasCols + D * d + b] * rv;
+      for (int st = 0; st < kOmgOpSteps; ++st) a[st] = K[64 * st];
+      const v4d t = res_chain([&](int st) { return a[st]; }, zs, L);
+      const bool mine = cls == c;
+      if (mine) acc = t;
+      pending &= ~__ballot(mine);
     }
   }
-}
-
-__global__ __launch_bounds__(kBrick4Threads) void k_omg_ras4(int n, const double* __restrict__ ras,
-                                                           const double* __restrict__ r,
-                                                           double* __restrict__ z, int zero) {
-  using B = Box2<2>;
-  __shared__ double rs[D * B::S];
-  const BrickLane L = brick_lane(n);
-  stage_box<2>(n, L.x0, L.y0, r, rs);
-  __syncthreads();
-  const int row0 = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * kRowsPerWave);
-  const int cls = L.valid ? ras_class(L.x, L.y, n) : -1;
-  const int o = (L.ly + 2) * B::X + L.lx + 2;
-  double acc[kRowsPerWave];
 #pragma unroll
-  for (int j = 0; j < kRowsPerWave; ++j) acc[j] = (L.valid && !zero) ? z[D * L.e + row0 + j] : 0.0;
-  uint64_t pending = __ballot(L.valid);
-  while (pending) {   // the wavefront's distinct classes, one per trip (one trip inside)
-    const int c = __builtin_amdgcn_readfirstlane(__shfl(cls, __builtin_ctzll(pending), 64));
-    double t[kRowsPerWave];
-#pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) t[j] = acc[j];
-    ras_rows4((ConstPtr)ras + ((int64_t)c * D + row0) * kOmgRasCols, rs, o, t);
-    const bool mine = cls == c;
-    if (mine) {
-#pragma unroll
-      for (int j = 0; j < kRowsPerWave; ++j) acc[j] = t[j];
-    }
-    pending &= ~__ballot(mine);
-  }
-  if (L.valid) {
-#pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) z[D * L.e + row0 + j] = acc[j];
-  }
-}
-
-// acc[j] -= sum over the 5 slots of A(row j, neighbour column b) z_nb[b]
-// (A = kRowsPerWave consecutive rows of a class's blocks, [slot][row][16]).
-__device__ __forceinline__ void res_rows4(ConstPtr A, const double* zs, int o, double acc[kRowsPerWave]) {
-  using B = Box2<1>;
-#pragma unroll 1
-  for (int s = 0; s < kSlots; ++s) {
-    const int os = kSlotOff[s][1] * B::X + kSlotOff[s][0];
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      const double zv = zs[b * B::S + o + os];
-#pragma unroll
-      for (int j = 0; j < kRowsPerWave; ++j) acc[j] -= A[s * D * D + j * D + b] * zv;
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBrick4Threads) void k_omg_res4(int n, const double* __restrict__ op,
-                                                           const double* __restrict__ f,
-                                                           const double* __restrict__ z,
-                                                           double* __restrict__ r) {
-  using B = Box2<1>;
-  __shared__ double zs[D * B::S];
-  const BrickLane L = brick_lane(n);
-  stage_box<1>(n, L.x0, L.y0, z, zs);
-  __syncthreads();
-  const int row0 = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * kRowsPerWave);
-  const int cls = L.valid ? op_axis(L.x, n) + 3 * op_axis(L.y, n) : -1;
-  const int o = (L.ly + 1) * B::X + L.lx + 1;
-  double acc[kRowsPerWave];
-#pragma unroll
-  for (int j = 0; j < kRowsPerWave; ++j) acc[j] = (L.valid && f) ? f[D * L.e + row0 + j] : 0.0;
-  uint64_t pending = __ballot(L.valid);
-  while (pending) {
-    const int c = __builtin_amdgcn_readfirstlane(__shfl(cls, __builtin_ctzll(pending), 64));
-    double t[kRowsPerWave];
-#pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) t[j] = acc[j];
-    res_rows4((ConstPtr)op + ((int64_t)c * kSlots * D + row0) * D, zs, o, t);
-    const bool mine = cls == c;
-    if (mine) {
-#pragma unroll
-      for (int j = 0; j < kRowsPerWave; ++j) acc[j] = t[j];
-    }
-    pending &= ~__ballot(mine);
-  }
-  if (L.valid) {
-#pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) r[D * L.e + row0 + j] = acc[j];
-  }
+  for (int v = 0; v < 4; ++v) r[D * L.e + 4 * v + L.q] = fv[v] - acc[v];
 }
 
 // ---- transfers: one thread per (square, dof); every component injected alike
@@ -401,34 +402,32 @@ __global__ __launch_bounds__(kThreads) void k_omg_dense(int m, const double* __r
 }
 
 unsigned blocks_for(int64_t threads) { return unsigned((threads + kThreads - 1) / kThreads); }
+unsigned bricks(int nk) { return unsigned((nk / kBrick) * (nk / kBrick)); }
 
 }  // namespace
 
-hipError_t launch_omg_res(int nk, const double* op, const double* f, const double* z, double* r,
-                          hipStream_t st) {
-  if (nk <= kOmgSplitMaxN)
+hipError_t launch_omg_res(int nk, const double* op, const double* opm, const double* f, const double* z,
+                          double* r, hipStream_t st) {
+  if (nk <= kOmgSplitMaxN) {
     hipLaunchKernelGGL(k_omg_res_split, dim3(blocks_for(8 * (int64_t)D * nk * nk)), dim3(kThreads), 0, st,
                        nk, op, f, z, r);
-  else if (nk <= kOmgBrick1MaxN)
-    hipLaunchKernelGGL(k_omg_res, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
-                       dim3(kBrickThreads), 0, st, nk, op, f, z, r);
-  else
-    hipLaunchKernelGGL(k_omg_res4, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
-                       dim3(kBrick4Threads), 0, st, nk, op, f, z, r);
+  } else {
+    if (nk % kBrick) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_omg_res_m, dim3(bricks(nk)), dim3(kMfmaThreads), 0, st, nk, opm, f, z, r);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_omg_ras(int nk, const double* ras, const double* r, double* z, bool zero,
-                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (nk <= kOmgSplitMaxN)
+hipError_t launch_omg_ras(int nk, const double* ras, const double* rasm, const double* r, double* z,
+                          bool zero, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (nk <= kOmgSplitMaxN) {
     hipExtLaunchKernelGGL(k_omg_ras_split, dim3(blocks_for(16 * (int64_t)D * nk * nk)), dim3(kThreads), 0,
                           st, ev0, ev1, 0, nk, ras, r, z, int(zero));
-  else if (nk <= kOmgBrick1MaxN)
-    hipExtLaunchKernelGGL(k_omg_ras, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
-                          dim3(kBrickThreads), 0, st, ev0, ev1, 0, nk, ras, r, z, int(zero));
-  else
-    hipExtLaunchKernelGGL(k_omg_ras4, dim3(unsigned(((nk + kBrick - 1) / kBrick) * ((nk + kBrick - 1) / kBrick))),
-                          dim3(kBrick4Threads), 0, st, ev0, ev1, 0, nk, ras, r, z, int(zero));
+  } else {
+    if (nk % kBrick) return hipErrorInvalidValue;
+    hipExtLaunchKernelGGL(k_omg_ras_m, dim3(bricks(nk)), dim3(kMfmaThreads), 0, st, ev0, ev1, 0, nk, rasm,
+                          r, z, int(zero));
+  }
   return hipGetLastError();
 }
 

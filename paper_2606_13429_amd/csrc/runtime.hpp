@@ -158,6 +158,7 @@ struct OuterMg {
   int J = 0, m = 2;
   std::vector<int> n;
   std::vector<double*> op, ras, f, z, r;
+  std::vector<double*> opm, rasm;   // the tables in MFMA operand order
   double* cinv = nullptr;
   double* zp = nullptr;            // B r of the current outer iteration (16 n^2)
   hipGraphExec_t graph = nullptr;

@@ -4,12 +4,12 @@ A* as B in the flexible outer iteration) against the oracle
 
 Level operators: every DCG_OP_OMG_* operator element by element against the
 oracle's hierarchy of A* (layout converted element-major <-> component-major),
-at n = 16 (two levels) and n = 64 (four levels), where every level runs the
-small-level (split) kernels.  Bar: max abs difference <= 1e-12 x max |oracle|
-for the single operators, 1e-11 for the W-cycle and B (FP64, different
-summation order).  The brick kernels of the levels above 64 squares per side
-(1024-thread bricks up to 256, the four-rows-per-wavefront bricks above) on
-sampled squares of the levels 128 (n = 128) and 512, 256, 128 (n = 512),
+at n = 16 (two levels, the small-level split kernels) and n = 64 (four
+levels; the finest runs the MFMA brick kernels, interior and boundary
+bricks).  Bar: max abs difference <= 1e-12 x max |oracle| for the single
+operators, 1e-11 for the W-cycle and B (FP64, different summation order).
+The MFMA brick kernels on sampled squares of the levels 128 (n = 128) and
+512, 256, 128 (n = 512),
 against the oracle's rows evaluated square by square on a 16 x 16 window
 (tests/window2d.py): A*_k z 1e-12, the RAS step from zero and from a start
 1e-11.  Solves: the preconditioned flexible iteration against the oracle's at

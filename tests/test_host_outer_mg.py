@@ -83,3 +83,34 @@ def test_tables_match_the_oracle_hierarchy(n, dt, nu):
 def test_bad_arguments_are_rejected(n, level, which):
     with pytest.raises(lib.DCGError):
         lib.dcg_host_outer_mg(n, 10.0, 1e-3, 1.0, level, which)
+
+
+def _from_operand_order(tm):
+    """The class matrices as the MFMA kernels read them: at step s lane l
+    supplies row l % 16, column 4 s + l / 16."""
+    ncls, steps, _ = tm.shape
+    out = np.empty((ncls, 16, 4 * steps))
+    for s in range(steps):
+        for l in range(64):
+            out[:, l % 16, 4 * s + l // 16] = tm[:, s, l]
+    return out
+
+
+@pytest.mark.parametrize("n,dt", [(16, 1e-2), (32, 1e-4)])
+def test_operand_order_tables_hold_the_same_matrices(n, dt):
+    pen, nu = 10.0, 1.0
+    J = {16: 2, 32: 3}[n]
+    rng = np.random.default_rng(n)
+    for k in range(1, J + 1):
+        nk = n >> (J - k)
+        op = lib.dcg_host_outer_mg(n, pen, dt, nu, k, 0)
+        opm = _from_operand_order(lib.dcg_host_outer_mg(n, pen, dt, nu, k, 3))
+        assert np.array_equal(opm, op.transpose(0, 2, 1, 3).reshape(9, 16, 80))
+        # the same level product through the reordered table
+        op_back = opm.reshape(9, 16, 5, 16).transpose(0, 2, 1, 3)
+        z = rng.standard_normal(16 * nk * nk)
+        assert np.array_equal(_dense_from_op(nk, op_back) @ z, _dense_from_op(nk, op) @ z)
+        if k >= 2:
+            ras = lib.dcg_host_outer_mg(n, pen, dt, nu, k, 1)
+            rasm = _from_operand_order(lib.dcg_host_outer_mg(n, pen, dt, nu, k, 4))
+            assert np.array_equal(rasm, ras)
