@@ -178,8 +178,8 @@ TRAFFIC = {"source_digest": "a1247be0d3a54e72", "n": 512,
 
 # The same counters for the 3D A* product k_astar3 at n = 32 (exact inner solve;
 # profiles/solve3d_n32_fp64.md), valid while dcg3d_kernels.hip is unchanged.
-TRAFFIC3 = {"source_digest": "ca3ce7c62147d607", "n": 32,
-            "fetch_kib": 525986.3, "fetch_scale": 2.0, "write_kib": 18456.7, "write_scale": 1.0}
+TRAFFIC3 = {"source_digest": "261bf7a788f3d427", "n": 32,
+            "fetch_kib": 540280.0, "fetch_scale": 2.0, "write_kib": 18433.3, "write_scale": 1.0}
 
 
 def source_digest(*names):

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kAThreads) void k_astar3(int n, const double* __res
     const double* xv = xs[el][s];
 #pragma unroll 8
     for (int col = 0; col < 24; ++col) {
-      const double cv = c[col * 24];
+      const double cv = __builtin_nontemporal_load(c + col * 24);   // streamed once per launch
       acc[0] += cv * xv[col];
       acc[1] += cv * xv[24 + col];
       acc[2] += cv * xv[48 + col];
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kAThreads) void k_adivz3(int n, const double* __res
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int b = 0; b < kNb; ++b) acc[k] += c[(8 * k + b) * 24] * ys[el][s][b];
+      for (int b = 0; b < kNb; ++b) acc[k] += __builtin_nontemporal_load(c + (8 * k + b) * 24) * ys[el][s][b];
   }
   const int j = r >> 3, a = r & 7;
 #pragma unroll
