@@ -172,7 +172,7 @@ def err_vs_oracle(dcg):
 # each scaled by the reading of a plain 1 GiB copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE
 # 1 GiB).  Valid only for the kernel source it was taken on: the digest of the RAS kernel
 # sources must match, else the bench reports traffic as null.
-TRAFFIC = {"source_digest": "a1247be0d3a54e72", "n": 512,
+TRAFFIC = {"source_digest": "3b55b51a6e6af9d0", "n": 512,
            "fetch_kib": 9428.6, "fetch_scale": 2.0, "write_kib": 14645.6, "write_scale": 1.0}
 
 

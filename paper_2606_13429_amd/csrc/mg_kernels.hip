@@ -131,7 +131,6 @@ template <typename T, int WPT>
 __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs<T> a) {
   constexpr int TPB = 4 / WPT;          // tiles per workgroup
   constexpr int G = 64 * WPT;           // threads per tile
-  constexpr int ROWS = 128 / WPT;       // factor rows per wavefront
   constexpr int RPT = (128 + G - 1) / G;  // residual rows per thread
   constexpr int NBW = 36 / WPT;         // packed blocks per wavefront
   constexpr int NP = NBW < 8 ? NBW : 8; // blocks prefetched before the residual
