@@ -79,7 +79,7 @@ def test_tables_match_the_oracle_hierarchy(n, dt, nu):
     assert abs(inv - ref).max() <= 1e-9 * abs(ref).max()
 
 
-@pytest.mark.parametrize("n,level,which", [(24, 1, 0), (128, 1, 0), (16, 1, 1), (16, 2, 2), (16, 3, 0)])
+@pytest.mark.parametrize("n,level,which", [(24, 1, 0), (128, 1, 0), (16, 1, 1), (16, 2, 2), (16, 3, 0), (16, 1, 4)])
 def test_bad_arguments_are_rejected(n, level, which):
     with pytest.raises(lib.DCGError):
         lib.dcg_host_outer_mg(n, 10.0, 1e-3, 1.0, level, which)
