@@ -868,7 +868,7 @@ def main():
                     help="outer iterations of the 3D solver against dt at n = 8, 16, 32")
     ap.add_argument("--outer-mg-sweep", action="store_true",
                     help="DCG, FCG(8) and FCG(8) with the outer multigrid preconditioner against n")
-    ap.add_argument("--omg-m", type=int, default=2, help="outer multigrid: smoothing steps")
+    ap.add_argument("--omg-m", type=int, default=4, help="outer multigrid: smoothing steps")
     ap.add_argument("--omg-only", action="store_true",
                     help="outer multigrid sweep: the preconditioned solves only")
     ap.add_argument("--omg-profile", action="store_true",
@@ -1104,7 +1104,7 @@ def main():
         # method): FCG(8) with B = one W-cycle on A*, the same right-hand side
         log("outer multigrid preconditioner: setup + one solve")
         t0 = time.time()
-        so = dcg.Solver(n, dt, prec="mixed", outer="fcg", m_max=8, outer_mg=2,
+        so = dcg.Solver(n, dt, prec="mixed", outer="fcg", m_max=8, outer_mg=args.omg_m,
                         max_outer=args.max_outer, levels=args.levels)
         to_setup = time.time() - t0
         so.solve(bs[0], x, tol)                       # warm-up (graph capture)
@@ -1114,7 +1114,7 @@ def main():
         torch.cuda.synchronize()
         to = time.time() - t0
         result["outer_mg_preconditioner_seed0"] = {
-            "method": "FCG(8), directions from B r_i, B = one W-cycle on A* (m = 2), mixed form",
+            "method": "FCG(8), directions from B r_i, B = one W-cycle on A* (m = %d), mixed form" % args.omg_m,
             "solves_per_s": round(1.0 / to, 4), "outer_iters": sto.outer_iters,
             "total_wcycles": sto.total_wcycles, "rel_res_true": sto.rel_res_true,
             "setup_s": round(to_setup, 1),
