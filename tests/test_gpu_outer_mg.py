@@ -131,6 +131,33 @@ def test_preconditioned_solve_matches_oracle(n, dt):
             assert np.linalg.norm(xg - res.x) <= 1e-7 * np.linalg.norm(res.x)
 
 
+def test_warm_started_preconditioned_solve_matches_oracle():
+    # the time-stepping use: x0 given (here a rough guess), FCG(8) with B,
+    # against the oracle's dcg(x0=...) with the same B
+    n, dt, tol, m = 32, 1e-2, 1e-8, 2
+    print("outer mg warm start n=%d dt=%g" % (n, dt), flush=True)
+    As = d.operator(n, dt)
+    V = d.deflation_basis(n)
+    E = (V.T @ As @ V).tocsr()
+    f = elem_to_comp(rhs(n, 1), n)
+    x0 = 0.1 * elem_to_comp(rhs(n, 2), n)
+    inner = kr.mg_inner(mg.Hierarchy(E, n))
+    B = pc.preconditioner(pc.Hierarchy(As, n), m)
+    res = kr.dcg(As, V, f, inner, tol=tol, outer='fcg', m_max=8, precond=B, x0=x0)
+    s = _solver(n, dt, m=m, x0_given=True)
+    b = _dev(rhs(n, 1))
+    x = _dev(comp_to_elem(x0, n))
+    status, st = s.solve(b, x, tol)
+    s.close()
+    print("  Out %d (oracle %d) Tot %d (oracle %d)" % (st.outer_iters, res.iterations,
+                                                      st.total_wcycles, res.total_cycles), flush=True)
+    assert status == lib.DCG_OK and st.rel_res_true <= 10 * tol
+    assert abs(st.outer_iters - res.iterations) <= 2
+    assert abs(st.total_wcycles - res.total_cycles) <= max(2, 0.02 * res.total_cycles)
+    xg = elem_to_comp(_host(x), n)
+    assert np.linalg.norm(xg - res.x) <= 1e-7 * np.linalg.norm(res.x)
+
+
 @pytest.mark.parametrize("n", [128, 512])
 def test_full_size_level_steps_on_sampled_squares(n):
     dt = 1e-4
