@@ -711,12 +711,13 @@ def outer_mg_sweep(args):
     outer iterations, W-cycles, wall time and the true residual."""
     import torch
     import paper_2606_13429_amd as dcg
+    from paper_2606_13429_amd import _binding as lib
     from dcg_workloads import rhs
     torch.cuda.set_device(0)
     rows = []
     cases = [(n, 1e-4) for n in (64, 128, 256, 512)] + [(n, 1e-2) for n in (64, 128, 256)]
     methods = (("dcg", dict(outer="cg")), ("fcg8", dict(outer="fcg", m_max=8)),
-               ("fcg8+omg", dict(outer="fcg", m_max=8, outer_mg=args.omg_m)))
+               ("fcg8+omg", dict(outer="fcg", m_max=8, outer_mg=args.omg_m, c_A=args.omg_c_A)))
     if args.omg_profile:   # one capped preconditioned solve at the headline size (profiling runs)
         cases, methods = [(args.n, args.dt)], methods[2:]
     elif args.omg_only:    # the preconditioned column only
@@ -728,12 +729,18 @@ def outer_mg_sweep(args):
             s = dcg.Solver(n, dt, prec="mixed",
                            max_outer=args.max_outer if args.omg_profile else args.sweep_max_outer,
                            levels=levels_option(n, args.levels), **kw)
-            s.solve(b, x, args.tol)                       # graph capture, caches
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            status, st = s.solve(b, x, args.tol)
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t0
+            try:
+                s.solve(b, x, args.tol)                       # graph capture, caches
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                status, st = s.solve(b, x, args.tol)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+            except lib.DCGError as e:   # e.g. a breakdown of the outer iteration
+                s.close()
+                rows.append({"n": n, "dt": dt, "method": name, "status": e.status, "error": str(e)})
+                log("omg sweep n=%d dt=%g %s: %s" % (n, dt, name, e))
+                continue
             s.close()
             rows.append({"n": n, "dt": dt, "method": name, "status": status, "outer": st.outer_iters,
                          "tot": st.total_wcycles, "solve_s": round(t, 3), "rel_res_true": st.rel_res_true})
@@ -741,6 +748,7 @@ def outer_mg_sweep(args):
                 % (n, dt, name, status, st.outer_iters, st.total_wcycles, t, st.rel_res_true))
     print(json.dumps({"metric": "outer iterations and solve time against n: DCG, FCG(8), FCG(8) with "
                                 "the outer multigrid preconditioner", "m": args.omg_m, "tol": args.tol,
+                      "omg_c_A": args.omg_c_A,
                       "rows": rows}), flush=True)
 
 
@@ -877,6 +885,8 @@ def main():
     ap.add_argument("--outer-mg-sweep", action="store_true",
                     help="DCG, FCG(8) and FCG(8) with the outer multigrid preconditioner against n")
     ap.add_argument("--omg-m", type=int, default=4, help="outer multigrid: smoothing steps")
+    ap.add_argument("--omg-c-A", dest="omg_c_A", type=float, default=0.0,
+                    help="outer multigrid sweep: the adaptive inner tolerance for the preconditioned solves")
     ap.add_argument("--omg-only", action="store_true",
                     help="outer multigrid sweep: the preconditioned solves only")
     ap.add_argument("--omg-profile", action="store_true",
