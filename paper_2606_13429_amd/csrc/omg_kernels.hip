@@ -8,9 +8,9 @@
 // thread's chain of loads.  Larger levels stage the input of an 8 x 8 brick
 // in LDS and run the step as FP64 MFMA products of the class tables with the
 // brick's gathered inputs (measured against vector-FMA bricks with the table
-// rows read per lane or through scalar loads: 2-5x faster above 64 squares
-// per side, slower below, where a boundary brick's several classes cost one
-// trip each).
+// rows read per lane or through scalar loads: 2-5x faster from 128 squares
+// per side up, 1.3x at 64; slower than the split kernels below 64, where
+// every brick is a boundary brick whose several classes cost one trip each).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
