@@ -1,9 +1,11 @@
 """BDF2 time stepping (warm-started deflated CG with resident operators)
 against the oracle's BDF2 recursion on the same seeded forcing."""
+import os
+
 import numpy as np
 import pytest
 
-from dcg_workloads import forcing_load, fourier_modes
+from dcg_workloads import TIMESTEP, forcing_load, fourier_modes
 from layout import comp_to_elem, elem_to_comp
 from oracle import discretisation as d
 from oracle import krylov as kr
@@ -71,3 +73,49 @@ def test_bdf2_rhs_sampled_at_full_size():
         ref = Me @ u + c * Fh[sl]
         assert np.allclose(fh[sl], ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
         assert np.array_equal(x0h[sl], 2.0 * s1h[sl] - s2h[sl])
+
+
+GOLDEN_BDF2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "bdf2_n32_dt1e-5_100steps.txt")
+
+
+def _bdf2_golden():
+    rows, samples, final = [], [], None
+    with open(GOLDEN_BDF2) as fh:
+        for line in fh:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            if t[0] == "step":
+                rows.append((int(t[2]), int(t[3]), float(t[4])))
+            elif t[0] == "final_norm":
+                final = float(t[1])
+            elif t[0] == "x":
+                samples.append((int(t[1]), float(t[2])))
+    return rows, final, samples
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_BDF2), reason="oracle golden file not written")
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bdf2_100_steps_match_stored_oracle(prec):
+    # the workload's 100 steps (dt = 1e-5, its forcing) on a 32 x 32 grid
+    # against the oracle's run (tests/golden/make_bdf2_golden.py): every
+    # step's outer count within +-2 and its state norm, and the final state
+    # at 256 sampled entries.  Each solve stops at a relative residual of
+    # 1e-8 and the states of both runs carry that error from step to step
+    # (BDF2 is stable, so it does not grow); the bars allow 2e-8 of ||s||.
+    rows, final, samples = _bdf2_golden()
+    n, dt = 32, 1e-5
+    print("bdf2 100 steps n=%d %s" % (n, prec), flush=True)
+    F = torch.from_numpy(forcing_load(n, fourier_modes(TIMESTEP["seed"], TIMESTEP["modes"]))).cuda()
+    stepper = BDF2(n, dt, prec=prec, tol=1e-8)
+    worst = 0.0
+    for k, (outer, _, nrm) in enumerate(rows):
+        st = stepper.step(F)
+        assert abs(st.outer_iters - outer) <= 2, (k + 1, st.outer_iters, outer)
+        got = torch.linalg.norm(stepper.state).item()
+        worst = max(worst, abs(got - nrm) / nrm)
+    x = stepper.state.cpu().numpy()
+    err = max(abs(x[i] - v) for i, v in samples) / final
+    print("  worst step norm difference %.2e, final sampled difference %.2e" % (worst, err), flush=True)
+    assert worst <= 2e-8 and err <= 2e-8
