@@ -55,7 +55,7 @@ def _ras_apply(n, ras, r):
     return out.ravel()
 
 
-@pytest.mark.parametrize("n,dt,nu", [(16, 1e-2, 1.0), (32, 1e-4, 0.7)])
+@pytest.mark.parametrize("n,dt,nu", [(16, 1e-2, 1.0), (32, 1e-4, 0.7), (64, 1e-3, 1.0)])
 def test_tables_match_the_oracle_hierarchy(n, dt, nu):
     pen = 10.0
     As = d.operator(n, dt, nu=nu, penalty=pen)
