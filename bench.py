@@ -579,7 +579,8 @@ def three_d(args):
     torch.cuda.set_device(0)
     t0 = time.time()
     s = dcg.Solver3D(n, dt, nu=THREE_D["nu"], penalty=THREE_D["penalty"], inner=args.inner3,
-                     c_A=args.cA3, max_outer=args.max_outer3, levels=args.levels3)
+                     c_A=args.cA3, max_outer=args.max_outer3, levels=args.levels3,
+                     restarts=args.restarts3)
     log("3d setup n=%d (%d elements) %.1f s" % (n, n ** 3, time.time() - t0))
     bs = [torch.from_numpy(rhs3d(n, i)).cuda() for i in range(max(args.steps, 1))]
     x = torch.empty_like(bs[0])
@@ -593,7 +594,8 @@ def three_d(args):
     t_all = time.perf_counter()
     for i in range(args.steps):
         status, st = s.solve(bs[i], x, tol)
-        rows.append({"status": status, "outer": st.outer_iters, "inner_steps": st.total_wcycles,
+        rows.append({"status": status, "outer": st.outer_iters, "restarts": st.restarts,
+                     "inner_steps": st.total_wcycles,
                      "inner_per_outer": round(st.inner_per_outer, 2), "rel_res_true": st.rel_res_true,
                      "ms": round(st.t_solve_ms, 1)})
         log("3d step %d: status=%d outer=%d inner steps=%d res=%.2e %.1f ms"
@@ -873,6 +875,8 @@ def main():
     ap.add_argument("--3d-inner", dest="inner3", choices=("exact", "cg", "mg"), default="exact")
     ap.add_argument("--3d-max-outer", dest="max_outer3", type=int, default=50000,
                     help="3D: cap on outer iterations (profiling runs only)")
+    ap.add_argument("--3d-restarts", dest="restarts3", type=int, default=0,
+                    help="3D solver: warm restarts while the true residual misses tol")
     ap.add_argument("--3d-levels", dest="levels3", type=int, default=0,
                     help="3D multigrid: levels kept (0 = all, coarsest 2 cubes per side)")
     ap.add_argument("--3d-cA", dest="cA3", type=float, default=0.0,

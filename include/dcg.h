@@ -487,7 +487,10 @@ typedef enum {
  * and rejects other values with DCG_EINVAL.  The iterative inner solves stop
  * at the relative residual c_F tol (eq. (fixed_tol)), or with c_A > 0 at
  * c_A tol ||b|| / ||r_i|| inside the outer loop and c_A tol for the prologue
- * and epilogue (eq. (tol)); max_inner is their n_max.
+ * and epilogue (eq. (tol)); max_inner is their n_max.  opt->restarts = R > 0
+ * reruns Algorithm 2 from the reconstructed x while its true residual misses
+ * tol, at most R times (pi(b) and f_D of the first pass; the status is then
+ * DCG_OK only if the true residual meets tol), as in dcg_solve.
  *
  * DCG3D_INNER_MG: the Galerkin hierarchy of L = B_11 + B_22 + B_33 (levels
  * k = 1..J by 2 x 2 x 2 agglomeration, trilinear injection P_k, L_{k-1} =

@@ -25,16 +25,19 @@ class Solver3D:
     and post-smoothing steps, ``levels`` levels, 0 = all) or by block-Jacobi
     CG (inner="cg"), the iterative ones to c_F * tol, or with c_A > 0 to the
     adaptive tolerance of eq. (tol); inner="none" switches the deflation off
-    (plain CG on A*).
+    (plain CG on A*).  restarts > 0 reruns Algorithm 2 from the returned x
+    while its true residual misses tol (at most that many times).
 
     >>> s = Solver3D(n=16, dt=1e-3)
     >>> status, stats = s.solve(b, x, tol=1e-8)     # 72 n^3 cuda float64 tensors
     """
 
     def __init__(self, n, dt, nu=1.0, penalty=40.0, c_F=0.01, max_outer=50000,
-                 max_inner=None, inner="exact", c_A=0.0, levels=0, smooth=10, use_graph=True):
+                 max_inner=None, inner="exact", c_A=0.0, levels=0, smooth=10, use_graph=True,
+                 restarts=0):
         _, opt = dcg_defaults()
         opt.prec, opt.outer, opt.c_A, opt.x0_given = DCG_FP64, DCG_OUTER_CG, c_A, 0
+        opt.restarts = restarts
         if max_inner is None:
             max_inner = 100 if inner == "mg" else DCG3D_DEFAULT_MAX_INNER
         opt.c_F, opt.max_outer, opt.max_inner = c_F, max_outer, max_inner

@@ -591,8 +591,10 @@ struct dcg3d_ctx {
     H3(dcg3::launch_fill(nt, 0.0, xh, nullptr));
     copy(r, p, nt);
     double rho = dot(r, r, nt);
-    int it = 0;
+    int it = 0, pass = 0;
     dcg_status status = DCG_OK;
+    double res = 0.0;
+    while (true) {   // one pass of Algorithm 2; further passes are warm restarts from x
     while (it < opt.max_outer && std::sqrt(rho) > tol * fnorm) {
       // q = M_D p = w - dt A_div Z E^{-1} Z^T w, w = A* p
       astar(p, w);
@@ -624,8 +626,26 @@ struct dcg3d_ctx {
     astar(x, w);
     copy(f, tz, nt);
     H3(dcg3::launch_axpy(nt, -1.0, w, tz, nullptr));
-    const double res = std::sqrt(dot(tz, tz, nt));
+    res = std::sqrt(dot(tz, tz, nt));
+    if (status != DCG_OK || res <= tol * fnorm || pass >= opt.restarts) break;
+    // warm restart (not in the paper; the reading of the 2D solver): x_hat = x,
+    // r = f_D - M_D x_hat with pi(f) and f_D of the first pass
+    ++pass;
+    copy(x, xh, nt);
+    astar(pf, w);
+    copy(f, r, nt);
+    H3(dcg3::launch_axpy(nt, -1.0, w, r, nullptr));
+    astar(xh, w);
+    H3(dcg3::launch_zt3(ne, w, s, nullptr));
+    inner(s, yh, rel_in);
+    H3(dcg3::launch_adivz3(n, Cd, dt, w, yh, q, nullptr));
+    H3(dcg3::launch_axpy(nt, -1.0, q, r, nullptr));
+    copy(r, p, nt);
+    rho = dot(r, r, nt);
+    }
+    if (opt.restarts > 0 && status == DCG_OK && res > tol * fnorm) status = DCG_NOT_CONVERGED;
     out.status = status;
+    out.restarts = pass;
     out.outer_iters = it;
     out.total_wcycles = int32_t(inner_total);
     out.inner_solves = int32_t(inner_solves);
@@ -767,6 +787,7 @@ dcg_status dcg3d_setup(int32_t n, double penalty, double dt, double nu, int32_t 
   if (o.outer != DCG_OUTER_CG) return fail3(nullptr, DCG_EINVAL, "the 3D solver runs the CG outer iteration");
   if (!(o.c_A >= 0.0) || !std::isfinite(o.c_A)) return fail3(nullptr, DCG_EINVAL, "c_A must be >= 0");
   if (o.x0_given) return fail3(nullptr, DCG_EINVAL, "the 3D solver starts from x0 = 0");
+  if (o.restarts < 0) return fail3(nullptr, DCG_EINVAL, "restarts must be >= 0");
   if (!(o.c_F > 0.0) || o.max_outer < 0 || o.max_inner < 1)
     return fail3(nullptr, DCG_EINVAL, "c_F must be > 0, max_outer >= 0, max_inner >= 1");
   if (inner == DCG3D_INNER_MG) {

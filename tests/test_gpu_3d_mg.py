@@ -293,3 +293,37 @@ def test_full_size_solve():
     # the exact inner solve takes 266-268 outer iterations on this system
     assert abs(st.outer_iters - 268) <= 10
     assert 20 <= st.total_wcycles / st.inner_solves <= 60
+
+
+def test_warm_restarts_match_oracle():
+    # a loose fixed inner tolerance (c_F tol = 1e-8) leaves the true residual
+    # above tol when the recurrence test stops; one warm restart from the
+    # reconstructed x (the oracle's dcg(restarts=)) brings it under tol
+    n, dt, tol, c = 4, 1e-3, 1e-8, 1.0
+    print("3d mg restarts n=%d dt=%g" % (n, dt), flush=True)
+    As = d3.operator(n, dt, nu=NU, penalty=PEN)
+    V = d3.deflation_basis(n)
+    E = (V.T @ As @ V).tocsr()
+    f = elem_to_comp3(rhs3d(n, 4), n)
+    inner = kr.mg_inner(mg3.Hierarchy(E, n), 10, 10)
+    res = kr.dcg(As, V, f, inner, tol=tol, c_F=c, restarts=2)
+    plain = kr.dcg(As, V, f, inner, tol=tol, c_F=c)
+    b = _dev(rhs3d(n, 4))
+    got = {}
+    for R in (0, 2):
+        s = dcg.Solver3D(n, dt, nu=NU, penalty=PEN, inner="mg", c_F=c, restarts=R)
+        x = torch.empty_like(b)
+        status, st = s.solve(b, x, tol)
+        s.close()
+        got[R] = (status, st, elem_to_comp3(_host(x), n))
+        print("  restarts %d: status %d Out %d restarts %d true %.2e (oracle Out %d restarts %d true %.2e)"
+              % (R, status, st.outer_iters, st.restarts, st.rel_res_true,
+                 (res if R else plain).iterations, (res if R else plain).restarts,
+                 (res if R else plain).rel_res_true), flush=True)
+    status, st, xg = got[2]
+    assert status == lib.DCG_OK and st.rel_res_true <= tol
+    assert st.restarts == res.restarts >= 1
+    assert abs(st.outer_iters - res.iterations) <= 2
+    assert np.linalg.norm(xg - res.x) <= 1e-6 * np.linalg.norm(res.x)
+    # without restarts the same solve stops above tol, as the oracle's does
+    assert plain.rel_res_true > tol and got[0][1].rel_res_true > tol and got[0][1].restarts == 0
